@@ -1,0 +1,405 @@
+/*
+ * oracle.c -- plain sequential FP64 reference of the edge-flux hot path.
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library, and the GPU library never
+ * calls it.
+ *
+ * What it follows (the paper gives the loop semantics, not the numerics):
+ *  - Sec. 3.2: a single-threaded sequential back-end is the reference every
+ *    parallel build must reproduce; here it is a plain loop over edges in
+ *    input order, no plan, no threads, no blocking.
+ *  - Sec. 3.1 (the op_par_loop example): OP_INC through a map is a sequential
+ *    sum over the set elements; an edge loop reads its two nodes through the
+ *    edge->node map and increments both.
+ *  - Sec. 2: time marching with a 5-stage Runge-Kutta scheme.
+ *  - The flux itself is not in the paper.  The workload defines it as
+ *      F_e = 1/2 (f(q_i) + f(q_j)).n_e - 1/2 lambda_e (q_j - q_i),
+ *      lambda_e = |u_avg.n_e| + c_avg |n_e|,
+ *    with +F_e added to res_i and -F_e to res_j (Euler flux of the
+ *    conservative state rho, rho u, rho v, rho w, rho E, rho phi, ideal gas).
+ *
+ * Readings taken where the definition is silent (each one is listed in the
+ * design notes of the repository):
+ *  - u_avg and c_avg are arithmetic means of the nodal velocity and sound speed;
+ *  - the passive scalar is carried as rho*phi with flux rho*phi * (u.n);
+ *  - the explicit update is q = q0 - alpha_k dt res/vol (the residual is the
+ *    net outflow, so the sign must be negative for the scheme to be stable);
+ *  - stage coefficients alpha = (1/4, 1/6, 3/8, 1/2, 1);
+ *  - the residual norm is per variable, sum over nodes of res^2 (compensated);
+ *  - d|x|/dx = +1 at x = +0.
+ *
+ * Arrays are host memory in SoA layout: component c of element k at
+ * a[c * count + k].  Maps are row-major pairs e2n[2e], e2n[2e+1], 0-based.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static const double RK_ALPHA[5] = {1.0 / 4.0, 1.0 / 6.0, 3.0 / 8.0, 1.0 / 2.0, 1.0};
+
+double orc_rk_alpha(int k) { return (k >= 0 && k < 5) ? RK_ALPHA[k] : 0.0; }
+
+/* ---------------------------------------------------------- plain FP64 -- */
+
+typedef struct {
+    double u[3], p, c;
+} prim;
+
+static void node_prim(const double q[6], double gamma, prim *s)
+{
+    double rho = q[0];
+    s->u[0] = q[1] / rho;
+    s->u[1] = q[2] / rho;
+    s->u[2] = q[3] / rho;
+    s->p = (gamma - 1.0) * (q[4] - 0.5 * (q[1] * s->u[0] + q[2] * s->u[1] + q[3] * s->u[2]));
+    s->c = sqrt(gamma * s->p / rho);
+}
+
+/* f(q).n for one node, given its primitives. */
+static void normal_flux(const double q[6], const prim *s, const double n[3], double f[6])
+{
+    double U = s->u[0] * n[0] + s->u[1] * n[1] + s->u[2] * n[2];
+    f[0] = q[0] * U;
+    f[1] = q[1] * U + s->p * n[0];
+    f[2] = q[2] * U + s->p * n[1];
+    f[3] = q[3] * U + s->p * n[2];
+    f[4] = (q[4] + s->p) * U;
+    f[5] = q[5] * U;
+}
+
+static void edge_flux(const double qi[6], const prim *si, const double qj[6], const prim *sj,
+                      const double n[3], double F[6])
+{
+    double fi[6], fj[6];
+    normal_flux(qi, si, n, fi);
+    normal_flux(qj, sj, n, fj);
+    double Ui = si->u[0] * n[0] + si->u[1] * n[1] + si->u[2] * n[2];
+    double Uj = sj->u[0] * n[0] + sj->u[1] * n[1] + sj->u[2] * n[2];
+    double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    double lam = fabs(0.5 * (Ui + Uj)) + 0.5 * (si->c + sj->c) * nn;
+    for (int v = 0; v < 6; ++v) F[v] = 0.5 * (fi[v] + fj[v]) - 0.5 * lam * (qj[v] - qi[v]);
+}
+
+void orc_flux(const double qi[6], const double qj[6], const double n[3], double gamma,
+              double F[6])
+{
+    prim si, sj;
+    node_prim(qi, gamma, &si);
+    node_prim(qj, gamma, &sj);
+    edge_flux(qi, &si, qj, &sj, n, F);
+}
+
+static void gather6(const double *q, int64_t N, int64_t i, double out[6])
+{
+    for (int v = 0; v < 6; ++v) out[v] = q[(int64_t)v * N + i];
+}
+
+static int check_map(int64_t N, int64_t E, const int32_t *e2n)
+{
+    for (int64_t e = 0; e < 2 * E; ++e)
+        if (e2n[e] < 0 || e2n[e] >= N) return ORC_ERANGE;
+    return 0;
+}
+
+int orc_residual(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+                 double gamma, double *res, double *S)
+{
+    if (N <= 0 || E < 0) return ORC_EINVAL;
+    if (check_map(N, E, e2n)) return ORC_ERANGE;
+    prim *P = malloc((size_t)N * sizeof(prim));
+    if (!P) return ORC_ENOMEM;
+    for (int64_t i = 0; i < N; ++i) {
+        double qi[6];
+        gather6(q, N, i, qi);
+        node_prim(qi, gamma, &P[i]);
+    }
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t i = e2n[2 * e], j = e2n[2 * e + 1];
+        double qi[6], qj[6], n[3], F[6];
+        gather6(q, N, i, qi);
+        gather6(q, N, j, qj);
+        for (int d = 0; d < 3; ++d) n[d] = w[(int64_t)d * E + e];
+        edge_flux(qi, &P[i], qj, &P[j], n, F);
+        for (int v = 0; v < 6; ++v) {
+            res[(int64_t)v * N + i] += F[v];
+            res[(int64_t)v * N + j] -= F[v];
+            if (S) {
+                S[(int64_t)v * N + i] += fabs(F[v]);
+                S[(int64_t)v * N + j] += fabs(F[v]);
+            }
+        }
+    }
+    free(P);
+    return 0;
+}
+
+/* Neumaier's compensated summation. */
+typedef struct {
+    double s, c;
+} ksum;
+
+static void ksum_add(ksum *k, double x)
+{
+    double t = k->s + x;
+    if (fabs(k->s) >= fabs(x))
+        k->c += (k->s - t) + x;
+    else
+        k->c += (x - t) + k->s;
+    k->s = t;
+}
+
+int orc_rk_stage(int64_t N, const double *q0, double *res, const double *vol, double alpha_dt,
+                 double *q, double ss[6])
+{
+    if (N <= 0) return ORC_EINVAL;
+    for (int v = 0; v < 6; ++v) {
+        ksum k = {0.0, 0.0};
+        for (int64_t i = 0; i < N; ++i) {
+            double r = res[(int64_t)v * N + i];
+            ksum_add(&k, r * r);
+            q[(int64_t)v * N + i] = q0[(int64_t)v * N + i] - alpha_dt * r / vol[i];
+            res[(int64_t)v * N + i] = 0.0;
+        }
+        ss[v] = k.s + k.c;
+    }
+    return 0;
+}
+
+int orc_rk_iteration(int64_t N, int64_t E, const int32_t *e2n, double *q0, const double *w,
+                     const double *vol, double gamma, double dt, double ss[30])
+{
+    double *res = calloc((size_t)N * 6, sizeof(double));
+    double *q = malloc((size_t)N * 6 * sizeof(double));
+    if (!res || !q) {
+        free(res);
+        free(q);
+        return ORC_ENOMEM;
+    }
+    memcpy(q, q0, (size_t)N * 6 * sizeof(double));
+    int rc = 0;
+    for (int k = 0; k < 5 && !rc; ++k) {
+        rc = orc_residual(N, E, e2n, q, w, gamma, res, NULL);
+        if (!rc) rc = orc_rk_stage(N, q0, res, vol, RK_ALPHA[k] * dt, q, ss + 6 * k);
+    }
+    if (!rc) memcpy(q0, q, (size_t)N * 6 * sizeof(double));
+    free(res);
+    free(q);
+    return rc;
+}
+
+int orc_spectral_radius(int64_t N, int64_t E, const int32_t *e2n, const double *q,
+                        const double *w, double gamma, double *lam_sum)
+{
+    if (N <= 0 || E < 0) return ORC_EINVAL;
+    if (check_map(N, E, e2n)) return ORC_ERANGE;
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t i = e2n[2 * e], j = e2n[2 * e + 1];
+        double qi[6], qj[6], n[3];
+        prim si, sj;
+        gather6(q, N, i, qi);
+        gather6(q, N, j, qj);
+        node_prim(qi, gamma, &si);
+        node_prim(qj, gamma, &sj);
+        for (int d = 0; d < 3; ++d) n[d] = w[(int64_t)d * E + e];
+        double Ui = si.u[0] * n[0] + si.u[1] * n[1] + si.u[2] * n[2];
+        double Uj = sj.u[0] * n[0] + sj.u[1] * n[1] + sj.u[2] * n[2];
+        double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        double lam = fabs(0.5 * (Ui + Uj)) + 0.5 * (si.c + sj.c) * nn;
+        lam_sum[i] += lam;
+        lam_sum[j] += lam;
+    }
+    return 0;
+}
+
+double orc_dt(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+              const double *vol, double gamma, double cfl)
+{
+    double *ls = calloc((size_t)N, sizeof(double));
+    if (!ls) return -1.0;
+    if (orc_spectral_radius(N, E, e2n, q, w, gamma, ls)) {
+        free(ls);
+        return -1.0;
+    }
+    double dt = INFINITY;
+    for (int64_t i = 0; i < N; ++i) {
+        double t = vol[i] / ls[i];
+        if (t < dt) dt = t;
+    }
+    free(ls);
+    return cfl * dt;
+}
+
+/* ------------------------------------------------------- dual numbers -- */
+
+/* Forward-mode dual number with up to 15 tangent directions: value and
+ * derivatives propagated by the chain rule, one elementary operation at a
+ * time.  Only the first `nt` tangents are used. */
+#define NT_MAX 15
+typedef struct {
+    double v, d[NT_MAX];
+} dn;
+
+static int nt;
+
+static dn dconst(double x)
+{
+    dn r;
+    r.v = x;
+    for (int k = 0; k < NT_MAX; ++k) r.d[k] = 0.0;
+    return r;
+}
+static dn dadd(dn a, dn b)
+{
+    dn r;
+    r.v = a.v + b.v;
+    for (int k = 0; k < nt; ++k) r.d[k] = a.d[k] + b.d[k];
+    return r;
+}
+static dn dsub(dn a, dn b)
+{
+    dn r;
+    r.v = a.v - b.v;
+    for (int k = 0; k < nt; ++k) r.d[k] = a.d[k] - b.d[k];
+    return r;
+}
+static dn dmul(dn a, dn b)
+{
+    dn r;
+    r.v = a.v * b.v;
+    for (int k = 0; k < nt; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return r;
+}
+static dn dscale(double s, dn a)
+{
+    dn r;
+    r.v = s * a.v;
+    for (int k = 0; k < nt; ++k) r.d[k] = s * a.d[k];
+    return r;
+}
+static dn ddiv(dn a, dn b)
+{
+    dn r;
+    r.v = a.v / b.v;
+    for (int k = 0; k < nt; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+    return r;
+}
+static dn dsqrt(dn a)
+{
+    dn r;
+    r.v = sqrt(a.v);
+    for (int k = 0; k < nt; ++k) r.d[k] = a.d[k] / (2.0 * r.v);
+    return r;
+}
+static dn dabs(dn a)
+{
+    double s = signbit(a.v) ? -1.0 : 1.0;
+    return dscale(s, a);
+}
+
+/* Flux of one edge on dual numbers, the same formula as edge_flux(). */
+static void dual_flux(const dn qi[6], const dn qj[6], const dn n[3], double gamma, dn F[6])
+{
+    const dn *qs[2] = {qi, qj};
+    dn u[2][3], p[2], c[2], U[2], f[2][6];
+    for (int s = 0; s < 2; ++s) {
+        const dn *q = qs[s];
+        for (int d = 0; d < 3; ++d) u[s][d] = ddiv(q[1 + d], q[0]);
+        dn ke = dadd(dadd(dmul(q[1], u[s][0]), dmul(q[2], u[s][1])), dmul(q[3], u[s][2]));
+        p[s] = dscale(gamma - 1.0, dsub(q[4], dscale(0.5, ke)));
+        c[s] = dsqrt(ddiv(dscale(gamma, p[s]), q[0]));
+        U[s] = dadd(dadd(dmul(u[s][0], n[0]), dmul(u[s][1], n[1])), dmul(u[s][2], n[2]));
+        f[s][0] = dmul(q[0], U[s]);
+        for (int d = 0; d < 3; ++d) f[s][1 + d] = dadd(dmul(q[1 + d], U[s]), dmul(p[s], n[d]));
+        f[s][4] = dmul(dadd(q[4], p[s]), U[s]);
+        f[s][5] = dmul(q[5], U[s]);
+    }
+    dn nn = dsqrt(dadd(dadd(dmul(n[0], n[0]), dmul(n[1], n[1])), dmul(n[2], n[2])));
+    dn lam = dadd(dabs(dscale(0.5, dadd(U[0], U[1]))), dmul(dscale(0.5, dadd(c[0], c[1])), nn));
+    for (int v = 0; v < 6; ++v)
+        F[v] = dsub(dscale(0.5, dadd(f[0][v], f[1][v])), dmul(dscale(0.5, lam), dsub(qj[v], qi[v])));
+}
+
+int orc_jvp(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+            double gamma, const double *dq, const double *dw, double *jv)
+{
+    if (N <= 0 || E < 0) return ORC_EINVAL;
+    if (check_map(N, E, e2n)) return ORC_ERANGE;
+    nt = 1;
+    memset(jv, 0, (size_t)N * 6 * sizeof(double));
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t i = e2n[2 * e], j = e2n[2 * e + 1];
+        dn qi[6], qj[6], n[3], F[6];
+        for (int v = 0; v < 6; ++v) {
+            qi[v] = dconst(q[(int64_t)v * N + i]);
+            qi[v].d[0] = dq ? dq[(int64_t)v * N + i] : 0.0;
+            qj[v] = dconst(q[(int64_t)v * N + j]);
+            qj[v].d[0] = dq ? dq[(int64_t)v * N + j] : 0.0;
+        }
+        for (int d = 0; d < 3; ++d) {
+            n[d] = dconst(w[(int64_t)d * E + e]);
+            n[d].d[0] = dw ? dw[(int64_t)d * E + e] : 0.0;
+        }
+        dual_flux(qi, qj, n, gamma, F);
+        for (int v = 0; v < 6; ++v) {
+            jv[(int64_t)v * N + i] += F[v].d[0];
+            jv[(int64_t)v * N + j] -= F[v].d[0];
+        }
+    }
+    return 0;
+}
+
+int orc_edge_jacobian(const double qi[6], const double qj[6], const double n[3], double gamma,
+                      double F[6], double J[6 * 15])
+{
+    nt = 15;
+    dn a[6], b[6], m[3], G[6];
+    for (int v = 0; v < 6; ++v) {
+        a[v] = dconst(qi[v]);
+        a[v].d[v] = 1.0;
+        b[v] = dconst(qj[v]);
+        b[v].d[6 + v] = 1.0;
+    }
+    for (int d = 0; d < 3; ++d) {
+        m[d] = dconst(n[d]);
+        m[d].d[12 + d] = 1.0;
+    }
+    dual_flux(a, b, m, gamma, G);
+    for (int v = 0; v < 6; ++v) {
+        if (F) F[v] = G[v].v;
+        for (int k = 0; k < 15; ++k) J[15 * v + k] = G[v].d[k];
+    }
+    return 0;
+}
+
+int orc_adjoint(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+                double gamma, const double *rbar, double *qbar, double *wbar)
+{
+    if (N <= 0 || E < 0) return ORC_EINVAL;
+    if (check_map(N, E, e2n)) return ORC_ERANGE;
+    memset(qbar, 0, (size_t)N * 6 * sizeof(double));
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t i = e2n[2 * e], j = e2n[2 * e + 1];
+        double qi[6], qj[6], n[3], J[6 * 15], Fb[6];
+        gather6(q, N, i, qi);
+        gather6(q, N, j, qj);
+        for (int d = 0; d < 3; ++d) n[d] = w[(int64_t)d * E + e];
+        orc_edge_jacobian(qi, qj, n, gamma, NULL, J);
+        /* res_i gets +F and res_j gets -F, so dL/dF = rbar_i - rbar_j */
+        for (int v = 0; v < 6; ++v) Fb[v] = rbar[(int64_t)v * N + i] - rbar[(int64_t)v * N + j];
+        for (int k = 0; k < 15; ++k) {
+            double s = 0.0;
+            for (int v = 0; v < 6; ++v) s += J[15 * v + k] * Fb[v];
+            if (k < 6)
+                qbar[(int64_t)k * N + i] += s;
+            else if (k < 12)
+                qbar[(int64_t)(k - 6) * N + j] += s;
+            else
+                wbar[(int64_t)(k - 12) * E + e] = s;
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,61 @@
+/*
+ * oracle.h -- sequential FP64 reference of the edge-flux hot path.
+ *
+ * TEST INFRASTRUCTURE: used only by the test suite, the smoke check and the
+ * CPU baseline of the benchmark.  Host arrays, SoA (component c of element k
+ * at a[c*count + k]), 0-based row-major edge->node pairs.
+ */
+#ifndef ORACLE_H
+#define ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ERANGE = -2, ORC_ENOMEM = -7 };
+
+/* alpha_k of the 5-stage scheme, k = 0..4 */
+double orc_rk_alpha(int k);
+
+/* Flux of one edge from q_i to q_j with weight n (F added to i, subtracted from j). */
+void orc_flux(const double qi[6], const double qj[6], const double n[3], double gamma,
+              double F[6]);
+
+/* res[6N] += sum over edges of +F at the first node and -F at the second.
+ * S[6N] (optional) += |F| at both nodes: the scale of each residual entry. */
+int orc_residual(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+                 double gamma, double *res, double *S);
+
+/* ss[v] = sum_i res[v,i]^2 (compensated); q = q0 - alpha_dt*res/vol; res = 0. */
+int orc_rk_stage(int64_t N, const double *q0, double *res, const double *vol, double alpha_dt,
+                 double *q, double ss[6]);
+
+/* One 5-stage iteration in place on q0; ss[6k + v] is stage k's sum of squares. */
+int orc_rk_iteration(int64_t N, int64_t E, const int32_t *e2n, double *q0, const double *w,
+                     const double *vol, double gamma, double dt, double ss[30]);
+
+/* lam_sum[N] += sum over incident edges of lambda_e. */
+int orc_spectral_radius(int64_t N, int64_t E, const int32_t *e2n, const double *q,
+                        const double *w, double gamma, double *lam_sum);
+
+/* cfl * min_i vol_i / sum_{e at i} lambda_e; negative on error. */
+double orc_dt(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+              const double *vol, double gamma, double cfl);
+
+/* jv[6N] = J (dq, dw): the residual's directional derivative (dual numbers). */
+int orc_jvp(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+            double gamma, const double *dq, const double *dw, double *jv);
+
+/* Exact 6x15 Jacobian of one edge's flux w.r.t. (q_i, q_j, n), row-major. */
+int orc_edge_jacobian(const double qi[6], const double qj[6], const double n[3], double gamma,
+                      double F[6], double J[6 * 15]);
+
+/* qbar[6N] = sum_e J_q^T (rbar_i - rbar_j); wbar[3E] = J_n^T (rbar_i - rbar_j). */
+int orc_adjoint(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+                double gamma, const double *rbar, double *qbar, double *wbar);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,18 @@
+"""Reader for the text fixtures in this folder."""
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def flux_hand_cases():
+    cases = []
+    with open(os.path.join(HERE, "flux_hand_cases.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            name, qi, qj, n, F = [p.strip() for p in line.split("|")]
+            cases.append((name, *(np.array([float(x) for x in s.split()]) for s in (qi, qj, n, F))))
+    return cases
