@@ -1,0 +1,286 @@
+/*
+ * opflux.h -- C ABI of the MI355X edge-flux library (libopflux.so).
+ *
+ * The calls follow the paper's statement of an unstructured-mesh problem
+ * (Sec. 2: sets, data on sets, mappings between sets, operations over sets)
+ * and the OP2 API built on it (Sec. 3.1): declare sets, an arity-2 map from
+ * edges to nodes, data arrays on sets, then run a loop over a set whose
+ * arguments say how each array is reached (directly, or through the map) and
+ * how it is accessed (READ, WRITE, RW, INC).  As in OP2 (Sec. 3.2), the library
+ * owns the maps, may renumber the sets, and decides how a loop is executed;
+ * for an indirect loop it builds an execution plan once per map (Sec. 4.1):
+ * mini-partitions of consecutive edges, a colouring of the mini-partitions so
+ * that partitions of one colour share no node, and a colouring of the edges
+ * inside each partition so that edges of one colour share no node.
+ *
+ * Conventions
+ *  - Every call returns an int status: OPF_OK (0) or a negative opf_status.
+ *    Nothing throws or aborts across the ABI; opf_last_error() gives a message.
+ *  - Sizes are int64_t, indices int32_t.  Handles (opf_set, opf_map, opf_dat)
+ *    are small non-negative integers valid until opf_finalize().
+ *  - A context is not thread-safe.  Loops are asynchronous on the HIP stream
+ *    passed as `stream` (a hipStream_t; NULL = the null stream); the library
+ *    never synchronises unless asked (opf_sync, opf_plan).
+ *  - Data arrays ("dats") are borrowed device memory in SoA layout: component c
+ *    of element k is at ptr[c * ld + k], ld >= set size.  They must be in the
+ *    library's internal numbering once a plan has renumbered their set (use
+ *    opf_get_perm to move data in and out).  The caller keeps them alive.
+ */
+#ifndef OPFLUX_H
+#define OPFLUX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct opf_ctx opf_ctx;
+typedef int32_t opf_set;
+typedef int32_t opf_map;
+typedef int32_t opf_dat;
+
+/* map value of a direct argument (OP2's OP_ID) */
+#define OPF_ID (-1)
+
+typedef enum {
+    OPF_OK = 0,
+    OPF_EINVAL = -1,     /* bad argument value or handle                         */
+    OPF_ERANGE = -2,     /* map entry outside the target set                     */
+    OPF_ESIZE = -3,      /* set size, dimension or leading dimension mismatch    */
+    OPF_ETYPE = -4,      /* data type mismatch                                   */
+    OPF_EACCESS = -5,    /* access mode does not match the kernel's signature    */
+    OPF_ESTATE = -6,     /* missing or stale plan, wrong call order              */
+    OPF_ENOMEM = -7,     /* host or device allocation failed                     */
+    OPF_EDEVICE = -8,    /* HIP error, or no device bound to the context         */
+    OPF_ENONFINITE = -9, /* a reduction result is not finite                     */
+    OPF_EPLAN = -10      /* plan verification found a violation                  */
+} opf_status;
+
+typedef enum { OPF_F64 = 0, OPF_F32 = 1 } opf_dtype;
+
+/* access modes of an argument (Sec. 3.1: OP_READ, OP_INC; WRITE and RW for
+ * direct arguments and globals; MIN for a global minimum) */
+typedef enum { OPF_READ = 0, OPF_WRITE = 1, OPF_RW = 2, OPF_INC = 3, OPF_MIN = 4 } opf_access;
+
+/* The fixed kernel registry (there is no code generation; each kernel has a
+ * fixed argument signature, listed at opf_par_loop). */
+typedef enum {
+    OPF_K_EDGE_FLUX = 0,     /* edge flux, OP_INC of +F / -F into both nodes      */
+    OPF_K_EDGE_FLUX_ADJ = 1, /* reverse (adjoint) of the edge flux                */
+    OPF_K_RK_STAGE = 2,      /* direct explicit stage update + sum-of-squares     */
+    OPF_K_EDGE_SPECRAD = 3,  /* OP_INC of the edge spectral radius into nodes     */
+    OPF_K_DT_MIN = 4         /* direct: global min over nodes of cfl*vol/lambda   */
+} opf_kernel;
+
+/* How an indirect (edge) loop resolves its increments. */
+typedef enum {
+    OPF_V_COLOURED = 0, /* mini-partitions staged in LDS, edge colours serialised
+                           inside a partition, one launch per partition colour   */
+    OPF_V_ATOMIC = 1    /* one thread per edge, FP64 atomic adds to HBM          */
+} opf_variant;
+
+typedef enum { OPF_RENUM_NONE = 0, OPF_RENUM_RCM = 1, OPF_RENUM_MORTON = 2 } opf_renumber;
+
+/* ------------------------------------------------------------ context -- */
+
+/* Creates a context bound to HIP device `hip_device`, or a host-only context
+ * when hip_device == -1 (declarations, planning and verification work; loops
+ * return OPF_EDEVICE).  No device memory is allocated here.
+ * Errors: OPF_EINVAL (out == NULL), OPF_EDEVICE (no such device). */
+int opf_init(opf_ctx **out, int hip_device);
+
+/* Frees host memory and every device buffer the library allocated (plans,
+ * scratch).  Never frees borrowed dats.  Synchronises the device first.
+ * Accepts NULL. */
+int opf_finalize(opf_ctx *ctx);
+
+/* Message for the last non-zero status returned on ctx ("" if none). The
+ * pointer stays valid until the next call on ctx. */
+const char *opf_last_error(const opf_ctx *ctx);
+
+/* Optional device allocator for plan arrays and scratch: alloc(user, bytes)
+ * returns device memory or NULL; free(user, ptr) releases it.  Must be set
+ * before the first opf_plan.  NULL functions restore hipMalloc / hipFree.
+ * Errors: OPF_ESTATE (a plan already exists). */
+int opf_set_allocator(opf_ctx *ctx, void *(*alloc_fn)(void *user, size_t bytes),
+                      void (*free_fn)(void *user, void *ptr), void *user);
+
+/* ------------------------------------------------------- declarations -- */
+
+/* Declares a set of `size` elements, 0 < size < 2^31 (Sec. 3.1, op_decl_set).
+ * `name` may be NULL.  Errors: OPF_EINVAL, OPF_ESIZE. */
+int opf_decl_set(opf_ctx *ctx, int64_t size, const char *name, opf_set *out);
+
+/* Declares a map from set `from` to set `to` of arity `dim` (Sec. 3.1,
+ * op_decl_map; argument order from, to, dim).  `idx` is host memory,
+ * row-major from.size x dim; it is COPIED and the library owns the copy.
+ * index_base is 0 or 1 (the paper's Fortran maps are 1-based).  Declaring a
+ * map again under the same name replaces it and makes its plan stale.
+ * Errors: OPF_EINVAL (bad handle, dim < 1, index_base), OPF_ERANGE (an entry
+ * outside [0, to.size) after subtracting index_base). */
+int opf_decl_map(opf_ctx *ctx, opf_set from, opf_set to, int dim, const int32_t *idx,
+                 int index_base, const char *name, opf_map *out);
+
+typedef struct {
+    int32_t renumber;      /* opf_renumber; RCM is the default choice             */
+    int32_t block_size;    /* edges per mini-partition: 64, 128, ..., 2048         */
+    int32_t colour_sort;   /* 1: order edges inside each partition by colour       */
+    int32_t pad;
+    const double *coords;  /* host, SoA 3 x to.size; required for MORTON          */
+} opf_plan_opts;
+
+typedef struct {
+    int64_t nblocks;            /* mini-partitions                                */
+    int32_t nblock_colours;     /* colours of mini-partitions                     */
+    int32_t max_elem_colours;   /* max edge colours inside one partition          */
+    double mean_elem_colours;   /* mean edge colours per partition                */
+    int64_t sum_unique;         /* sum over partitions of distinct nodes          */
+    int32_t max_unique;         /* max distinct nodes of one partition            */
+    int32_t min_blocks_per_colour;
+    int64_t bandwidth_before;   /* max |i - j| over edges, user numbering         */
+    int64_t bandwidth_after;    /* the same after renumbering                     */
+    double plan_seconds;        /* host time of opf_plan                          */
+    int64_t device_bytes;       /* device memory held by the plan                 */
+} opf_plan_info;
+
+/* Builds the execution plan of an arity-2 map (edges -> nodes) on the host
+ * (Sec. 4: renumbering for locality; Sec. 4.1: mini-partitions, two-level
+ * colouring; Sec. 4.1.2: colour-sorted edges as an option), verifies it
+ * bit-exactly, and uploads it to the device (device contexts only; blocks until
+ * the upload is done).  The plan renumbers both sets: afterwards every dat on
+ * them must be in internal numbering.  A set can be renumbered by one plan only.
+ * `info` may be NULL.
+ * Errors: OPF_EINVAL (dim != 2, self-loop edge, bad options), OPF_ESTATE (a set
+ * already renumbered by another plan), OPF_ENOMEM, OPF_EDEVICE, OPF_EPLAN. */
+int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info *info);
+
+/* Internal label of every user element of set s: new_of_old[user] = internal.
+ * Caller-owned host buffer of s.size entries.  Identity if s was not renumbered.
+ * For the edge set it gives each user edge's position in internal order. */
+int opf_get_perm(const opf_ctx *ctx, opf_set s, int32_t *new_of_old);
+
+/* Read-only view of a plan's host arrays (valid until opf_finalize or the next
+ * opf_plan on the same map).  Internal numbering throughout. */
+typedef struct {
+    int64_t nnodes, nedges, nblocks;
+    int32_t nblock_colours, block_size;
+    const int32_t *e2n;            /* [2E] internal map, internal edge order          */
+    const int64_t *block_offsets;  /* [nblocks+1] edge range of each partition        */
+    const int32_t *block_colour;   /* [nblocks]                                       */
+    const int32_t *colour_blocks;  /* [nblocks] partition ids grouped by colour       */
+    const int64_t *colour_offsets; /* [nblock_colours+1] into colour_blocks           */
+    const uint8_t *elem_colour;    /* [E] edge colour inside its partition            */
+    const int32_t *block_ncolours; /* [nblocks] edge colours of each partition        */
+    const int64_t *unique_offsets; /* [nblocks+1] into unique_nodes                   */
+    const int32_t *unique_nodes;   /* sorted distinct nodes of each partition         */
+    const uint16_t *local_idx;     /* [2E] endpoint positions in the partition's list */
+} opf_plan_view;
+
+int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out);
+
+typedef struct {
+    int32_t ok;        /* 1 when every property holds                         */
+    int32_t property;  /* first violated property 1..7, 0 if none            */
+    int64_t where;     /* element (node, edge or partition) of the violation  */
+    char message[160];
+} opf_plan_report;
+
+/* Host-only, bit-exact verification of a plan: (1) the node relabelling is a
+ * bijection; (2) the edge reordering is a bijection and keeps every edge's
+ * endpoints and orientation; (3) partitions of one colour share no node; (4)
+ * inside a partition, edges of one colour share no node; (5) partitions are
+ * contiguous edge ranges of at most block_size edges, grouped by colour;
+ * (6) local indices resolve to the map's nodes; (7) colour counts fit their
+ * types.  Works without a GPU.  Errors: OPF_EPLAN (report filled),
+ * OPF_ESTATE (no plan). */
+int opf_plan_verify(const opf_ctx *ctx, opf_map map, opf_plan_report *report);
+
+/* Declares a dat on set s borrowing device memory: dim components of type t,
+ * SoA with leading dimension ld >= s.size (Sec. 3.1, op_decl_dat; SoA layout as
+ * in Sec. 4.1.2).  Errors: OPF_EINVAL (NULL ptr on a device context, bad
+ * handle, dim < 1), OPF_ESIZE (ld < size), OPF_ETYPE (unknown type). */
+int opf_decl_dat(opf_ctx *ctx, opf_set s, int dim, int type, void *dev_ptr, int64_t ld,
+                 const char *name, opf_dat *out);
+
+/* ------------------------------------------------------------- loops -- */
+
+/* One argument of a loop (Sec. 3.1, op_arg_dat(dat, idx, map, dim, type,
+ * access)): idx is the map column (0 or 1) for an indirect argument, or -1
+ * with map == OPF_ID for a direct one. */
+typedef struct {
+    opf_dat dat;
+    int32_t idx;
+    opf_map map;
+    int32_t dim;
+    int32_t type;
+    int32_t access;
+} opf_arg;
+
+/* A global argument: a constant (READ, host or device memory) or a reduction
+ * target (INC or MIN, device memory of dim values that the loop updates). */
+typedef struct {
+    void *ptr;
+    int32_t dim;
+    int32_t type;
+    int32_t access;
+    int32_t on_device;
+} opf_gbl;
+
+/* Runs kernel k over set s.  Argument signatures (checked; dims are exact):
+ *
+ *  EDGE_FLUX over edges, variant COLOURED or ATOMIC:
+ *     (q, 0, e2n, 6, T, READ) (q, 1, e2n, 6, T, READ) (n, -1, ID, 3, T, READ)
+ *     (res, 0, e2n, 6, F64, INC) (res, 1, e2n, 6, F64, INC)
+ *     gbl (gamma, 1, F64, READ, host)
+ *   with T = F64, or T = F32 for the FP32-storage form (state, weights and flux
+ *   arithmetic in FP32, accumulation into the FP64 residual).
+ *  EDGE_FLUX_ADJ over edges (FP64):
+ *     (q,0,e2n,6,READ) (q,1,e2n,6,READ) (n,-1,ID,3,READ)
+ *     (rbar,0,e2n,6,READ) (rbar,1,e2n,6,READ)
+ *     (qbar,0,e2n,6,INC) (qbar,1,e2n,6,INC) (nbar,-1,ID,3,WRITE)
+ *     gbl (gamma, 1, F64, READ, host)
+ *  EDGE_SPECRAD over edges: (q,0,e2n,6,T,READ) (q,1,e2n,6,T,READ)
+ *     (n,-1,ID,3,T,READ) (lam,0,e2n,1,F64,INC) (lam,1,e2n,1,F64,INC) gbl gamma
+ *  RK_STAGE over nodes (direct):
+ *     (q0,-1,ID,6,T,READ) (res,-1,ID,6,F64,RW) (vol,-1,ID,1,F64,READ)
+ *     (q,-1,ID,6,T,WRITE)
+ *     gbl (alpha_dt, 1, F64, READ, host) gbl (ss, 6, F64, INC, device)
+ *   computes q = q0 - alpha_dt * res / vol in FP64 (rounded once to T), adds
+ *   sum_i res_i^2 per component to ss, and zeroes res.  The sum is
+ *   deterministic: fixed partition, fixed order.
+ *  DT_MIN over nodes (direct): (vol,-1,ID,1,F64,READ) (lam,-1,ID,1,F64,READ)
+ *     gbl (cfl, 1, F64, READ, host) gbl (dt, 1, F64, MIN, device)
+ *   dt = min(dt, cfl * min_i vol_i / lam_i).
+ *
+ * Asynchronous on `stream`.  Errors: OPF_EINVAL, OPF_ESIZE, OPF_ETYPE,
+ * OPF_EACCESS (signature mismatch), OPF_ESTATE (indirect loop without a
+ * current plan), OPF_EDEVICE (host-only context or launch failure). */
+int opf_par_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args, int ngbl,
+                 const opf_gbl *gbls, int variant, void *stream);
+
+/* Typed wrappers over opf_par_loop with the signatures above. */
+int opf_edge_flux(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n, opf_dat res,
+                  double gamma, int variant, void *stream);
+int opf_edge_flux_adjoint(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
+                          opf_dat rbar, opf_dat qbar, opf_dat nbar, double gamma, int variant,
+                          void *stream);
+int opf_edge_specrad(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
+                     opf_dat lam, double gamma, int variant, void *stream);
+int opf_rk_stage(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol, opf_dat q,
+                 double alpha_dt, double *ss_dev, void *stream);
+int opf_dt_min(opf_ctx *ctx, opf_set nodes, opf_dat vol, opf_dat lam, double cfl,
+               double *dt_dev, void *stream);
+
+/* Waits for `stream` and reports asynchronous HIP errors.  Errors: OPF_EDEVICE. */
+int opf_sync(opf_ctx *ctx, void *stream);
+
+/* Optional reduction check: reads n doubles from device memory and returns
+ * OPF_ENONFINITE if any is NaN or infinite (synchronises `stream`). */
+int opf_check_finite(opf_ctx *ctx, const double *dev_ptr, int n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OPFLUX_H */

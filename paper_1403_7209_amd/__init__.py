@@ -1,0 +1,436 @@
+"""Python binding of libopflux, the MI355X edge-flux library.
+
+Argument marshalling only: every step of the path (edge loops, stage updates,
+reductions) runs in the library's HIP kernels.  PyTorch supplies device
+memory (tensors become the library's borrowed dats) and streams.
+
+The calls mirror the C ABI in include/opflux.h, which follows the OP2 API of
+the paper (Sec. 3.1): declare sets, an edge->node map and data on sets, then
+run loops over sets whose arguments say how each array is reached and
+accessed.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+from . import _build
+
+__all__ = ["Context", "OpfError", "FluxProblem", "EdgeFluxFunction", "RK_ALPHA", "load",
+           "COLOURED", "ATOMIC"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = _build.LIB
+
+OK, EINVAL, ERANGE, ESIZE, ETYPE, EACCESS, ESTATE, ENOMEM, EDEVICE, ENONFINITE, EPLAN = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10
+STATUS = {0: "OPF_OK", -1: "OPF_EINVAL", -2: "OPF_ERANGE", -3: "OPF_ESIZE", -4: "OPF_ETYPE",
+          -5: "OPF_EACCESS", -6: "OPF_ESTATE", -7: "OPF_ENOMEM", -8: "OPF_EDEVICE",
+          -9: "OPF_ENONFINITE", -10: "OPF_EPLAN"}
+F64, F32 = 0, 1
+READ, WRITE, RW, INC, MIN = 0, 1, 2, 3, 4
+K_EDGE_FLUX, K_EDGE_FLUX_ADJ, K_RK_STAGE, K_EDGE_SPECRAD, K_DT_MIN = 0, 1, 2, 3, 4
+COLOURED, ATOMIC = 0, 1
+RENUMBER = {"none": 0, "rcm": 1, "morton": 2}
+ID = -1
+
+# Stage coefficients of the 5-stage scheme (low-storage form
+# q_k = q_0 - alpha_k dt res(q_{k-1}) / vol).
+RK_ALPHA = (1.0 / 4.0, 1.0 / 6.0, 3.0 / 8.0, 1.0 / 2.0, 1.0)
+
+# Exported symbols of include/opflux.h.
+SYMBOLS = ("opf_init", "opf_finalize", "opf_last_error", "opf_set_allocator", "opf_decl_set",
+           "opf_decl_map", "opf_plan", "opf_get_perm", "opf_plan_view_get", "opf_plan_verify",
+           "opf_decl_dat", "opf_par_loop", "opf_edge_flux", "opf_edge_flux_adjoint",
+           "opf_edge_specrad", "opf_rk_stage", "opf_dt_min", "opf_sync", "opf_check_finite")
+
+
+class OpfError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("renumber", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("colour_sort", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("coords", ctypes.c_void_p)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("nblocks", ctypes.c_int64), ("nblock_colours", ctypes.c_int32),
+                ("max_elem_colours", ctypes.c_int32), ("mean_elem_colours", ctypes.c_double),
+                ("sum_unique", ctypes.c_int64), ("max_unique", ctypes.c_int32),
+                ("min_blocks_per_colour", ctypes.c_int32), ("bandwidth_before", ctypes.c_int64),
+                ("bandwidth_after", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class PlanView(ctypes.Structure):
+    _fields_ = [("nnodes", ctypes.c_int64), ("nedges", ctypes.c_int64), ("nblocks", ctypes.c_int64),
+                ("nblock_colours", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("e2n", ctypes.c_void_p), ("block_offsets", ctypes.c_void_p),
+                ("block_colour", ctypes.c_void_p), ("colour_blocks", ctypes.c_void_p),
+                ("colour_offsets", ctypes.c_void_p), ("elem_colour", ctypes.c_void_p),
+                ("block_ncolours", ctypes.c_void_p), ("unique_offsets", ctypes.c_void_p),
+                ("unique_nodes", ctypes.c_void_p), ("local_idx", ctypes.c_void_p)]
+
+
+class PlanReport(ctypes.Structure):
+    _fields_ = [("ok", ctypes.c_int32), ("property", ctypes.c_int32), ("where", ctypes.c_int64),
+                ("message", ctypes.c_char * 160)]
+
+
+class Arg(ctypes.Structure):
+    _fields_ = [("dat", ctypes.c_int32), ("idx", ctypes.c_int32), ("map", ctypes.c_int32),
+                ("dim", ctypes.c_int32), ("type", ctypes.c_int32), ("access", ctypes.c_int32)]
+
+
+class Gbl(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("dim", ctypes.c_int32), ("type", ctypes.c_int32),
+                ("access", ctypes.c_int32), ("on_device", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def _hip_runtimes():
+    with open("/proc/self/maps") as f:
+        return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+
+
+def load():
+    """Loads libopflux.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1403_7209_amd._build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name in SYMBOLS:
+        getattr(lib, name)  # raises AttributeError if the export is missing
+    vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    lib.opf_init.argtypes = [P(vp), ctypes.c_int]
+    lib.opf_finalize.argtypes = [vp]
+    lib.opf_last_error.argtypes = [vp]
+    lib.opf_last_error.restype = ctypes.c_char_p
+    lib.opf_set_allocator.argtypes = [vp, vp, vp, vp]
+    lib.opf_decl_set.argtypes = [vp, i64, ctypes.c_char_p, P(i32)]
+    lib.opf_decl_map.argtypes = [vp, i32, i32, ctypes.c_int, vp, ctypes.c_int, ctypes.c_char_p, P(i32)]
+    lib.opf_plan.argtypes = [vp, i32, P(PlanOpts), P(PlanInfo)]
+    lib.opf_get_perm.argtypes = [vp, i32, vp]
+    lib.opf_plan_view_get.argtypes = [vp, i32, P(PlanView)]
+    lib.opf_plan_verify.argtypes = [vp, i32, P(PlanReport)]
+    lib.opf_decl_dat.argtypes = [vp, i32, ctypes.c_int, ctypes.c_int, vp, i64, ctypes.c_char_p, P(i32)]
+    lib.opf_par_loop.argtypes = [vp, ctypes.c_int, i32, ctypes.c_int, P(Arg), ctypes.c_int, P(Gbl),
+                                 ctypes.c_int, vp]
+    lib.opf_edge_flux.argtypes = [vp, i32, i32, i32, i32, i32, d, ctypes.c_int, vp]
+    lib.opf_edge_flux_adjoint.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, d, ctypes.c_int, vp]
+    lib.opf_edge_specrad.argtypes = [vp, i32, i32, i32, i32, i32, d, ctypes.c_int, vp]
+    lib.opf_rk_stage.argtypes = [vp, i32, i32, i32, i32, i32, d, vp, vp]
+    lib.opf_dt_min.argtypes = [vp, i32, i32, i32, d, vp, vp]
+    lib.opf_sync.argtypes = [vp, vp]
+    lib.opf_check_finite.argtypes = [vp, vp, ctypes.c_int, vp]
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise RuntimeError(f"more than one HIP runtime is mapped: {runtimes}")
+    _lib = lib
+    return lib
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_ptr(stream, device):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """An opf_ctx bound to one GPU (device >= 0) or host-only (device=None)."""
+
+    def __init__(self, device=None):
+        self.lib = load()
+        if device is None:
+            self.device = -1
+        else:
+            dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+            self.device = dev.index if dev.index is not None else torch.cuda.current_device()
+        self._ctx = ctypes.c_void_p()
+        rc = self.lib.opf_init(ctypes.byref(self._ctx), self.device)
+        if rc:
+            raise OpfError(rc, f"opf_init(device={self.device})")
+        self._dats = {}
+        self._keep = []
+
+    @property
+    def torch_device(self):
+        return torch.device("cuda", self.device)
+
+    def _check(self, rc, what):
+        if rc:
+            msg = self.lib.opf_last_error(self._ctx).decode(errors="replace")
+            raise OpfError(rc, f"{what}: {msg}")
+
+    def close(self):
+        if self._ctx:
+            self.lib.opf_finalize(self._ctx)
+            self._ctx = ctypes.c_void_p()
+            self._dats.clear()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- declarations ------------------------------------------------------
+    def decl_set(self, size, name=""):
+        out = ctypes.c_int32()
+        self._check(self.lib.opf_decl_set(self._ctx, int(size), name.encode(), ctypes.byref(out)),
+                    "opf_decl_set")
+        return out.value
+
+    def decl_map(self, from_set, to_set, dim, idx, index_base=0, name=""):
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        out = ctypes.c_int32()
+        self._check(self.lib.opf_decl_map(self._ctx, from_set, to_set, dim, _np_ptr(idx), index_base,
+                                          name.encode(), ctypes.byref(out)), "opf_decl_map")
+        return out.value
+
+    def plan(self, m, renumber="rcm", block_size=512, colour_sort=False, coords=None):
+        c = None if coords is None else np.ascontiguousarray(coords, dtype=np.float64)
+        opts = PlanOpts(RENUMBER[renumber], block_size, 1 if colour_sort else 0, 0,
+                        None if c is None else c.ctypes.data)
+        info = PlanInfo()
+        self._check(self.lib.opf_plan(self._ctx, m, ctypes.byref(opts), ctypes.byref(info)),
+                    "opf_plan")
+        return {k: getattr(info, k) for k, _ in PlanInfo._fields_}
+
+    def get_perm(self, s, size):
+        out = np.empty(size, dtype=np.int32)
+        self._check(self.lib.opf_get_perm(self._ctx, s, _np_ptr(out)), "opf_get_perm")
+        return out
+
+    def plan_view(self, m):
+        v = PlanView()
+        self._check(self.lib.opf_plan_view_get(self._ctx, m, ctypes.byref(v)), "opf_plan_view_get")
+        nb, E, nc = v.nblocks, v.nedges, v.nblock_colours
+
+        def arr(ptr, ctype, n, dtype):
+            if n == 0:
+                return np.empty(0, dtype=dtype)
+            buf = (ctype * n).from_address(ptr)
+            return np.frombuffer(buf, dtype=dtype).copy()
+
+        uoff = arr(v.unique_offsets, ctypes.c_int64, nb + 1, np.int64)
+        return dict(nnodes=v.nnodes, nedges=E, nblocks=nb, nblock_colours=nc,
+                    block_size=v.block_size,
+                    e2n=arr(v.e2n, ctypes.c_int32, 2 * E, np.int32).reshape(E, 2),
+                    block_offsets=arr(v.block_offsets, ctypes.c_int64, nb + 1, np.int64),
+                    block_colour=arr(v.block_colour, ctypes.c_int32, nb, np.int32),
+                    colour_blocks=arr(v.colour_blocks, ctypes.c_int32, nb, np.int32),
+                    colour_offsets=arr(v.colour_offsets, ctypes.c_int64, nc + 1, np.int64),
+                    elem_colour=arr(v.elem_colour, ctypes.c_uint8, E, np.uint8),
+                    block_ncolours=arr(v.block_ncolours, ctypes.c_int32, nb, np.int32),
+                    unique_offsets=uoff,
+                    unique_nodes=arr(v.unique_nodes, ctypes.c_int32, int(uoff[-1]), np.int32),
+                    local_idx=arr(v.local_idx, ctypes.c_uint16, 2 * E, np.uint16).reshape(E, 2))
+
+    def plan_verify(self, m):
+        rep = PlanReport()
+        rc = self.lib.opf_plan_verify(self._ctx, m, ctypes.byref(rep))
+        if rc not in (OK, EPLAN):
+            self._check(rc, "opf_plan_verify")
+        return dict(ok=bool(rep.ok), property=rep.property, where=rep.where,
+                    message=rep.message.decode(errors="replace"), status=rc)
+
+    def decl_dat(self, s, tensor, name=""):
+        """Declares a dat on set s borrowing a (dim, ld) or (ld,) device tensor."""
+        t = tensor
+        if t.dim() == 1:
+            dim, ld = 1, t.shape[0]
+        elif t.dim() == 2:
+            dim, ld = t.shape[0], t.stride(0)
+            if t.stride(1) != 1:
+                raise ValueError("dat tensors must be contiguous along elements")
+        else:
+            raise ValueError("dat tensors are (dim, ld) or (ld,)")
+        if t.dtype == torch.float64:
+            typ = F64
+        elif t.dtype == torch.float32:
+            typ = F32
+        else:
+            raise TypeError(f"unsupported dat dtype {t.dtype}")
+        if self.device >= 0 and (not t.is_cuda or t.device.index != self.device):
+            raise ValueError(f"dat '{name}' must be a tensor on cuda:{self.device}")
+        key = (s, t.data_ptr(), dim, typ, ld)
+        if key in self._dats:
+            return self._dats[key]
+        out = ctypes.c_int32()
+        self._check(self.lib.opf_decl_dat(self._ctx, s, dim, typ, ctypes.c_void_p(t.data_ptr()), ld,
+                                          name.encode(), ctypes.byref(out)), "opf_decl_dat")
+        self._dats[key] = out.value
+        return out.value
+
+    # -- loops -----------------------------------------------------------------
+    def par_loop(self, kernel, s, args, gbls, variant=COLOURED, stream=None):
+        a = (Arg * len(args))(*[Arg(*x) for x in args])
+        g = (Gbl * len(gbls))(*[Gbl(*x) for x in gbls])
+        self._check(self.lib.opf_par_loop(self._ctx, kernel, s, len(args), a, len(gbls), g, variant,
+                                          _stream_ptr(stream, self.device)), "opf_par_loop")
+
+    def edge_flux(self, edges, e2n, q, n, res, gamma=1.4, variant=COLOURED, stream=None):
+        self._check(self.lib.opf_edge_flux(self._ctx, edges, e2n, q, n, res, gamma, variant,
+                                           _stream_ptr(stream, self.device)), "opf_edge_flux")
+
+    def edge_flux_adjoint(self, edges, e2n, q, n, rbar, qbar, nbar, gamma=1.4, variant=COLOURED,
+                          stream=None):
+        self._check(self.lib.opf_edge_flux_adjoint(self._ctx, edges, e2n, q, n, rbar, qbar, nbar,
+                                                   gamma, variant, _stream_ptr(stream, self.device)),
+                    "opf_edge_flux_adjoint")
+
+    def edge_specrad(self, edges, e2n, q, n, lam, gamma=1.4, variant=COLOURED, stream=None):
+        self._check(self.lib.opf_edge_specrad(self._ctx, edges, e2n, q, n, lam, gamma, variant,
+                                              _stream_ptr(stream, self.device)), "opf_edge_specrad")
+
+    def rk_stage(self, nodes, q0, res, vol, q, alpha_dt, ss, stream=None):
+        """ss: float64 device tensor of 6 values, incremented by sum res^2."""
+        self._check(self.lib.opf_rk_stage(self._ctx, nodes, q0, res, vol, q, float(alpha_dt),
+                                          ctypes.c_void_p(ss.data_ptr()),
+                                          _stream_ptr(stream, self.device)), "opf_rk_stage")
+
+    def dt_min(self, nodes, vol, lam, cfl, dt, stream=None):
+        self._check(self.lib.opf_dt_min(self._ctx, nodes, vol, lam, float(cfl),
+                                        ctypes.c_void_p(dt.data_ptr()),
+                                        _stream_ptr(stream, self.device)), "opf_dt_min")
+
+    def sync(self, stream=None):
+        self._check(self.lib.opf_sync(self._ctx, _stream_ptr(stream, self.device)), "opf_sync")
+
+    def check_finite(self, t, stream=None):
+        rc = self.lib.opf_check_finite(self._ctx, ctypes.c_void_p(t.data_ptr()), t.numel(),
+                                       _stream_ptr(stream, self.device))
+        if rc == ENONFINITE:
+            return False
+        self._check(rc, "opf_check_finite")
+        return True
+
+
+class FluxProblem:
+    """The edge-flux path on one mesh: node and edge sets, the edge->node map,
+    its plan, and device dats in the library's internal numbering.
+
+    Inputs are host arrays in user numbering: e2n (E, 2) int32, w (3, E)
+    weights, vol (N,), q (6, N).  fp32=True keeps the state and weights in
+    FP32 (the residual, volumes and reductions stay FP64)."""
+
+    def __init__(self, ctx, e2n, w, vol, q, fp32=False, renumber="rcm", block_size=512,
+                 colour_sort=False, coords=None, gamma=1.4, index_base=0):
+        self.ctx, self.gamma, self.fp32 = ctx, float(gamma), fp32
+        e2n = np.ascontiguousarray(e2n, dtype=np.int32)
+        self.N, self.E = int(np.asarray(vol).shape[0]), int(e2n.shape[0])
+        self.nodes = ctx.decl_set(self.N, "nodes")
+        self.edges = ctx.decl_set(self.E, "edges")
+        self.e2n = ctx.decl_map(self.edges, self.nodes, 2, e2n, index_base, "e2n")
+        self.info = ctx.plan(self.e2n, renumber=renumber, block_size=block_size,
+                             colour_sort=colour_sort, coords=coords)
+        self.node_new = ctx.get_perm(self.nodes, self.N)
+        self.edge_new = ctx.get_perm(self.edges, self.E)
+        dev = ctx.torch_device
+        self.tdtype = torch.float32 if fp32 else torch.float64
+        self.w_t = self.nodes_in(w, edges=True).to(self.tdtype)
+        self.vol_t = self.nodes_in(np.asarray(vol, dtype=np.float64)[None, :])[0].contiguous()
+        self.qa = self.nodes_in(q).to(self.tdtype)          # q0 / state
+        self.qb = torch.empty_like(self.qa)                  # stage state
+        self.res = torch.zeros((6, self.N), dtype=torch.float64, device=dev)
+        self.ss = torch.zeros((5, 6), dtype=torch.float64, device=dev)
+        self.lam = torch.zeros(self.N, dtype=torch.float64, device=dev)
+        self.dt_t = torch.full((1,), float("inf"), dtype=torch.float64, device=dev)
+        self.w = ctx.decl_dat(self.edges, self.w_t, "n")
+        self.vol = ctx.decl_dat(self.nodes, self.vol_t, "vol")
+        self.res_d = ctx.decl_dat(self.nodes, self.res, "res")
+        self.lam_d = ctx.decl_dat(self.nodes, self.lam, "lam")
+
+    # -- numbering -------------------------------------------------------------
+    def nodes_in(self, a, edges=False):
+        """Host (d, n) array in user numbering -> device tensor in internal numbering."""
+        a = np.asarray(a)
+        perm = self.edge_new if edges else self.node_new
+        out = np.empty_like(a)
+        out[:, perm] = a
+        return torch.from_numpy(out).to(self.ctx.torch_device)
+
+    def nodes_out(self, t, edges=False):
+        """Device tensor in internal numbering -> host array in user numbering."""
+        perm = self.edge_new if edges else self.node_new
+        return t.detach().cpu().numpy()[:, perm]
+
+    def dat(self, t, name="", edges=False):
+        return self.ctx.decl_dat(self.edges if edges else self.nodes, t, name)
+
+    # -- loops -------------------------------------------------------------------
+    def residual(self, q_t, res_t, variant=COLOURED, stream=None):
+        """res_t += edge-flux residual of state q_t (both internal numbering)."""
+        self.ctx.edge_flux(self.edges, self.e2n, self.dat(q_t, "q"), self.w, self.dat(res_t, "res"),
+                           self.gamma, variant, stream)
+
+    def compute_dt(self, cfl=0.5, variant=COLOURED, stream=None):
+        """Global time step cfl * min_i vol_i / sum_e lambda_e of the current state."""
+        self.lam.zero_()
+        self.dt_t.fill_(float("inf"))
+        self.ctx.edge_specrad(self.edges, self.e2n, self.dat(self.qa, "q"), self.w, self.lam_d,
+                              self.gamma, variant, stream)
+        self.ctx.dt_min(self.nodes, self.vol, self.lam_d, cfl, self.dt_t, stream)
+        return float(self.dt_t.item())
+
+    def rk_iteration(self, dt, variant=COLOURED, stream=None):
+        """One 5-stage iteration; the new state is left in self.qa.  self.ss
+        (5, 6) receives each stage's per-variable sum of squared residuals."""
+        qa, qb = self.dat(self.qa, "qa"), self.dat(self.qb, "qb")
+        self.ss.zero_()
+        for k in range(5):
+            src = qa if k == 0 else qb
+            self.ctx.edge_flux(self.edges, self.e2n, src, self.w, self.res_d, self.gamma, variant,
+                               stream)
+            self.ctx.rk_stage(self.nodes, qa, self.res_d, self.vol, qb, RK_ALPHA[k] * dt,
+                              self.ss[k], stream)
+        self.qa, self.qb = self.qb, self.qa
+
+    def rms(self):
+        """Per-stage, per-variable RMS sqrt(ss / N) of the last iteration (host)."""
+        return np.sqrt(self.ss.cpu().numpy() / self.N)
+
+
+class EdgeFluxFunction(torch.autograd.Function):
+    """res = R(q, n) on a FluxProblem (internal numbering, FP64).  The backward
+    pass runs the hand-written adjoint edge kernel, which recomputes the edge
+    fluxes instead of storing them."""
+
+    @staticmethod
+    def forward(ctx, problem, q, w, variant=COLOURED):
+        res = torch.zeros((6, problem.N), dtype=torch.float64, device=q.device)
+        problem.ctx.edge_flux(problem.edges, problem.e2n, problem.dat(q.detach(), "q"),
+                              problem.dat(w.detach(), "n", edges=True), problem.dat(res, "res"),
+                              problem.gamma, variant)
+        ctx.problem, ctx.variant = problem, variant
+        ctx.save_for_backward(q, w)
+        return res
+
+    @staticmethod
+    def backward(ctx, rbar):
+        q, w = ctx.saved_tensors
+        p = ctx.problem
+        rbar = rbar.contiguous()
+        qbar = torch.zeros_like(q)
+        nbar = torch.empty_like(w)
+        p.ctx.edge_flux_adjoint(p.edges, p.e2n, p.dat(q.detach(), "q"),
+                                p.dat(w.detach(), "n", edges=True), p.dat(rbar, "rbar"),
+                                p.dat(qbar, "qbar"), p.dat(nbar, "nbar", edges=True), p.gamma,
+                                ctx.variant)
+        return None, qbar, nbar, None

@@ -1,0 +1,70 @@
+// kernels.hpp -- launch interface of the gfx950 kernels (internal to libopflux).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace opf {
+namespace gpu {
+
+enum EdgeOpKind { OP_FLUX = 0, OP_ADJOINT = 1, OP_SPECRAD = 2 };
+
+// Device copy of an execution plan (internal numbering, int32 offsets).
+struct DevPlan {
+    int N = 0, E = 0, nb = 0, nc = 0, umax = 0, block_size = 0;
+    const int2 *e2n = nullptr;            // [E] endpoint pairs
+    const int *block_off = nullptr;       // [nb+1]
+    const int *uniq_off = nullptr;        // [nb+1]
+    const int *uniq = nullptr;            // [sum U]
+    const uint32_t *lidx = nullptr;       // [E] two 16-bit local indices
+    const uint8_t *ecol = nullptr;        // [E]
+    const int *block_ncol = nullptr;      // [nb]
+    const int *colour_blocks = nullptr;   // [nb]
+    std::vector<int> colour_off;          // host copy [nc+1]
+};
+
+// Component pointers of the arrays an edge loop touches (SoA: one pointer per
+// component, each already offset by component * ld).
+struct EdgeArrays {
+    const void *xin[12] = {};  // node inputs (q, then rbar for the adjoint)
+    double *yout[6] = {};      // node increments (res, qbar or lambda)
+    const void *w[3] = {};     // edge weights
+    double *wout[3] = {};      // direct edge outputs (nbar)
+};
+
+struct LaunchOpts {
+    int xcd_remap = 1;  // map consecutive partitions of a colour to one XCD
+};
+
+// Returns 0 or a hipError_t value.
+int launch_edge(int op, bool fp32, int variant, const DevPlan &plan, const EdgeArrays &a,
+                double gamma, hipStream_t stream, const LaunchOpts &lo);
+
+struct NodeArrays {
+    const void *q0[6] = {};
+    double *res[6] = {};
+    const double *vol = nullptr;
+    void *q[6] = {};
+};
+
+// q = q0 - alpha_dt * res / vol, res = 0, ss[v] += sum res^2 (two passes,
+// deterministic).  `partial` holds kRkBlocks * 6 doubles.
+constexpr int kRkThreads = 256;
+constexpr int kRkBlocks = 2048;
+int launch_rk_stage(bool fp32, int N, const NodeArrays &a, double alpha_dt, double *ss,
+                    double *partial, hipStream_t stream);
+
+// dt = min(dt, cfl * min_i vol_i / lam_i); `partial` holds kRkBlocks doubles.
+int launch_dt_min(int N, const double *vol, const double *lam, double cfl, double *dt,
+                  double *partial, hipStream_t stream);
+
+// LDS bytes one partition of an edge loop needs.
+size_t edge_lds_bytes(int op, bool fp32, int umax);
+
+// Raises the dynamic-LDS limit of every coloured kernel instance to `bytes`.
+int set_lds_limit(size_t bytes);
+
+}  // namespace gpu
+}  // namespace opf

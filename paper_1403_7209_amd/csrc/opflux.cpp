@@ -1,0 +1,744 @@
+// opflux.cpp -- C ABI of libopflux: context, declarations, plans and loops.
+//
+// Follows the OP2 model (Sec. 3.1-3.2): sets, maps and dats are declared once;
+// the library owns the maps and may renumber the sets; an op_par_loop-style
+// call names a kernel and describes each argument (dat, map column, map,
+// dimension, type, access), and the library checks that description against
+// the kernel's fixed signature before launching it.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "opflux.h"
+#include "planner.hpp"
+
+namespace {
+
+struct SetRec {
+    int64_t size = 0;
+    std::string name;
+    int plan_map = -1;  // map whose plan renumbered this set
+};
+
+struct MapRec {
+    opf_set from = -1, to = -1;
+    int dim = 0;
+    std::vector<int32_t> idx;  // 0-based, row-major
+    std::string name;
+    uint64_t version = 0;
+};
+
+struct DatRec {
+    opf_set set = -1;
+    int dim = 0;
+    int type = 0;
+    void *ptr = nullptr;
+    int64_t ld = 0;
+    std::string name;
+};
+
+struct PlanRec {
+    opf::Plan host;
+    opf::gpu::DevPlan dev;
+    std::vector<void *> bufs;
+    uint64_t map_version = 0;
+    int64_t device_bytes = 0;
+    bool on_device = false;
+};
+
+size_t type_size(int t) { return t == OPF_F32 ? 4 : 8; }
+
+}  // namespace
+
+struct opf_ctx {
+    int device = -1;
+    std::string err;
+    std::vector<SetRec> sets;
+    std::vector<MapRec> maps;
+    std::vector<DatRec> dats;
+    std::map<int, std::unique_ptr<PlanRec>> plans;
+    void *(*alloc_fn)(void *, size_t) = nullptr;
+    void (*free_fn)(void *, void *) = nullptr;
+    void *alloc_user = nullptr;
+    double *scratch = nullptr;  // partial sums of the direct reductions
+    size_t max_lds = 65536;
+    size_t lds_limit = 65536;
+    uint64_t next_version = 1;
+
+    int fail(int code, const std::string &msg)
+    {
+        err = msg;
+        return code;
+    }
+    void *dalloc(size_t bytes)
+    {
+        if (bytes == 0) bytes = 256;
+        if (alloc_fn) return alloc_fn(alloc_user, bytes);
+        void *p = nullptr;
+        return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+    }
+    void dfree(void *p)
+    {
+        if (!p) return;
+        if (free_fn)
+            free_fn(alloc_user, p);
+        else
+            (void)hipFree(p);
+    }
+    bool set_ok(opf_set s) const { return s >= 0 && s < (opf_set)sets.size(); }
+    bool map_ok(opf_map m) const { return m >= 0 && m < (opf_map)maps.size(); }
+    bool dat_ok(opf_dat d) const { return d >= 0 && d < (opf_dat)dats.size(); }
+};
+
+namespace {
+
+int hip_fail(opf_ctx *ctx, hipError_t e, const char *what)
+{
+    return ctx->fail(OPF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void free_plan(opf_ctx *ctx, PlanRec &p)
+{
+    for (void *b : p.bufs) ctx->dfree(b);
+    p.bufs.clear();
+    p.on_device = false;
+}
+
+template <typename T>
+int upload(opf_ctx *ctx, PlanRec &p, const std::vector<T> &v, const T *&out)
+{
+    const size_t bytes = v.size() * sizeof(T);
+    void *d = ctx->dalloc(bytes);
+    if (!d) return ctx->fail(OPF_ENOMEM, "device allocation of plan arrays failed");
+    p.bufs.push_back(d);
+    p.device_bytes += (int64_t)bytes;
+    if (bytes) {
+        hipError_t e = hipMemcpy(d, v.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(ctx, e, "plan upload");
+    }
+    out = static_cast<const T *>(d);
+    return OPF_OK;
+}
+
+int upload_plan(opf_ctx *ctx, PlanRec &pr)
+{
+    const opf::Plan &P = pr.host;
+    if (P.E >= (int64_t)1 << 31 || (int64_t)P.uniq.size() >= (int64_t)1 << 31)
+        return ctx->fail(OPF_ESIZE, "plan too large for 32-bit device offsets");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+    const int64_t nb = P.nblocks();
+    std::vector<int2> e2n(P.E);
+    for (int64_t k = 0; k < P.E; ++k) e2n[k] = make_int2(P.e2n[2 * k], P.e2n[2 * k + 1]);
+    std::vector<int> block_off(nb + 1), uniq_off(nb + 1);
+    for (int64_t b = 0; b <= nb; ++b) {
+        block_off[b] = (int)P.block_off[b];
+        uniq_off[b] = (int)P.uniq_off[b];
+    }
+    std::vector<uint32_t> lidx(P.E);
+    for (int64_t k = 0; k < P.E; ++k)
+        lidx[k] = (uint32_t)P.lidx[2 * k] | ((uint32_t)P.lidx[2 * k + 1] << 16);
+    opf::gpu::DevPlan &D = pr.dev;
+    D = opf::gpu::DevPlan();
+    D.N = (int)P.N;
+    D.E = (int)P.E;
+    D.nb = (int)nb;
+    D.nc = P.nblock_colours;
+    D.umax = P.max_unique;
+    D.block_size = P.block_size;
+    D.colour_off.assign(P.colour_off.begin(), P.colour_off.end());
+    int rc = OPF_OK;
+    if (!rc) rc = upload(ctx, pr, e2n, D.e2n);
+    if (!rc) rc = upload(ctx, pr, block_off, D.block_off);
+    if (!rc) rc = upload(ctx, pr, uniq_off, D.uniq_off);
+    if (!rc) rc = upload(ctx, pr, P.uniq, D.uniq);
+    if (!rc) rc = upload(ctx, pr, lidx, D.lidx);
+    if (!rc) rc = upload(ctx, pr, P.ecol, D.ecol);
+    if (!rc) rc = upload(ctx, pr, P.block_ncol, D.block_ncol);
+    if (!rc) rc = upload(ctx, pr, P.colour_blocks, D.colour_blocks);
+    if (rc) {
+        free_plan(ctx, pr);
+        return rc;
+    }
+    pr.on_device = true;
+    return OPF_OK;
+}
+
+// Expected shape of one loop argument.
+struct Want {
+    opf_set set;  // set the dat lives on
+    int idx;      // map column, or -1
+    opf_map map;  // map, or OPF_ID
+    int dim;
+    int type;     // -1: any of F64/F32 (checked by the caller)
+    int access;
+};
+
+int check_arg(opf_ctx *ctx, const opf_arg &a, const Want &w, int pos)
+{
+    const std::string at = "argument " + std::to_string(pos) + ": ";
+    if (!ctx->dat_ok(a.dat)) return ctx->fail(OPF_EINVAL, at + "invalid dat handle");
+    const DatRec &d = ctx->dats[a.dat];
+    if (a.map != w.map || a.idx != w.idx)
+        return ctx->fail(OPF_EINVAL, at + "expected map " + std::to_string(w.map) + " index " +
+                                         std::to_string(w.idx));
+    if (d.set != w.set) return ctx->fail(OPF_EINVAL, at + "dat '" + d.name + "' is on the wrong set");
+    if (a.dim != w.dim || d.dim != w.dim)
+        return ctx->fail(OPF_ESIZE, at + "expected dimension " + std::to_string(w.dim));
+    if (a.type != d.type) return ctx->fail(OPF_ETYPE, at + "type differs from the dat's type");
+    if (w.type >= 0 && a.type != w.type) return ctx->fail(OPF_ETYPE, at + "wrong data type");
+    if (a.access != w.access) return ctx->fail(OPF_EACCESS, at + "wrong access mode");
+    return OPF_OK;
+}
+
+int check_gbl(opf_ctx *ctx, const opf_gbl &g, int dim, int access, int on_device, int pos)
+{
+    const std::string at = "global " + std::to_string(pos) + ": ";
+    if (!g.ptr) return ctx->fail(OPF_EINVAL, at + "NULL pointer");
+    if (g.dim != dim) return ctx->fail(OPF_ESIZE, at + "expected dimension " + std::to_string(dim));
+    if (g.type != OPF_F64) return ctx->fail(OPF_ETYPE, at + "globals are F64");
+    if (g.access != access) return ctx->fail(OPF_EACCESS, at + "wrong access mode");
+    if (g.on_device != on_device)
+        return ctx->fail(OPF_EINVAL, at + (on_device ? "must be device memory" : "must be host memory"));
+    return OPF_OK;
+}
+
+const void *comp(const DatRec &d, int c)
+{
+    return static_cast<const char *>(d.ptr) + (size_t)c * (size_t)d.ld * type_size(d.type);
+}
+
+int device_ready(opf_ctx *ctx)
+{
+    if (ctx->device < 0) return ctx->fail(OPF_EDEVICE, "host-only context cannot run loops");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+    if (!ctx->scratch) {
+        ctx->scratch = static_cast<double *>(
+            ctx->dalloc(sizeof(double) * 6 * opf::gpu::kRkBlocks));
+        if (!ctx->scratch) return ctx->fail(OPF_ENOMEM, "scratch allocation failed");
+    }
+    return OPF_OK;
+}
+
+int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args, int ngbl,
+              const opf_gbl *gbls, int variant, hipStream_t st)
+{
+    const int want_args = kernel == OPF_K_EDGE_FLUX_ADJ ? 8 : 5;
+    if (nargs != want_args || !args)
+        return ctx->fail(OPF_EINVAL, "expected " + std::to_string(want_args) + " arguments");
+    if (ngbl != 1 || !gbls) return ctx->fail(OPF_EINVAL, "expected one global (gamma)");
+    if (variant != OPF_V_COLOURED && variant != OPF_V_ATOMIC)
+        return ctx->fail(OPF_EINVAL, "unknown variant");
+    const opf_map m = args[0].map;
+    if (!ctx->map_ok(m)) return ctx->fail(OPF_EINVAL, "argument 0: invalid map");
+    const MapRec &mr = ctx->maps[m];
+    if (mr.dim != 2 || mr.from != s)
+        return ctx->fail(OPF_EINVAL, "the loop set must be the source set of an arity-2 map");
+    if (!ctx->dat_ok(args[0].dat)) return ctx->fail(OPF_EINVAL, "argument 0: invalid dat");
+    const int T = ctx->dats[args[0].dat].type;
+    if (T != OPF_F64 && T != OPF_F32) return ctx->fail(OPF_ETYPE, "argument 0: unknown type");
+    if (kernel == OPF_K_EDGE_FLUX_ADJ && T != OPF_F64)
+        return ctx->fail(OPF_ETYPE, "the adjoint loop is FP64 only");
+    const opf_set nodes = mr.to;
+    int rc = OPF_OK;
+    const int yd = kernel == OPF_K_EDGE_SPECRAD ? 1 : 6;
+    std::vector<Want> w = {{nodes, 0, m, 6, T, OPF_READ}, {nodes, 1, m, 6, T, OPF_READ},
+                           {s, -1, OPF_ID, 3, T, OPF_READ}};
+    if (kernel == OPF_K_EDGE_FLUX_ADJ) {
+        w.push_back({nodes, 0, m, 6, OPF_F64, OPF_READ});
+        w.push_back({nodes, 1, m, 6, OPF_F64, OPF_READ});
+        w.push_back({nodes, 0, m, 6, OPF_F64, OPF_INC});
+        w.push_back({nodes, 1, m, 6, OPF_F64, OPF_INC});
+        w.push_back({s, -1, OPF_ID, 3, OPF_F64, OPF_WRITE});
+    } else {
+        w.push_back({nodes, 0, m, yd, OPF_F64, OPF_INC});
+        w.push_back({nodes, 1, m, yd, OPF_F64, OPF_INC});
+    }
+    for (int k = 0; k < nargs && !rc; ++k) rc = check_arg(ctx, args[k], w[k], k);
+    if (rc) return rc;
+    // the two map columns of a node argument must name the same dat
+    auto same = [&](int a, int b) {
+        return args[a].dat == args[b].dat
+                   ? OPF_OK
+                   : ctx->fail(OPF_EINVAL, "arguments " + std::to_string(a) + " and " +
+                                               std::to_string(b) + " must name the same dat");
+    };
+    rc = same(0, 1);
+    if (!rc) rc = kernel == OPF_K_EDGE_FLUX_ADJ ? same(3, 4) : same(3, 4);
+    if (!rc && kernel == OPF_K_EDGE_FLUX_ADJ) rc = same(5, 6);
+    if (rc) return rc;
+    rc = check_gbl(ctx, gbls[0], 1, OPF_READ, 0, 0);
+    if (rc) return rc;
+    auto it = ctx->plans.find(m);
+    if (it == ctx->plans.end()) return ctx->fail(OPF_ESTATE, "no plan for this map: call opf_plan");
+    PlanRec &pr = *it->second;
+    if (pr.map_version != mr.version) return ctx->fail(OPF_ESTATE, "plan is stale: map re-declared");
+    rc = device_ready(ctx);
+    if (rc) return rc;
+    if (!pr.on_device) return ctx->fail(OPF_ESTATE, "plan is not on the device");
+
+    const int op = kernel == OPF_K_EDGE_FLUX       ? opf::gpu::OP_FLUX
+                   : kernel == OPF_K_EDGE_FLUX_ADJ ? opf::gpu::OP_ADJOINT
+                                                   : opf::gpu::OP_SPECRAD;
+    const bool fp32 = T == OPF_F32;
+    if (variant == OPF_V_COLOURED) {
+        const size_t lds = opf::gpu::edge_lds_bytes(op, fp32, pr.dev.umax);
+        if (lds > ctx->max_lds)
+            return ctx->fail(OPF_EINVAL, "partition needs " + std::to_string(lds) +
+                                             " B of LDS; use a smaller block size");
+        if (lds > ctx->lds_limit) {
+            int e = opf::gpu::set_lds_limit(ctx->max_lds);
+            if (e) return hip_fail(ctx, (hipError_t)e, "raising the LDS limit");
+            ctx->lds_limit = ctx->max_lds;
+        }
+    }
+    opf::gpu::EdgeArrays ea;
+    const DatRec &q = ctx->dats[args[0].dat];
+    const DatRec &n = ctx->dats[args[2].dat];
+    for (int c = 0; c < 6; ++c) ea.xin[c] = comp(q, c);
+    for (int c = 0; c < 3; ++c) ea.w[c] = comp(n, c);
+    if (kernel == OPF_K_EDGE_FLUX_ADJ) {
+        const DatRec &rb = ctx->dats[args[3].dat], &qb = ctx->dats[args[5].dat];
+        const DatRec &nb = ctx->dats[args[7].dat];
+        for (int c = 0; c < 6; ++c) ea.xin[6 + c] = comp(rb, c);
+        for (int c = 0; c < 6; ++c) ea.yout[c] = (double *)comp(qb, c);
+        for (int c = 0; c < 3; ++c) ea.wout[c] = (double *)comp(nb, c);
+    } else {
+        const DatRec &r = ctx->dats[args[3].dat];
+        for (int c = 0; c < yd; ++c) ea.yout[c] = (double *)comp(r, c);
+    }
+    const double gamma = *static_cast<const double *>(gbls[0].ptr);
+    opf::gpu::LaunchOpts lo;
+    int e = opf::gpu::launch_edge(op, fp32, variant, pr.dev, ea, gamma, st, lo);
+    if (e) return hip_fail(ctx, (hipError_t)e, "edge loop launch");
+    return OPF_OK;
+}
+
+int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args, int ngbl,
+                const opf_gbl *gbls, hipStream_t st)
+{
+    int rc = OPF_OK;
+    if (kernel == OPF_K_RK_STAGE) {
+        if (nargs != 4 || !args) return ctx->fail(OPF_EINVAL, "expected 4 arguments");
+        if (ngbl != 2 || !gbls) return ctx->fail(OPF_EINVAL, "expected 2 globals");
+        if (!ctx->dat_ok(args[0].dat)) return ctx->fail(OPF_EINVAL, "argument 0: invalid dat");
+        const int T = ctx->dats[args[0].dat].type;
+        const Want w[4] = {{s, -1, OPF_ID, 6, T, OPF_READ},
+                           {s, -1, OPF_ID, 6, OPF_F64, OPF_RW},
+                           {s, -1, OPF_ID, 1, OPF_F64, OPF_READ},
+                           {s, -1, OPF_ID, 6, T, OPF_WRITE}};
+        for (int k = 0; k < 4 && !rc; ++k) rc = check_arg(ctx, args[k], w[k], k);
+        if (!rc) rc = check_gbl(ctx, gbls[0], 1, OPF_READ, 0, 0);
+        if (!rc) rc = check_gbl(ctx, gbls[1], 6, OPF_INC, 1, 1);
+        if (rc) return rc;
+        if (args[0].dat == args[3].dat || args[1].dat == args[3].dat)
+            return ctx->fail(OPF_EINVAL, "q must not alias q0 or res");
+        rc = device_ready(ctx);
+        if (rc) return rc;
+        opf::gpu::NodeArrays na;
+        const DatRec &q0 = ctx->dats[args[0].dat], &res = ctx->dats[args[1].dat];
+        const DatRec &vol = ctx->dats[args[2].dat], &q = ctx->dats[args[3].dat];
+        for (int c = 0; c < 6; ++c) {
+            na.q0[c] = comp(q0, c);
+            na.res[c] = (double *)comp(res, c);
+            na.q[c] = (void *)comp(q, c);
+        }
+        na.vol = static_cast<const double *>(vol.ptr);
+        const double adt = *static_cast<const double *>(gbls[0].ptr);
+        int e = opf::gpu::launch_rk_stage(T == OPF_F32, (int)ctx->sets[s].size, na, adt,
+                                          static_cast<double *>(gbls[1].ptr), ctx->scratch, st);
+        if (e) return hip_fail(ctx, (hipError_t)e, "RK stage launch");
+        return OPF_OK;
+    }
+    // DT_MIN
+    if (nargs != 2 || !args) return ctx->fail(OPF_EINVAL, "expected 2 arguments");
+    if (ngbl != 2 || !gbls) return ctx->fail(OPF_EINVAL, "expected 2 globals");
+    const Want w[2] = {{s, -1, OPF_ID, 1, OPF_F64, OPF_READ}, {s, -1, OPF_ID, 1, OPF_F64, OPF_READ}};
+    for (int k = 0; k < 2 && !rc; ++k) rc = check_arg(ctx, args[k], w[k], k);
+    if (!rc) rc = check_gbl(ctx, gbls[0], 1, OPF_READ, 0, 0);
+    if (!rc) rc = check_gbl(ctx, gbls[1], 1, OPF_MIN, 1, 1);
+    if (rc) return rc;
+    rc = device_ready(ctx);
+    if (rc) return rc;
+    const double cfl = *static_cast<const double *>(gbls[0].ptr);
+    int e = opf::gpu::launch_dt_min((int)ctx->sets[s].size,
+                                    static_cast<const double *>(ctx->dats[args[0].dat].ptr),
+                                    static_cast<const double *>(ctx->dats[args[1].dat].ptr), cfl,
+                                    static_cast<double *>(gbls[1].ptr), ctx->scratch, st);
+    if (e) return hip_fail(ctx, (hipError_t)e, "time-step launch");
+    return OPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int opf_init(opf_ctx **out, int hip_device)
+{
+    if (!out) return OPF_EINVAL;
+    *out = nullptr;
+    std::unique_ptr<opf_ctx> ctx(new (std::nothrow) opf_ctx());
+    if (!ctx) return OPF_ENOMEM;
+    if (hip_device < -1) return OPF_EINVAL;
+    if (hip_device >= 0) {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || hip_device >= n) return OPF_EDEVICE;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return OPF_EDEVICE;
+        ctx->max_lds = prop.sharedMemPerBlock;
+        if (prop.maxSharedMemoryPerMultiProcessor > ctx->max_lds)
+            ctx->max_lds = std::min<size_t>(prop.maxSharedMemoryPerMultiProcessor, 160 * 1024);
+    }
+    ctx->device = hip_device;
+    *out = ctx.release();
+    return OPF_OK;
+}
+
+int opf_finalize(opf_ctx *ctx)
+{
+    if (!ctx) return OPF_OK;
+    if (ctx->device >= 0) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        for (auto &kv : ctx->plans) free_plan(ctx, *kv.second);
+        ctx->dfree(ctx->scratch);
+    }
+    delete ctx;
+    return OPF_OK;
+}
+
+const char *opf_last_error(const opf_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int opf_set_allocator(opf_ctx *ctx, void *(*alloc_fn)(void *, size_t), void (*free_fn)(void *, void *),
+                      void *user)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (!ctx->plans.empty() || ctx->scratch)
+        return ctx->fail(OPF_ESTATE, "set the allocator before the first plan or loop");
+    if ((alloc_fn == nullptr) != (free_fn == nullptr))
+        return ctx->fail(OPF_EINVAL, "give both allocator functions or neither");
+    ctx->alloc_fn = alloc_fn;
+    ctx->free_fn = free_fn;
+    ctx->alloc_user = user;
+    return OPF_OK;
+}
+
+int opf_decl_set(opf_ctx *ctx, int64_t size, const char *name, opf_set *out)
+{
+    if (!ctx || !out) return ctx ? ctx->fail(OPF_EINVAL, "out is NULL") : OPF_EINVAL;
+    if (size <= 0 || size >= ((int64_t)1 << 31))
+        return ctx->fail(OPF_ESIZE, "set size must be in (0, 2^31)");
+    SetRec s;
+    s.size = size;
+    s.name = name ? name : "";
+    ctx->sets.push_back(s);
+    *out = (opf_set)ctx->sets.size() - 1;
+    return OPF_OK;
+}
+
+int opf_decl_map(opf_ctx *ctx, opf_set from, opf_set to, int dim, const int32_t *idx, int index_base,
+                 const char *name, opf_map *out)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (!out || !idx) return ctx->fail(OPF_EINVAL, "NULL argument");
+    if (!ctx->set_ok(from) || !ctx->set_ok(to)) return ctx->fail(OPF_EINVAL, "invalid set handle");
+    if (dim < 1) return ctx->fail(OPF_EINVAL, "map dimension must be >= 1");
+    if (index_base != 0 && index_base != 1) return ctx->fail(OPF_EINVAL, "index_base must be 0 or 1");
+    if (ctx->sets[from].plan_map >= 0 || ctx->sets[to].plan_map >= 0) {
+        // a map declared on renumbered sets would have to be in internal
+        // numbering; keep declarations in user numbering only
+        std::string nm = name ? name : "";
+        bool replacing = false;
+        for (const MapRec &m : ctx->maps)
+            if (!nm.empty() && m.name == nm) replacing = true;
+        if (!replacing) return ctx->fail(OPF_ESTATE, "declare maps before planning their sets");
+    }
+    const int64_t n = ctx->sets[from].size * dim, tsz = ctx->sets[to].size;
+    std::vector<int32_t> v(idx, idx + n);
+    for (int64_t k = 0; k < n; ++k) {
+        v[k] -= index_base;
+        if (v[k] < 0 || v[k] >= tsz)
+            return ctx->fail(OPF_ERANGE, "map entry " + std::to_string(k) + " = " +
+                                             std::to_string(idx[k]) + " is outside the target set");
+    }
+    MapRec m;
+    m.from = from;
+    m.to = to;
+    m.dim = dim;
+    m.idx.swap(v);
+    m.name = name ? name : "";
+    m.version = ctx->next_version++;
+    if (!m.name.empty())
+        for (size_t k = 0; k < ctx->maps.size(); ++k)
+            if (ctx->maps[k].name == m.name) {
+                ctx->maps[k] = std::move(m);  // the old plan becomes stale
+                *out = (opf_map)k;
+                return OPF_OK;
+            }
+    ctx->maps.push_back(std::move(m));
+    *out = (opf_map)ctx->maps.size() - 1;
+    return OPF_OK;
+}
+
+int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info *info)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (!ctx->map_ok(map)) return ctx->fail(OPF_EINVAL, "invalid map handle");
+    MapRec &m = ctx->maps[map];
+    if (m.dim != 2) return ctx->fail(OPF_EINVAL, "plans are built for arity-2 (edge) maps");
+    for (opf_set s : {m.from, m.to})
+        if (ctx->sets[s].plan_map >= 0 && ctx->sets[s].plan_map != map)
+            return ctx->fail(OPF_ESTATE, "set '" + ctx->sets[s].name + "' is renumbered by another plan");
+    opf::PlanOptions po;
+    if (opts) {
+        po.renumber = opts->renumber;
+        po.block_size = opts->block_size;
+        po.colour_sort = opts->colour_sort;
+        po.coords = opts->coords;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    auto pr = std::unique_ptr<PlanRec>(new (std::nothrow) PlanRec());
+    if (!pr) return ctx->fail(OPF_ENOMEM, "out of host memory");
+    int rc;
+    try {
+        rc = opf::build_plan(ctx->sets[m.to].size, ctx->sets[m.from].size, m.idx.data(), po,
+                             pr->host, ctx->err);
+    } catch (const std::bad_alloc &) {
+        return ctx->fail(OPF_ENOMEM, "out of host memory while planning");
+    }
+    if (rc) return rc;
+    opf::VerifyResult vr = opf::verify_plan(pr->host, m.idx.data());
+    if (!vr.ok)
+        return ctx->fail(OPF_EPLAN, "plan property " + std::to_string(vr.property) + ": " + vr.message);
+    pr->map_version = m.version;
+    auto old = ctx->plans.find(map);
+    if (old != ctx->plans.end()) {
+        if (ctx->device >= 0) {
+            (void)hipSetDevice(ctx->device);
+            (void)hipDeviceSynchronize();
+        }
+        free_plan(ctx, *old->second);
+        ctx->plans.erase(old);
+    }
+    if (ctx->device >= 0) {
+        rc = upload_plan(ctx, *pr);
+        if (rc) return rc;
+    }
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    ctx->sets[m.from].plan_map = map;
+    ctx->sets[m.to].plan_map = map;
+    if (info) {
+        const opf::Plan &P = pr->host;
+        info->nblocks = P.nblocks();
+        info->nblock_colours = P.nblock_colours;
+        info->max_elem_colours = P.max_elem_colours;
+        info->mean_elem_colours = P.mean_elem_colours;
+        info->sum_unique = (int64_t)P.uniq.size();
+        info->max_unique = P.max_unique;
+        info->min_blocks_per_colour = P.min_blocks_per_colour;
+        info->bandwidth_before = P.bandwidth_before;
+        info->bandwidth_after = P.bandwidth_after;
+        info->plan_seconds = secs;
+        info->device_bytes = pr->device_bytes;
+    }
+    ctx->plans[map] = std::move(pr);
+    return OPF_OK;
+}
+
+int opf_get_perm(const opf_ctx *ctx, opf_set s, int32_t *new_of_old)
+{
+    if (!ctx || !new_of_old || !ctx->set_ok(s)) return OPF_EINVAL;
+    const SetRec &sr = ctx->sets[s];
+    if (sr.plan_map < 0) {
+        for (int64_t i = 0; i < sr.size; ++i) new_of_old[i] = (int32_t)i;
+        return OPF_OK;
+    }
+    auto it = ctx->plans.find(sr.plan_map);
+    if (it == ctx->plans.end()) return OPF_ESTATE;
+    const MapRec &m = ctx->maps[sr.plan_map];
+    const std::vector<int32_t> &p = (s == m.to) ? it->second->host.node_new : it->second->host.edge_new;
+    std::memcpy(new_of_old, p.data(), p.size() * sizeof(int32_t));
+    return OPF_OK;
+}
+
+int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out)
+{
+    if (!ctx || !out || !ctx->map_ok(map)) return OPF_EINVAL;
+    auto it = ctx->plans.find(map);
+    if (it == ctx->plans.end()) return OPF_ESTATE;
+    const opf::Plan &P = it->second->host;
+    out->nnodes = P.N;
+    out->nedges = P.E;
+    out->nblocks = P.nblocks();
+    out->nblock_colours = P.nblock_colours;
+    out->block_size = P.block_size;
+    out->e2n = P.e2n.data();
+    out->block_offsets = P.block_off.data();
+    out->block_colour = P.block_colour.data();
+    out->colour_blocks = P.colour_blocks.data();
+    out->colour_offsets = P.colour_off.data();
+    out->elem_colour = P.ecol.data();
+    out->block_ncolours = P.block_ncol.data();
+    out->unique_offsets = P.uniq_off.data();
+    out->unique_nodes = P.uniq.data();
+    out->local_idx = P.lidx.data();
+    return OPF_OK;
+}
+
+int opf_plan_verify(const opf_ctx *ctx, opf_map map, opf_plan_report *report)
+{
+    if (!ctx || !ctx->map_ok(map)) return OPF_EINVAL;
+    auto it = ctx->plans.find(map);
+    if (it == ctx->plans.end()) return OPF_ESTATE;
+    opf::VerifyResult vr = opf::verify_plan(it->second->host, ctx->maps[map].idx.data());
+    if (report) {
+        report->ok = vr.ok ? 1 : 0;
+        report->property = vr.property;
+        report->where = vr.where;
+        std::snprintf(report->message, sizeof report->message, "%s", vr.message.c_str());
+    }
+    return vr.ok ? OPF_OK : OPF_EPLAN;
+}
+
+int opf_decl_dat(opf_ctx *ctx, opf_set s, int dim, int type, void *dev_ptr, int64_t ld,
+                 const char *name, opf_dat *out)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (!out || !ctx->set_ok(s)) return ctx->fail(OPF_EINVAL, "invalid set handle or out");
+    if (dim < 1) return ctx->fail(OPF_EINVAL, "dat dimension must be >= 1");
+    if (type != OPF_F64 && type != OPF_F32) return ctx->fail(OPF_ETYPE, "unknown dat type");
+    if (!dev_ptr && ctx->device >= 0) return ctx->fail(OPF_EINVAL, "NULL device pointer");
+    if (ld < ctx->sets[s].size) return ctx->fail(OPF_ESIZE, "leading dimension below the set size");
+    DatRec d;
+    d.set = s;
+    d.dim = dim;
+    d.type = type;
+    d.ptr = dev_ptr;
+    d.ld = ld;
+    d.name = name ? name : "";
+    ctx->dats.push_back(d);
+    *out = (opf_dat)ctx->dats.size() - 1;
+    return OPF_OK;
+}
+
+int opf_par_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args, int ngbl,
+                 const opf_gbl *gbls, int variant, void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (!ctx->set_ok(s)) return ctx->fail(OPF_EINVAL, "invalid set handle");
+    ctx->err.clear();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    switch (kernel) {
+    case OPF_K_EDGE_FLUX:
+    case OPF_K_EDGE_FLUX_ADJ:
+    case OPF_K_EDGE_SPECRAD: return edge_loop(ctx, kernel, s, nargs, args, ngbl, gbls, variant, st);
+    case OPF_K_RK_STAGE:
+    case OPF_K_DT_MIN: return direct_loop(ctx, kernel, s, nargs, args, ngbl, gbls, st);
+    default: return ctx->fail(OPF_EINVAL, "unknown kernel");
+    }
+}
+
+int opf_edge_flux(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n, opf_dat res,
+                  double gamma, int variant, void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (!ctx->dat_ok(q) || !ctx->dat_ok(n) || !ctx->dat_ok(res))
+        return ctx->fail(OPF_EINVAL, "invalid dat handle");
+    const int T = ctx->dats[q].type, TN = ctx->dats[n].type;
+    const opf_arg a[5] = {{q, 0, e2n, 6, T, OPF_READ},
+                          {q, 1, e2n, 6, T, OPF_READ},
+                          {n, -1, OPF_ID, 3, TN, OPF_READ},
+                          {res, 0, e2n, 6, OPF_F64, OPF_INC},
+                          {res, 1, e2n, 6, OPF_F64, OPF_INC}};
+    const opf_gbl g[1] = {{&gamma, 1, OPF_F64, OPF_READ, 0}};
+    return opf_par_loop(ctx, OPF_K_EDGE_FLUX, edges, 5, a, 1, g, variant, stream);
+}
+
+int opf_edge_flux_adjoint(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
+                          opf_dat rbar, opf_dat qbar, opf_dat nbar, double gamma, int variant,
+                          void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (!ctx->dat_ok(q) || !ctx->dat_ok(n)) return ctx->fail(OPF_EINVAL, "invalid dat handle");
+    const int T = ctx->dats[q].type, TN = ctx->dats[n].type;
+    const opf_arg a[8] = {{q, 0, e2n, 6, T, OPF_READ},          {q, 1, e2n, 6, T, OPF_READ},
+                          {n, -1, OPF_ID, 3, TN, OPF_READ},       {rbar, 0, e2n, 6, OPF_F64, OPF_READ},
+                          {rbar, 1, e2n, 6, OPF_F64, OPF_READ},   {qbar, 0, e2n, 6, OPF_F64, OPF_INC},
+                          {qbar, 1, e2n, 6, OPF_F64, OPF_INC},    {nbar, -1, OPF_ID, 3, OPF_F64, OPF_WRITE}};
+    const opf_gbl g[1] = {{&gamma, 1, OPF_F64, OPF_READ, 0}};
+    return opf_par_loop(ctx, OPF_K_EDGE_FLUX_ADJ, edges, 8, a, 1, g, variant, stream);
+}
+
+int opf_edge_specrad(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n, opf_dat lam,
+                     double gamma, int variant, void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (!ctx->dat_ok(q) || !ctx->dat_ok(n)) return ctx->fail(OPF_EINVAL, "invalid dat handle");
+    const int T = ctx->dats[q].type, TN = ctx->dats[n].type;
+    const opf_arg a[5] = {{q, 0, e2n, 6, T, OPF_READ},
+                          {q, 1, e2n, 6, T, OPF_READ},
+                          {n, -1, OPF_ID, 3, TN, OPF_READ},
+                          {lam, 0, e2n, 1, OPF_F64, OPF_INC},
+                          {lam, 1, e2n, 1, OPF_F64, OPF_INC}};
+    const opf_gbl g[1] = {{&gamma, 1, OPF_F64, OPF_READ, 0}};
+    return opf_par_loop(ctx, OPF_K_EDGE_SPECRAD, edges, 5, a, 1, g, variant, stream);
+}
+
+int opf_rk_stage(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol, opf_dat q,
+                 double alpha_dt, double *ss_dev, void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (!ctx->dat_ok(q0)) return ctx->fail(OPF_EINVAL, "invalid dat handle");
+    const int T = ctx->dats[q0].type;
+    const opf_arg a[4] = {{q0, -1, OPF_ID, 6, T, OPF_READ},
+                          {res, -1, OPF_ID, 6, OPF_F64, OPF_RW},
+                          {vol, -1, OPF_ID, 1, OPF_F64, OPF_READ},
+                          {q, -1, OPF_ID, 6, T, OPF_WRITE}};
+    const opf_gbl g[2] = {{&alpha_dt, 1, OPF_F64, OPF_READ, 0}, {ss_dev, 6, OPF_F64, OPF_INC, 1}};
+    return opf_par_loop(ctx, OPF_K_RK_STAGE, nodes, 4, a, 2, g, OPF_V_COLOURED, stream);
+}
+
+int opf_dt_min(opf_ctx *ctx, opf_set nodes, opf_dat vol, opf_dat lam, double cfl, double *dt_dev,
+               void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    const opf_arg a[2] = {{vol, -1, OPF_ID, 1, OPF_F64, OPF_READ}, {lam, -1, OPF_ID, 1, OPF_F64, OPF_READ}};
+    const opf_gbl g[2] = {{&cfl, 1, OPF_F64, OPF_READ, 0}, {dt_dev, 1, OPF_F64, OPF_MIN, 1}};
+    return opf_par_loop(ctx, OPF_K_DT_MIN, nodes, 2, a, 2, g, OPF_V_COLOURED, stream);
+}
+
+int opf_sync(opf_ctx *ctx, void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (ctx->device < 0) return ctx->fail(OPF_EDEVICE, "host-only context");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    return e == hipSuccess ? OPF_OK : hip_fail(ctx, e, "stream synchronise");
+}
+
+int opf_check_finite(opf_ctx *ctx, const double *dev_ptr, int n, void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (!dev_ptr || n < 1 || n > 4096) return ctx->fail(OPF_EINVAL, "bad pointer or count");
+    if (ctx->device < 0) return ctx->fail(OPF_EDEVICE, "host-only context");
+    std::vector<double> h(n);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(h.data(), dev_ptr, n * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reading the reduction");
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(h[k]))
+            return ctx->fail(OPF_ENONFINITE, "value " + std::to_string(k) + " is not finite");
+    return OPF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,501 @@
+// planner.cpp -- host execution plan of an edge -> node map (see planner.hpp).
+#include "planner.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <numeric>
+
+#include "opflux.h"
+
+namespace opf {
+namespace {
+
+struct Graph {
+    std::vector<int64_t> off;
+    std::vector<int32_t> adj;
+};
+
+// Symmetric node adjacency; each list ordered by (degree, id) as Cuthill-McKee
+// visits neighbours.  A repeated edge gives a repeated neighbour, which the
+// traversals below tolerate.
+Graph node_graph(int64_t N, int64_t E, const int32_t *e2n)
+{
+    Graph g;
+    g.off.assign(N + 1, 0);
+    for (int64_t e = 0; e < E; ++e) {
+        ++g.off[e2n[2 * e] + 1];
+        ++g.off[e2n[2 * e + 1] + 1];
+    }
+    for (int64_t i = 0; i < N; ++i) g.off[i + 1] += g.off[i];
+    g.adj.resize(g.off[N]);
+    std::vector<int64_t> fill(g.off.begin(), g.off.end() - 1);
+    for (int64_t e = 0; e < E; ++e) {
+        int32_t a = e2n[2 * e], b = e2n[2 * e + 1];
+        g.adj[fill[a]++] = b;
+        g.adj[fill[b]++] = a;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        auto b = g.adj.begin() + g.off[i], en = g.adj.begin() + g.off[i + 1];
+        std::sort(b, en, [&](int32_t x, int32_t y) {
+            int64_t dx = g.off[x + 1] - g.off[x], dy = g.off[y + 1] - g.off[y];
+            return dx != dy ? dx < dy : x < y;
+        });
+    }
+    return g;
+}
+
+// BFS from r; returns the number of levels and fills `last` with the last level.
+int bfs_levels(const Graph &g, int32_t r, std::vector<int32_t> &level, std::vector<int32_t> &queue,
+               std::vector<int32_t> &touched, std::vector<int32_t> &last)
+{
+    for (int32_t t : touched) level[t] = -1;
+    touched.clear();
+    queue.clear();
+    queue.push_back(r);
+    level[r] = 0;
+    touched.push_back(r);
+    int maxl = 0;
+    for (size_t h = 0; h < queue.size(); ++h) {
+        int32_t v = queue[h];
+        for (int64_t k = g.off[v]; k < g.off[v + 1]; ++k) {
+            int32_t w = g.adj[k];
+            if (level[w] < 0) {
+                level[w] = level[v] + 1;
+                maxl = std::max(maxl, level[w]);
+                queue.push_back(w);
+                touched.push_back(w);
+            }
+        }
+    }
+    last.clear();
+    for (int32_t v : queue)
+        if (level[v] == maxl) last.push_back(v);
+    return maxl + 1;
+}
+
+// Reverse Cuthill-McKee with a pseudo-peripheral start per component
+// (George and Liu's iteration: restart from a minimum-degree node of the last
+// BFS level while the eccentricity grows).  new_of_old[i] = RCM label.
+void rcm(int64_t N, const Graph &g, std::vector<int32_t> &new_of_old)
+{
+    std::vector<int32_t> level(N, -1), queue, touched, last;
+    std::vector<char> done(N, 0);
+    std::vector<int32_t> order;
+    order.reserve(N);
+    queue.reserve(N);
+    touched.reserve(N);
+    auto deg = [&](int32_t v) { return g.off[v + 1] - g.off[v]; };
+    for (int64_t s = 0; s < N; ++s) {
+        if (done[s]) continue;
+        int32_t r = (int32_t)s;
+        int ecc = bfs_levels(g, r, level, queue, touched, last);
+        for (int it = 0; it < 16; ++it) {
+            int32_t x = last[0];
+            for (int32_t v : last)
+                if (deg(v) < deg(x) || (deg(v) == deg(x) && v < x)) x = v;
+            int e2 = bfs_levels(g, x, level, queue, touched, last);
+            if (e2 <= ecc) break;
+            ecc = e2;
+            r = x;
+        }
+        size_t head = order.size();
+        order.push_back(r);
+        done[r] = 1;
+        for (size_t h = head; h < order.size(); ++h) {
+            int32_t v = order[h];
+            for (int64_t k = g.off[v]; k < g.off[v + 1]; ++k) {
+                int32_t w = g.adj[k];
+                if (!done[w]) {
+                    done[w] = 1;
+                    order.push_back(w);
+                }
+            }
+        }
+    }
+    new_of_old.assign(N, 0);
+    for (int64_t k = 0; k < N; ++k) new_of_old[order[k]] = (int32_t)(N - 1 - k);
+}
+
+inline uint64_t spread3(uint64_t x)  // 21 bits -> every third bit
+{
+    x &= 0x1fffffULL;
+    x = (x | x << 32) & 0x1f00000000ffffULL;
+    x = (x | x << 16) & 0x1f0000ff0000ffULL;
+    x = (x | x << 8) & 0x100f00f00f00f00fULL;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+    x = (x | x << 2) & 0x1249249249249249ULL;
+    return x;
+}
+
+void morton(int64_t N, const double *xyz, std::vector<int32_t> &new_of_old)
+{
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = hi[d] = xyz[d * N];
+        for (int64_t i = 0; i < N; ++i) {
+            lo[d] = std::min(lo[d], xyz[d * N + i]);
+            hi[d] = std::max(hi[d], xyz[d * N + i]);
+        }
+    }
+    std::vector<uint64_t> key(N);
+    for (int64_t i = 0; i < N; ++i) {
+        uint64_t k = 0;
+        for (int d = 0; d < 3; ++d) {
+            double span = hi[d] > lo[d] ? hi[d] - lo[d] : 1.0;
+            double t = (xyz[d * N + i] - lo[d]) / span;
+            uint64_t c = (uint64_t)std::min(2097151.0, std::max(0.0, t * 2097151.0));
+            k |= spread3(c) << d;
+        }
+        key[i] = k;
+    }
+    std::vector<int32_t> order(N);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    new_of_old.assign(N, 0);
+    for (int64_t k = 0; k < N; ++k) new_of_old[order[k]] = (int32_t)k;
+}
+
+inline int lowest_free(uint64_t used) { return used == ~0ULL ? -1 : __builtin_ctzll(~used); }
+
+}  // namespace
+
+int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions &opt, Plan &P,
+               std::string &err)
+{
+    const int BS = opt.block_size;
+    if (BS < 64 || BS > 2048 || (BS & (BS - 1))) {
+        err = "block_size must be a power of two in [64, 2048]";
+        return OPF_EINVAL;
+    }
+    if (opt.renumber < 0 || opt.renumber > 2) {
+        err = "unknown renumbering method";
+        return OPF_EINVAL;
+    }
+    if (opt.renumber == 2 && !opt.coords) {
+        err = "Morton renumbering needs node coordinates";
+        return OPF_EINVAL;
+    }
+    if (E < 1 || N < 2) {
+        err = "the map needs at least one edge and two nodes";
+        return OPF_EINVAL;
+    }
+    for (int64_t e = 0; e < E; ++e)
+        if (e2n_user[2 * e] == e2n_user[2 * e + 1]) {
+            err = "edge " + std::to_string(e) + " joins a node to itself";
+            return OPF_EINVAL;
+        }
+    P = Plan();
+    P.N = N;
+    P.E = E;
+    P.block_size = BS;
+
+    auto t0 = std::chrono::steady_clock::now();
+    auto lap = [&](int k) {
+        auto t1 = std::chrono::steady_clock::now();
+        P.phase_seconds[k] = std::chrono::duration<double>(t1 - t0).count();
+        t0 = t1;
+    };
+    // (1) node renumbering
+    if (opt.renumber == 1) {
+        Graph g = node_graph(N, E, e2n_user);
+        rcm(N, g, P.node_new);
+    } else if (opt.renumber == 2) {
+        morton(N, opt.coords, P.node_new);
+    } else {
+        P.node_new.resize(N);
+        std::iota(P.node_new.begin(), P.node_new.end(), 0);
+    }
+
+    lap(0);
+    // (2) relabel and order edges by (min, max) internal node: counting sort by
+    // the smaller endpoint, then by the larger one inside each bucket.
+    std::vector<int64_t> cnt(N + 1, 0);
+    for (int64_t e = 0; e < E; ++e) {
+        int32_t a = P.node_new[e2n_user[2 * e]], b = P.node_new[e2n_user[2 * e + 1]];
+        ++cnt[std::min(a, b) + 1];
+        P.bandwidth_before = std::max<int64_t>(
+            P.bandwidth_before, std::llabs((int64_t)e2n_user[2 * e] - e2n_user[2 * e + 1]));
+        P.bandwidth_after = std::max<int64_t>(P.bandwidth_after, std::llabs((int64_t)a - b));
+    }
+    for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> order(E);  // order[k] = user edge at internal position k
+    {
+        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int64_t e = 0; e < E; ++e) {
+            int32_t a = P.node_new[e2n_user[2 * e]], b = P.node_new[e2n_user[2 * e + 1]];
+            order[fill[std::min(a, b)]++] = (int32_t)e;
+        }
+        auto hi = [&](int32_t e) {
+            return std::max(P.node_new[e2n_user[2 * e]], P.node_new[e2n_user[2 * e + 1]]);
+        };
+        for (int64_t i = 0; i < N; ++i)
+            std::sort(order.begin() + cnt[i], order.begin() + cnt[i + 1],
+                      [&](int32_t x, int32_t y) { return hi(x) != hi(y) ? hi(x) < hi(y) : x < y; });
+    }
+    P.e2n.resize(2 * E);
+    for (int64_t k = 0; k < E; ++k) {
+        P.e2n[2 * k] = P.node_new[e2n_user[2 * order[k]]];
+        P.e2n[2 * k + 1] = P.node_new[e2n_user[2 * order[k] + 1]];
+    }
+
+    lap(1);
+    // (3) mini-partitions of consecutive edges
+    const int64_t nb = (E + BS - 1) / BS;
+    P.block_off.resize(nb + 1);
+    for (int64_t b = 0; b <= nb; ++b) P.block_off[b] = std::min<int64_t>(b * BS, E);
+
+    // (5) edge colours inside each partition; (6) distinct nodes and local indices
+    P.ecol.assign(E, 0);
+    P.block_ncol.assign(nb, 0);
+    P.lidx.resize(2 * E);
+    P.uniq_off.assign(nb + 1, 0);
+    P.uniq.reserve((size_t)(E / 2));
+    std::vector<int32_t> loc(N, -1);
+    std::vector<uint64_t> lmask;
+    std::vector<int32_t> nodes;
+    int64_t ncol_sum = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t e0 = P.block_off[b], e1 = P.block_off[b + 1];
+        nodes.clear();
+        for (int64_t k = e0; k < e1; ++k) {
+            nodes.push_back(P.e2n[2 * k]);
+            nodes.push_back(P.e2n[2 * k + 1]);
+        }
+        std::sort(nodes.begin(), nodes.end());
+        nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+        for (size_t u = 0; u < nodes.size(); ++u) loc[nodes[u]] = (int32_t)u;
+        lmask.assign(nodes.size(), 0);
+        int ncol = 0;
+        for (int64_t k = e0; k < e1; ++k) {
+            int32_t li = loc[P.e2n[2 * k]], lj = loc[P.e2n[2 * k + 1]];
+            P.lidx[2 * k] = (uint16_t)li;
+            P.lidx[2 * k + 1] = (uint16_t)lj;
+            int c = lowest_free(lmask[li] | lmask[lj]);
+            if (c < 0 || c > 255) {
+                err = "more than 64 edge colours in partition " + std::to_string(b);
+                return OPF_EPLAN;
+            }
+            lmask[li] |= 1ULL << c;
+            lmask[lj] |= 1ULL << c;
+            P.ecol[k] = (uint8_t)c;
+            ncol = std::max(ncol, c + 1);
+        }
+        for (int32_t v : nodes) loc[v] = -1;
+        P.block_ncol[b] = ncol;
+        ncol_sum += ncol;
+        P.max_elem_colours = std::max(P.max_elem_colours, ncol);
+        P.uniq.insert(P.uniq.end(), nodes.begin(), nodes.end());
+        P.uniq_off[b + 1] = (int64_t)P.uniq.size();
+        P.max_unique = std::max<int32_t>(P.max_unique, (int32_t)nodes.size());
+        if (nodes.size() > 65535) {
+            err = "partition with more than 65535 distinct nodes";
+            return OPF_EPLAN;
+        }
+    }
+    P.mean_elem_colours = (double)ncol_sum / (double)nb;
+
+    // (7) optional: order each partition's edges by colour (stable)
+    if (opt.colour_sort) {
+        std::vector<int32_t> idx;
+        std::vector<int32_t> t_e2n, t_order;
+        std::vector<uint16_t> t_lidx;
+        std::vector<uint8_t> t_col;
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t e0 = P.block_off[b], n = P.block_off[b + 1] - e0;
+            idx.resize(n);
+            std::iota(idx.begin(), idx.end(), 0);
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int32_t x, int32_t y) { return P.ecol[e0 + x] < P.ecol[e0 + y]; });
+            t_e2n.assign(P.e2n.begin() + 2 * e0, P.e2n.begin() + 2 * (e0 + n));
+            t_lidx.assign(P.lidx.begin() + 2 * e0, P.lidx.begin() + 2 * (e0 + n));
+            t_col.assign(P.ecol.begin() + e0, P.ecol.begin() + e0 + n);
+            t_order.assign(order.begin() + e0, order.begin() + e0 + n);
+            for (int64_t k = 0; k < n; ++k) {
+                int32_t s = idx[k];
+                P.e2n[2 * (e0 + k)] = t_e2n[2 * s];
+                P.e2n[2 * (e0 + k) + 1] = t_e2n[2 * s + 1];
+                P.lidx[2 * (e0 + k)] = t_lidx[2 * s];
+                P.lidx[2 * (e0 + k) + 1] = t_lidx[2 * s + 1];
+                P.ecol[e0 + k] = t_col[s];
+                order[e0 + k] = t_order[s];
+            }
+        }
+    }
+    P.edge_new.resize(E);
+    for (int64_t k = 0; k < E; ++k) P.edge_new[order[k]] = (int32_t)k;
+    lap(2);
+
+    // (4) colour the partitions greedily: lowest colour unused by any partition
+    // already sharing one of its nodes.  Colours are handed out in rounds of 64
+    // (one bit mask per node per round); a partition that finds all 64 colours
+    // of a round taken waits for the next round.
+    {
+        std::vector<uint64_t> nmask(N, 0);
+        P.block_colour.assign(nb, -1);
+        std::vector<int32_t> todo(nb), next;
+        std::iota(todo.begin(), todo.end(), 0);
+        int base = 0, nc = 0;
+        while (!todo.empty()) {
+            if (base >= kMaxBlockColours) {
+                err = "more than " + std::to_string(kMaxBlockColours) + " partition colours";
+                return OPF_EPLAN;
+            }
+            std::fill(nmask.begin(), nmask.end(), 0);
+            next.clear();
+            for (int32_t b : todo) {
+                uint64_t used = 0;
+                for (int64_t u = P.uniq_off[b]; u < P.uniq_off[b + 1]; ++u) used |= nmask[P.uniq[u]];
+                int c = lowest_free(used);
+                if (c < 0) {
+                    next.push_back(b);
+                    continue;
+                }
+                for (int64_t u = P.uniq_off[b]; u < P.uniq_off[b + 1]; ++u)
+                    nmask[P.uniq[u]] |= 1ULL << c;
+                P.block_colour[b] = base + c;
+                nc = std::max(nc, base + c + 1);
+            }
+            todo.swap(next);
+            base += 64;
+        }
+        P.nblock_colours = nc;
+        P.colour_off.assign(nc + 1, 0);
+        for (int64_t b = 0; b < nb; ++b) ++P.colour_off[P.block_colour[b] + 1];
+        for (int c = 0; c < nc; ++c) P.colour_off[c + 1] += P.colour_off[c];
+        P.colour_blocks.resize(nb);
+        std::vector<int64_t> fill(P.colour_off.begin(), P.colour_off.end() - 1);
+        for (int64_t b = 0; b < nb; ++b) P.colour_blocks[fill[P.block_colour[b]]++] = (int32_t)b;
+        // a round may leave colours unused; drop them so every colour is non-empty
+        std::vector<int64_t> off2(1, 0);
+        std::vector<int32_t> remap(nc, -1);
+        for (int c = 0; c < nc; ++c)
+            if (P.colour_off[c + 1] > P.colour_off[c]) {
+                remap[c] = (int32_t)off2.size() - 1;
+                off2.push_back(P.colour_off[c + 1]);
+            }
+        for (int64_t b = 0; b < nb; ++b) P.block_colour[b] = remap[P.block_colour[b]];
+        P.colour_off.swap(off2);
+        P.nblock_colours = (int32_t)P.colour_off.size() - 1;
+        nc = P.nblock_colours;
+        P.min_blocks_per_colour = (int32_t)nb;
+        for (int c = 0; c < nc; ++c)
+            P.min_blocks_per_colour = std::min<int32_t>(
+                P.min_blocks_per_colour, (int32_t)(P.colour_off[c + 1] - P.colour_off[c]));
+    }
+    lap(3);
+    return OPF_OK;
+}
+
+VerifyResult verify_plan(const Plan &P, const int32_t *e2n_user)
+{
+    VerifyResult r;
+    auto fail = [&](int prop, int64_t where, const std::string &msg) {
+        r.ok = false;
+        r.property = prop;
+        r.where = where;
+        r.message = msg;
+        return r;
+    };
+    const int64_t N = P.N, E = P.E, nb = P.nblocks();
+    // (1) node relabelling is a bijection
+    if ((int64_t)P.node_new.size() != N) return fail(1, -1, "node relabelling has the wrong size");
+    {
+        std::vector<char> seen(N, 0);
+        for (int64_t i = 0; i < N; ++i) {
+            int32_t v = P.node_new[i];
+            if (v < 0 || v >= N || seen[v]) return fail(1, i, "node relabelling is not a bijection");
+            seen[v] = 1;
+        }
+    }
+    // (2) edge reordering is a bijection that keeps endpoints and orientation
+    if ((int64_t)P.edge_new.size() != E || (int64_t)P.e2n.size() != 2 * E)
+        return fail(2, -1, "edge arrays have the wrong size");
+    {
+        std::vector<char> seen(E, 0);
+        for (int64_t e = 0; e < E; ++e) {
+            int32_t k = P.edge_new[e];
+            if (k < 0 || k >= E || seen[k]) return fail(2, e, "edge reordering is not a bijection");
+            seen[k] = 1;
+            if (P.e2n[2 * k] != P.node_new[e2n_user[2 * e]] ||
+                P.e2n[2 * k + 1] != P.node_new[e2n_user[2 * e + 1]])
+                return fail(2, e, "internal map does not match the relabelled user map");
+        }
+    }
+    // (5) partitions: contiguous, cover [0,E), at most block_size edges, grouped by colour
+    if ((int64_t)P.block_off.size() != nb + 1 || P.block_off[0] != 0 || P.block_off[nb] != E)
+        return fail(5, -1, "partition offsets do not cover the edge set");
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t n = P.block_off[b + 1] - P.block_off[b];
+        if (n <= 0 || n > P.block_size) return fail(5, b, "partition size out of range");
+    }
+    if ((int64_t)P.colour_off.size() != P.nblock_colours + 1 || P.colour_off[0] != 0 ||
+        P.colour_off[P.nblock_colours] != nb || (int64_t)P.colour_blocks.size() != nb)
+        return fail(5, -1, "colour offsets do not cover the partitions");
+    {
+        std::vector<char> seen(nb, 0);
+        for (int c = 0; c < P.nblock_colours; ++c) {
+            if (P.colour_off[c + 1] <= P.colour_off[c]) return fail(5, c, "empty partition colour");
+            for (int64_t k = P.colour_off[c]; k < P.colour_off[c + 1]; ++k) {
+                int32_t b = P.colour_blocks[k];
+                if (b < 0 || b >= nb || seen[b] || P.block_colour[b] != c)
+                    return fail(5, k, "partition listed under the wrong colour or twice");
+                seen[b] = 1;
+            }
+        }
+    }
+    // (7) colour counts fit their types
+    if (P.nblock_colours < 1 || P.nblock_colours > kMaxBlockColours)
+        return fail(7, -1, "partition colour count");
+    for (int64_t b = 0; b < nb; ++b)
+        if (P.block_ncol[b] < 1 || P.block_ncol[b] > 64) return fail(7, b, "edge colour count");
+    // (6) local indices resolve to the map's nodes; unique lists sorted and distinct
+    if ((int64_t)P.uniq_off.size() != nb + 1 || P.uniq_off[nb] != (int64_t)P.uniq.size())
+        return fail(6, -1, "distinct-node offsets do not match the lists");
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t u0 = P.uniq_off[b], nu = P.uniq_off[b + 1] - u0;
+        if (nu < 1 || nu > 65535) return fail(7, b, "distinct-node count out of range");
+        for (int64_t u = 1; u < nu; ++u)
+            if (P.uniq[u0 + u] <= P.uniq[u0 + u - 1]) return fail(6, b, "distinct nodes not sorted");
+        for (int64_t k = P.block_off[b]; k < P.block_off[b + 1]; ++k)
+            for (int s = 0; s < 2; ++s) {
+                int64_t l = P.lidx[2 * k + s];
+                if (l >= nu || P.uniq[u0 + l] != P.e2n[2 * k + s])
+                    return fail(6, k, "local index does not resolve to the map's node");
+            }
+        for (int64_t k = P.block_off[b]; k < P.block_off[b + 1]; ++k)
+            if (P.ecol[k] >= P.block_ncol[b]) return fail(7, k, "edge colour above the count");
+    }
+    // (3) partitions of one colour share no node
+    {
+        std::vector<int32_t> stamp(N, -1);
+        for (int c = 0; c < P.nblock_colours; ++c)
+            for (int64_t k = P.colour_off[c]; k < P.colour_off[c + 1]; ++k) {
+                const int32_t b = P.colour_blocks[k];
+                for (int64_t u = P.uniq_off[b]; u < P.uniq_off[b + 1]; ++u) {
+                    const int32_t v = P.uniq[u];
+                    if (stamp[v] == c) return fail(3, b, "two partitions of one colour share a node");
+                    stamp[v] = c;
+                }
+            }
+    }
+    // (4) inside a partition, edges of one colour share no node
+    {
+        std::vector<uint64_t> lm;
+        for (int64_t b = 0; b < nb; ++b) {
+            lm.assign(P.uniq_off[b + 1] - P.uniq_off[b], 0);
+            for (int64_t k = P.block_off[b]; k < P.block_off[b + 1]; ++k) {
+                uint64_t bit = 1ULL << P.ecol[k];
+                int li = P.lidx[2 * k], lj = P.lidx[2 * k + 1];
+                if ((lm[li] & bit) || (lm[lj] & bit) || li == lj)
+                    return fail(4, k, "two edges of one colour share a node");
+                lm[li] |= bit;
+                lm[lj] |= bit;
+            }
+        }
+    }
+    return r;
+}
+
+}  // namespace opf

@@ -1,0 +1,66 @@
+// planner.hpp -- host execution plan of an edge -> node map.
+//
+// Sec. 4 (renumbering for cache locality, GPS in the paper; RCM or a Morton
+// curve here) and Sec. 4.1 (mini-partitions of the execution set, a colouring
+// of the partitions so that same-colour partitions share no node, and a
+// colouring of the edges inside each partition for one-edge-per-thread
+// execution; the plan is built once and reused).  Sec. 4.1.2: optional
+// ordering of each partition's edges by colour.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace opf {
+
+constexpr int kMaxBlockColours = 1024;
+
+struct PlanOptions {
+    int renumber = 1;  // 0 none, 1 RCM, 2 Morton
+    int block_size = 512;
+    int colour_sort = 0;
+    const double *coords = nullptr;  // SoA 3 x N
+};
+
+struct Plan {
+    int64_t N = 0, E = 0;
+    int block_size = 0;
+    std::vector<int32_t> node_new;  // [N] internal label of user node
+    std::vector<int32_t> edge_new;  // [E] internal position of user edge
+    std::vector<int32_t> e2n;       // [2E] internal map in internal edge order
+    std::vector<int64_t> block_off; // [nb+1]
+    std::vector<int32_t> block_colour;
+    std::vector<int32_t> colour_blocks;
+    std::vector<int64_t> colour_off;
+    std::vector<uint8_t> ecol;       // [E]
+    std::vector<int32_t> block_ncol; // [nb]
+    std::vector<int64_t> uniq_off;   // [nb+1]
+    std::vector<int32_t> uniq;       // sum U_b
+    std::vector<uint16_t> lidx;      // [2E]
+    int32_t nblock_colours = 0;
+    int32_t max_elem_colours = 0;
+    double mean_elem_colours = 0.0;
+    int32_t max_unique = 0;
+    int32_t min_blocks_per_colour = 0;
+    int64_t bandwidth_before = 0, bandwidth_after = 0;
+    double phase_seconds[4] = {0, 0, 0, 0};  // renumber, edge order, partitions, colours
+    int64_t nblocks() const { return (int64_t)block_colour.size(); }
+};
+
+// Builds a plan of the map e2n (2E entries, 0-based, user numbering).
+// Returns 0, or a negative opf_status with `err` set.
+int build_plan(int64_t N, int64_t E, const int32_t *e2n, const PlanOptions &opt, Plan &plan,
+               std::string &err);
+
+struct VerifyResult {
+    bool ok = true;
+    int property = 0;
+    int64_t where = -1;
+    std::string message;
+};
+
+// Bit-exact check of the plan's properties (1..7) against the user map.
+VerifyResult verify_plan(const Plan &plan, const int32_t *e2n_user);
+
+}  // namespace opf

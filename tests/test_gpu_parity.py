@@ -1,0 +1,214 @@
+"""GPU parity of the edge-flux path against the FP64 oracle, through the C ABI.
+
+Tolerances (normwise per variable, max |y - y*| / max |y*|):
+  FP64 residual, stage update, sum of squares, time step, adjoint: 1e-12
+  FP32-storage form from identical (FP32-rounded) inputs: 1e-5
+The coloured variant must also be bitwise reproducible run to run.
+"""
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+import paper_1403_7209_amd as pk
+from tests._util import normwise, report
+from tests.golden.load import flux_hand_cases
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL64, TOL32 = 1e-12, 1e-5
+
+
+def problem(m, q, fp32=False, renumber="rcm", block_size=512, colour_sort=False):
+    ctx = pk.Context(DEV)
+    coords = m.xyz if renumber == "morton" else None
+    return pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, fp32=fp32, renumber=renumber,
+                          block_size=block_size, colour_sort=colour_sort, coords=coords)
+
+
+def gpu_residual(p, variant):
+    res = torch.zeros((6, p.N), dtype=torch.float64, device=DEV)
+    p.residual(p.qa, res, variant)
+    p.ctx.sync()
+    return p.nodes_out(res)
+
+
+@pytest.mark.parametrize("variant", [pk.COLOURED, pk.ATOMIC], ids=["coloured", "atomic"])
+@pytest.mark.parametrize("case", flux_hand_cases(), ids=lambda c: c[0])
+def test_two_node_hand_cases(case, variant):
+    name, qi, qj, n, F = case
+    print(f"[two-node {name}]", flush=True)
+    ctx = pk.Context(DEV)
+    p = pk.FluxProblem(ctx, np.array([[0, 1]], np.int32), n.reshape(3, 1), np.ones(2),
+                       np.stack([qi, qj], 1), block_size=64)
+    res = gpu_residual(p, variant)
+    assert np.abs(res[:, 0] - F).max() <= 1e-14 * np.abs(F).max()
+    assert np.array_equal(res[:, 1], -res[:, 0])
+
+
+MESHES = {
+    "kuhn3": dict(n=3, split=0, jitter=0.2),
+    "mix4": dict(n=4, split=1, jitter=0.25),
+    "mix8": dict(n=8, split=1, jitter=0.25),
+    "A": meshgen.CONFIGS["A"],
+}
+
+
+@pytest.fixture(scope="module", params=list(MESHES))
+def small(request):
+    c = MESHES[request.param]
+    m = meshgen.build_mesh(c["n"], c["split"], c["jitter"])
+    q = meshgen.state(m.N, m.perm)
+    res = oracle.residual(m.e2n, q, m.w)
+    return request.param, m, q, res
+
+
+@pytest.mark.parametrize("renumber,bs,csort", [("rcm", 512, False), ("rcm", 64, True),
+                                               ("morton", 2048, False), ("none", 256, False)])
+def test_residual_small(small, renumber, bs, csort):
+    name, m, q, ref = small
+    print(f"[residual {name} {renumber} bs={bs} sort={csort}]", flush=True)
+    p = problem(m, q, renumber=renumber, block_size=bs, colour_sort=csort)
+    for variant in (pk.COLOURED, pk.ATOMIC):
+        res = gpu_residual(p, variant)
+        assert report(f"variant {variant}", normwise(res, ref), TOL64)
+    # OP_INC accumulates into what is already there
+    res = torch.zeros((6, p.N), dtype=torch.float64, device=DEV)
+    p.residual(p.qa, res)
+    p.residual(p.qa, res)
+    p.ctx.sync()
+    assert normwise(p.nodes_out(res), 2 * ref) <= TOL64
+
+
+def test_coloured_is_bitwise_deterministic(small):
+    name, m, q, _ = small
+    p = problem(m, q)
+    a = gpu_residual(p, pk.COLOURED)
+    b = gpu_residual(p, pk.COLOURED)
+    assert a.tobytes() == b.tobytes()
+
+
+def test_rk_stage_and_norm(small):
+    name, m, q, ref = small
+    print(f"[rk stage {name}]", flush=True)
+    p = problem(m, q)
+    rng = np.random.default_rng(1)
+    res_h = ref * (1.0 + 0.1 * rng.standard_normal(ref.shape))
+    q0 = q + 0.01 * rng.standard_normal(q.shape)
+    q_ref, ss_ref = oracle.rk_stage(q0, res_h.copy(), m.vol, 0.37)
+    q0_t = p.nodes_in(q0)
+    res_t = p.nodes_in(res_h)
+    out_t = torch.empty_like(q0_t)
+    ss = torch.zeros(6, dtype=torch.float64, device=DEV)
+    p.ctx.rk_stage(p.nodes, p.dat(q0_t), p.dat(res_t), p.vol, p.dat(out_t), 0.37, ss)
+    p.ctx.sync()
+    assert report("q", normwise(p.nodes_out(out_t), q_ref), TOL64)
+    assert np.abs(ss.cpu().numpy() - ss_ref).max() <= TOL64 * np.abs(ss_ref).max()
+    assert torch.count_nonzero(res_t).item() == 0
+
+
+def test_time_step(small):
+    name, m, q, _ = small
+    p = problem(m, q)
+    dt_ref = oracle.dt(m.e2n, q, m.w, m.vol)
+    for variant in (pk.COLOURED, pk.ATOMIC):
+        dt = p.compute_dt(0.5, variant)
+        assert abs(dt - dt_ref) <= TOL64 * dt_ref
+
+
+def test_rk_iteration(small):
+    name, m, q, _ = small
+    print(f"[rk iteration {name}]", flush=True)
+    dt = oracle.dt(m.e2n, q, m.w, m.vol)
+    q_ref = q.copy()
+    ss_ref = []
+    for _ in range(2):
+        q_ref, s = oracle.rk_iteration(m.e2n, q_ref, m.w, m.vol, dt)
+        ss_ref.append(s)
+    for variant in (pk.COLOURED, pk.ATOMIC):
+        p = problem(m, q)
+        for it in range(2):
+            p.rk_iteration(dt, variant)
+            p.ctx.sync()
+            rms = p.rms()
+            assert report(f"rms it{it} v{variant}", normwise(rms, np.sqrt(ss_ref[it] / m.N)), TOL64)
+        assert report(f"q v{variant}", normwise(p.nodes_out(p.qa), q_ref), TOL64)
+
+
+def test_fp32_storage_stage(small):
+    name, m, q, _ = small
+    q32 = q.astype(np.float32).astype(np.float64)
+    w32 = m.w.astype(np.float32).astype(np.float64)
+    ref = oracle.residual(m.e2n, q32, w32)
+    p = problem(m, q, fp32=True)
+    for variant in (pk.COLOURED, pk.ATOMIC):
+        res = gpu_residual(p, variant)
+        assert report(f"fp32 residual v{variant}", normwise(res, ref), TOL32)
+    dt = oracle.dt(m.e2n, q32, w32, m.vol)
+    q1_ref, ss_ref = oracle.rk_iteration(m.e2n, q32, w32, m.vol, dt)
+    p.rk_iteration(dt)
+    p.ctx.sync()
+    assert report("fp32 state", normwise(p.nodes_out(p.qa), q1_ref), TOL32)
+    assert report("fp32 rms", normwise(p.rms(), np.sqrt(ss_ref / m.N)), TOL32)
+
+
+def test_adjoint(small):
+    name, m, q, _ = small
+    print(f"[adjoint {name}]", flush=True)
+    rbar = meshgen.normal(6 * m.N, purpose=21).reshape(6, m.N)
+    qbar_ref, wbar_ref = oracle.adjoint(m.e2n, q, m.w, rbar)
+    p = problem(m, q)
+    rb = p.nodes_in(rbar)
+    for variant in (pk.COLOURED, pk.ATOMIC):
+        qbar = torch.zeros((6, p.N), dtype=torch.float64, device=DEV)
+        nbar = torch.empty((3, p.E), dtype=torch.float64, device=DEV)
+        p.ctx.edge_flux_adjoint(p.edges, p.e2n, p.dat(p.qa), p.w, p.dat(rb), p.dat(qbar),
+                                p.dat(nbar, edges=True), p.gamma, variant)
+        p.ctx.sync()
+        assert report(f"qbar v{variant}", normwise(p.nodes_out(qbar), qbar_ref), TOL64)
+        assert report(f"nbar v{variant}", normwise(p.nodes_out(nbar, edges=True), wbar_ref), TOL64)
+
+
+def test_autograd_dot_product_and_gradcheck():
+    m = meshgen.build_mesh(3, 0, 0.2)
+    q = meshgen.state(m.N, m.perm)
+    p = problem(m, q)
+    qt = p.qa.clone().requires_grad_(True)
+    wt = p.w_t.clone().requires_grad_(True)
+    res = pk.EdgeFluxFunction.apply(p, qt, wt, pk.COLOURED)
+    rbar = torch.randn_like(res)
+    qbar, wbar = torch.autograd.grad(res, (qt, wt), rbar)
+    dq = torch.randn_like(qt)
+    dw = torch.randn_like(wt) * wt.detach().norm(dim=0)
+    jv = oracle.jvp(m.e2n, q, m.w, p.nodes_out(dq), p.nodes_out(dw, edges=True))
+    lhs = float((p.nodes_out(rbar) * jv).sum())
+    rhs = float((qbar * dq).sum() + (wbar * dw).sum())
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+    f = lambda a, b: pk.EdgeFluxFunction.apply(p, a, b, pk.COLOURED)
+    assert torch.autograd.gradcheck(f, (qt, wt), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def test_argument_checks_on_device():
+    m = meshgen.build_mesh(3, 0, 0.0)
+    q = meshgen.state(m.N, m.perm)
+    p = problem(m, q)
+    res32 = torch.zeros((6, p.N), dtype=torch.float32, device=DEV)
+    with pytest.raises(pk.OpfError) as e:
+        p.ctx.edge_flux(p.edges, p.e2n, p.dat(p.qa), p.w, p.dat(res32), 1.4)
+    assert e.value.status == pk.ETYPE
+    short = torch.zeros((6, p.N), dtype=torch.float64, device=DEV)
+    with pytest.raises(pk.OpfError) as e:  # a node dat passed where the edge weight goes
+        p.ctx.edge_flux(p.edges, p.e2n, p.dat(p.qa), p.dat(short), p.dat(short), 1.4)
+    assert e.value.status in (pk.EINVAL, pk.ESIZE)
+    ss = torch.zeros(6, dtype=torch.float64, device=DEV)
+    with pytest.raises(pk.OpfError) as e:  # q must not alias q0
+        p.ctx.rk_stage(p.nodes, p.dat(p.qa), p.res_d, p.vol, p.dat(p.qa), 0.1, ss)
+    assert e.value.status == pk.EINVAL
+    nanq = p.qa.clone()
+    nanq[0, 0] = float("nan")
+    res = torch.zeros((6, p.N), dtype=torch.float64, device=DEV)
+    p.residual(nanq, res)
+    p.ctx.rk_stage(p.nodes, p.dat(p.qa), p.dat(res), p.vol, p.dat(p.qb), 0.1, ss)
+    assert p.ctx.check_finite(ss) is False
