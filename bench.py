@@ -1,0 +1,243 @@
+"""Throughput of the edge-flux hot path on one MI355X.
+
+Workload: the periodic 160^3 box (4,096,000 nodes) split into a layered mix of
+5- and 6-tet cubes (26,624,000 edges), nodes jittered by U(-0.25h, 0.25h) and
+randomly relabelled, then renumbered by the planner.  All inputs are seeded
+and synthetic.
+
+One step = one 5-stage Runge-Kutta iteration in FP64 (5 edge-flux loops + 5
+stage updates with residual norms), the same iteration in the FP32-storage
+form, and one FP64 adjoint edge sweep: 11 edge loops over all edges.
+
+value = 11 * E / (seconds per step): edges per second over the whole step,
+inputs resident in HBM.  The roofline entry is the FP64 edge-flux loop,
+priced in algorithmic bytes (32 B per edge: map 8 + weights 24; 96 B per
+node: state read 48 + residual write 48) against 8 TB/s.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES = {  # algorithmic bytes: (per edge, per node)
+    "fp64": (32, 96),
+    "fp32": (20, 72),
+    "adjoint": (56, 144),
+    "rk64": (0, 152),
+    "rk32": (0, 104),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(mesh, q, seconds=12.0):
+    """The oracle (single thread) on a bounded sample of the same workload:
+    repeated FP64 residual passes over the full mesh until ~`seconds` elapse."""
+    import oracle
+    passes, t0 = 0, time.perf_counter()
+    res = np.zeros_like(q)
+    while True:
+        oracle.residual(mesh.e2n, q, mesh.w, res=res)
+        passes += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": passes * mesh.E / el, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"{passes} sequential FP64 residual passes over all {mesh.E} edges "
+                      f"of the same mesh ({el:.1f} s, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--variant", choices=["owner", "coloured", "atomic", "coloured-lds-atomic"],
+                    default="owner")
+    ap.add_argument("--cluster-size", type=int, default=512)
+    ap.add_argument("--no-lane-groups", action="store_true")
+    ap.add_argument("--renumber", choices=["rcm", "morton", "none"], default="morton")
+    ap.add_argument("--block-size", type=int, default=512)
+    ap.add_argument("--colour-sort", action="store_true")
+    ap.add_argument("--n", type=int, default=160, help="nodes per axis of the layered box")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import meshgen
+    import paper_1403_7209_amd as pk
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    variant = pk.VARIANTS[args.variant]
+
+    t0 = time.perf_counter()
+    mesh = meshgen.build_mesh(args.n, 1, 0.25)
+    q = meshgen.state(mesh.N, mesh.perm)
+    N, E = mesh.N, mesh.E
+    log(f"mesh: N={N} E={E} ({time.perf_counter() - t0:.1f} s)")
+
+    ctx = pk.Context(dev)
+    t0 = time.perf_counter()
+    p64 = pk.FluxProblem(ctx, mesh.e2n, mesh.w, mesh.vol, q, renumber=args.renumber,
+                         block_size=args.block_size, colour_sort=args.colour_sort,
+                         coords=mesh.xyz, cluster_size=args.cluster_size,
+                         lane_groups=not args.no_lane_groups)
+    p32 = pk.FluxProblem(ctx, mesh.e2n, mesh.w, mesh.vol, q, fp32=True, like=p64)
+    info = p64.info
+    log(f"plan: {info['plan_seconds']:.1f} s, nb={info['nblocks']} nc={info['nblock_colours']} "
+        f"sumU/N={info['sum_unique'] / N:.3f} maxU={info['max_unique']} "
+        f"edge colours mean {info['mean_elem_colours']:.1f} ({time.perf_counter() - t0:.1f} s)")
+
+    dt = p64.compute_dt(0.5, variant)
+    rbar = torch.from_numpy(meshgen.normal(6 * N, purpose=21).reshape(6, N)).to(dev)
+    qbar = torch.zeros((6, N), dtype=torch.float64, device=dev)
+    nbar = torch.empty((3, E), dtype=torch.float64, device=dev)
+    rbar_d, qbar_d = p64.dat(rbar, "rbar"), p64.dat(qbar, "qbar")
+    nbar_d = p64.dat(nbar, "nbar", edges=True)
+    q0_init64, q0_init32 = p64.qa.clone(), p32.qa.clone()
+
+    stream = torch.cuda.current_stream(dev)
+    timers = {k: [] for k in ("fp64", "fp32", "adjoint", "rk64", "rk32")}
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    # the owner variant writes each residual once, so the stage need not zero it
+    ra, rk = (pk.WRITE, pk.READ) if variant == pk.OWNER else (pk.INC, pk.RW)
+
+    def rk_iter(p, kflux, krk, rec):
+        qa, qb = p.dat(p.qa, "qa"), p.dat(p.qb, "qb")
+        p.ss.zero_()
+        for k in range(5):
+            a = ev() if rec else None
+            p.ctx.edge_flux(p.edges, p.e2n, qa if k == 0 else qb, p.w, p.res_d, p.gamma, variant,
+                            ra)
+            b = ev() if rec else None
+            p.ctx.rk_stage(p.nodes, qa, p.res_d, p.vol, qb, pk.RK_ALPHA[k] * dt, p.ss[k],
+                           rk)
+            c = ev() if rec else None
+            if rec:
+                timers[kflux].append((a, b))
+                timers[krk].append((b, c))
+        p.qa, p.qb = p.qb, p.qa
+
+    def step(rec):
+        rk_iter(p64, "fp64", "rk64", rec)
+        rk_iter(p32, "fp32", "rk32", rec)
+        if variant != pk.OWNER:
+            qbar.zero_()
+        a = ev() if rec else None
+        ctx.edge_flux_adjoint(p64.edges, p64.e2n, p64.dat(p64.qa, "q"), p64.w, rbar_d, qbar_d,
+                              nbar_d, p64.gamma, variant, ra)
+        b = ev() if rec else None
+        if rec:
+            timers["adjoint"].append((a, b))
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    # restart from the initial state so every run times the same iterations
+    p64.qa.copy_(q0_init64)
+    p32.qa.copy_(q0_init32)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    e_start = ev()
+    for _ in range(args.steps):
+        step(True)
+    e_end = ev()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_step = e_start.elapsed_time(e_end) / args.steps
+    ctx.sync()
+    if not ctx.check_finite(p64.ss) or not ctx.check_finite(p32.ss):
+        log("warning: non-finite residual norm")
+
+    per = {}
+    for k, lst in timers.items():
+        ms = float(np.mean([a.elapsed_time(b) for a, b in lst]))
+        be, bn = BYTES[k]
+        gbs = (be * E + bn * N) / (ms * 1e-3) / 1e9
+        per[k] = {"ms": round(ms, 4), "algorithmic_GBs": round(gbs, 1),
+                  "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        if be:
+            per[k]["edges_per_s"] = round(E / (ms * 1e-3), 1)
+        log(f"{k:8s} {ms * 1e3:9.1f} us  {gbs:8.1f} GB/s algorithmic  "
+            f"({100 * gbs / HBM_PEAK_GBS:.1f} % of 8 TB/s)")
+    speedup32 = per["fp64"]["ms"] / per["fp32"]["ms"]
+    value = 11 * E / (ms_step * 1e-3)
+    log(f"step {ms_step:.3f} ms (wall {1e3 * wall / args.steps:.3f} ms), {value:.4e} edges/s, "
+        f"FP32/FP64 loop speedup {speedup32:.3f}")
+
+    dom = per["fp64"]
+    be, bn = BYTES["fp64"]
+    out = {
+        "metric": "edges/s of edge-flux residual loop (FP64, FP32, adjoint) + % HBM roofline",
+        "value": round(value, 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"periodic {args.n}^3 box, layered 5/6-tet mix, jitter 0.25h: "
+                        f"N={N} nodes, E={E} edges; step = FP64 RK5 iteration + FP32-storage "
+                        f"RK5 iteration + 1 FP64 adjoint sweep (11 edge loops)",
+            "variant": args.variant,
+            "renumber": args.renumber,
+            "block_size": args.block_size,
+            "colour_sort": bool(args.colour_sort),
+            "cluster_size": args.cluster_size,
+            "lane_groups": not args.no_lane_groups,
+            "plan": {k: info[k] for k in ("nblocks", "nblock_colours", "sum_unique", "max_unique",
+                                          "mean_elem_colours", "nclusters", "owner_edge_visits")},
+        },
+        "forms": per,
+        "fp32_speedup_over_fp64": round(speedup32, 4),
+        "roofline": {
+            "kernel": "FP64 edge-flux loop (opf_edge_flux)",
+            "bound": "hbm",
+            "achieved": dom["algorithmic_GBs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": dom["hbm_frac"],
+            "bytes_per_launch": be * E + bn * N,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(mesh, q)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,8 +77,17 @@ typedef enum {
 /* How an indirect (edge) loop resolves its increments. */
 typedef enum {
     OPF_V_COLOURED = 0, /* mini-partitions staged in LDS, edge colours serialised
-                           inside a partition, one launch per partition colour   */
-    OPF_V_ATOMIC = 1    /* one thread per edge, FP64 atomic adds to HBM          */
+                           inside a partition, one launch per partition colour
+                           (Sec. 4.1); deterministic                              */
+    OPF_V_ATOMIC = 1,   /* one thread per edge, FP64 atomic adds to HBM          */
+    OPF_V_OWNER = 2,    /* one workgroup per cluster of consecutive nodes runs
+                           every edge touching the cluster (edges between two
+                           clusters run twice) and writes its nodes' totals
+                           once; single launch, no colours (owner-compute as in
+                           Sec. 3.2, at workgroup level).  LDS accumulation uses
+                           FP64 LDS atomics, so the summation order varies      */
+    OPF_V_COLOURED_LDS_ATOMIC = 3 /* as COLOURED, with LDS atomics in place of
+                           the edge colours inside a partition                  */
 } opf_variant;
 
 typedef enum { OPF_RENUM_NONE = 0, OPF_RENUM_RCM = 1, OPF_RENUM_MORTON = 2 } opf_renumber;
@@ -124,9 +133,15 @@ int opf_decl_map(opf_ctx *ctx, opf_set from, opf_set to, int dim, const int32_t 
                  int index_base, const char *name, opf_map *out);
 
 typedef struct {
-    int32_t renumber;      /* opf_renumber; RCM is the default choice             */
+    int32_t renumber;      /* opf_renumber                                         */
     int32_t block_size;    /* edges per mini-partition: 64, 128, ..., 2048         */
     int32_t colour_sort;   /* 1: order edges inside each partition by colour       */
+    int32_t cluster_size;  /* nodes per owner cluster, 64..4096; 0 = none (the
+                              OWNER variant is then unavailable).  Edges are
+                              ordered by the cluster pair they join.               */
+    int32_t lane_groups;   /* 1: inside each cluster-pair segment, order edges in
+                              groups of 64 sharing no node, so the lanes of one
+                              wavefront update distinct nodes (OWNER variant)     */
     int32_t pad;
     const double *coords;  /* host, SoA 3 x to.size; required for MORTON          */
 } opf_plan_opts;
@@ -143,6 +158,10 @@ typedef struct {
     int64_t bandwidth_after;    /* the same after renumbering                     */
     double plan_seconds;        /* host time of opf_plan                          */
     int64_t device_bytes;       /* device memory held by the plan                 */
+    int64_t nclusters;          /* owner clusters (0 without clusters)            */
+    int64_t owner_edge_visits;  /* edges run by the OWNER variant (>= E)          */
+    int32_t max_cluster_segments;
+    int32_t owner_ok;           /* 1 when the OWNER variant can run               */
 } opf_plan_info;
 
 /* Builds the execution plan of an arity-2 map (edges -> nodes) on the host
@@ -151,6 +170,8 @@ typedef struct {
  * bit-exactly, and uploads it to the device (device contexts only; blocks until
  * the upload is done).  The plan renumbers both sets: afterwards every dat on
  * them must be in internal numbering.  A set can be renumbered by one plan only.
+ * `opts` NULL means RCM, block_size 512, no colour sort, cluster_size 512,
+ * lane groups on.
  * `info` may be NULL.
  * Errors: OPF_EINVAL (dim != 2, self-loop edge, bad options), OPF_ESTATE (a set
  * already renumbered by another plan), OPF_ENOMEM, OPF_EDEVICE, OPF_EPLAN. */
@@ -176,6 +197,10 @@ typedef struct {
     const int64_t *unique_offsets; /* [nblocks+1] into unique_nodes                   */
     const int32_t *unique_nodes;   /* sorted distinct nodes of each partition         */
     const uint16_t *local_idx;     /* [2E] endpoint positions in the partition's list */
+    int64_t cluster_size, nclusters;
+    const int64_t *cluster_seg_offsets; /* [nclusters+1] into the two arrays below  */
+    const int32_t *cluster_seg_start;   /* first edge of each segment of a cluster  */
+    const int32_t *cluster_seg_len;     /* edges in the segment                     */
 } opf_plan_view;
 
 int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out);
@@ -193,7 +218,8 @@ typedef struct {
  * inside a partition, edges of one colour share no node; (5) partitions are
  * contiguous edge ranges of at most block_size edges, grouped by colour;
  * (6) local indices resolve to the map's nodes; (7) colour counts fit their
- * types.  Works without a GPU.  Errors: OPF_EPLAN (report filled),
+ * types; (8) every edge is in the work of exactly the owner clusters of its
+ * two endpoints.  Works without a GPU.  Errors: OPF_EPLAN (report filled),
  * OPF_ESTATE (no plan). */
 int opf_plan_verify(const opf_ctx *ctx, opf_map map, opf_plan_report *report);
 
@@ -230,12 +256,15 @@ typedef struct {
 
 /* Runs kernel k over set s.  Argument signatures (checked; dims are exact):
  *
- *  EDGE_FLUX over edges, variant COLOURED or ATOMIC:
+ *  EDGE_FLUX over edges, any variant:
  *     (q, 0, e2n, 6, T, READ) (q, 1, e2n, 6, T, READ) (n, -1, ID, 3, T, READ)
  *     (res, 0, e2n, 6, F64, INC) (res, 1, e2n, 6, F64, INC)
  *     gbl (gamma, 1, F64, READ, host)
  *   with T = F64, or T = F32 for the FP32-storage form (state, weights and flux
- *   arithmetic in FP32, accumulation into the FP64 residual).
+ *   arithmetic in FP32, accumulation into the FP64 residual).  With the OWNER
+ *   variant the two node increments may instead be WRITE: res = sum of the
+ *   edge contributions, with no need to zero res first (the same holds for the
+ *   increments of the other edge kernels).
  *  EDGE_FLUX_ADJ over edges (FP64):
  *     (q,0,e2n,6,READ) (q,1,e2n,6,READ) (n,-1,ID,3,READ)
  *     (rbar,0,e2n,6,READ) (rbar,1,e2n,6,READ)
@@ -248,8 +277,10 @@ typedef struct {
  *     (q,-1,ID,6,T,WRITE)
  *     gbl (alpha_dt, 1, F64, READ, host) gbl (ss, 6, F64, INC, device)
  *   computes q = q0 - alpha_dt * res / vol in FP64 (rounded once to T), adds
- *   sum_i res_i^2 per component to ss, and zeroes res.  The sum is
- *   deterministic: fixed partition, fixed order.
+ *   sum_i res_i^2 per component to ss, and zeroes res.  With res READ instead
+ *   of RW, res is left untouched (for a following edge loop that WRITEs it).
+ *   The sum is deterministic: fixed partition, fixed order.  q must not alias
+ *   q0 or res.
  *  DT_MIN over nodes (direct): (vol,-1,ID,1,F64,READ) (lam,-1,ID,1,F64,READ)
  *     gbl (cfl, 1, F64, READ, host) gbl (dt, 1, F64, MIN, device)
  *   dt = min(dt, cfl * min_i vol_i / lam_i).
@@ -260,16 +291,18 @@ typedef struct {
 int opf_par_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args, int ngbl,
                  const opf_gbl *gbls, int variant, void *stream);
 
-/* Typed wrappers over opf_par_loop with the signatures above. */
+/* Typed wrappers over opf_par_loop with the signatures above.  res_access and
+ * qbar_access are OPF_INC, or OPF_WRITE with the OWNER variant; for the stage
+ * update res_access is OPF_RW (zero after use) or OPF_READ (keep). */
 int opf_edge_flux(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n, opf_dat res,
-                  double gamma, int variant, void *stream);
+                  double gamma, int variant, int res_access, void *stream);
 int opf_edge_flux_adjoint(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
                           opf_dat rbar, opf_dat qbar, opf_dat nbar, double gamma, int variant,
-                          void *stream);
+                          int qbar_access, void *stream);
 int opf_edge_specrad(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
                      opf_dat lam, double gamma, int variant, void *stream);
 int opf_rk_stage(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol, opf_dat q,
-                 double alpha_dt, double *ss_dev, void *stream);
+                 double alpha_dt, double *ss_dev, int res_access, void *stream);
 int opf_dt_min(opf_ctx *ctx, opf_set nodes, opf_dat vol, opf_dat lam, double cfl,
                double *dt_dev, void *stream);
 

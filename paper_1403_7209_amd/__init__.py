@@ -18,7 +18,7 @@ import torch
 from . import _build
 
 __all__ = ["Context", "OpfError", "FluxProblem", "EdgeFluxFunction", "RK_ALPHA", "load",
-           "COLOURED", "ATOMIC"]
+           "COLOURED", "ATOMIC", "OWNER", "COLOURED_LDS_ATOMIC", "VARIANTS"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = _build.LIB
@@ -31,7 +31,9 @@ STATUS = {0: "OPF_OK", -1: "OPF_EINVAL", -2: "OPF_ERANGE", -3: "OPF_ESIZE", -4: 
 F64, F32 = 0, 1
 READ, WRITE, RW, INC, MIN = 0, 1, 2, 3, 4
 K_EDGE_FLUX, K_EDGE_FLUX_ADJ, K_RK_STAGE, K_EDGE_SPECRAD, K_DT_MIN = 0, 1, 2, 3, 4
-COLOURED, ATOMIC = 0, 1
+COLOURED, ATOMIC, OWNER, COLOURED_LDS_ATOMIC = 0, 1, 2, 3
+VARIANTS = {"coloured": COLOURED, "atomic": ATOMIC, "owner": OWNER,
+            "coloured-lds-atomic": COLOURED_LDS_ATOMIC}
 RENUMBER = {"none": 0, "rcm": 1, "morton": 2}
 ID = -1
 
@@ -54,7 +56,8 @@ class OpfError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("renumber", ctypes.c_int32), ("block_size", ctypes.c_int32),
-                ("colour_sort", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("colour_sort", ctypes.c_int32), ("cluster_size", ctypes.c_int32),
+                ("lane_groups", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("coords", ctypes.c_void_p)]
 
 
@@ -64,7 +67,9 @@ class PlanInfo(ctypes.Structure):
                 ("sum_unique", ctypes.c_int64), ("max_unique", ctypes.c_int32),
                 ("min_blocks_per_colour", ctypes.c_int32), ("bandwidth_before", ctypes.c_int64),
                 ("bandwidth_after", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("nclusters", ctypes.c_int64),
+                ("owner_edge_visits", ctypes.c_int64), ("max_cluster_segments", ctypes.c_int32),
+                ("owner_ok", ctypes.c_int32)]
 
 
 class PlanView(ctypes.Structure):
@@ -74,7 +79,10 @@ class PlanView(ctypes.Structure):
                 ("block_colour", ctypes.c_void_p), ("colour_blocks", ctypes.c_void_p),
                 ("colour_offsets", ctypes.c_void_p), ("elem_colour", ctypes.c_void_p),
                 ("block_ncolours", ctypes.c_void_p), ("unique_offsets", ctypes.c_void_p),
-                ("unique_nodes", ctypes.c_void_p), ("local_idx", ctypes.c_void_p)]
+                ("unique_nodes", ctypes.c_void_p), ("local_idx", ctypes.c_void_p),
+                ("cluster_size", ctypes.c_int64), ("nclusters", ctypes.c_int64),
+                ("cluster_seg_offsets", ctypes.c_void_p), ("cluster_seg_start", ctypes.c_void_p),
+                ("cluster_seg_len", ctypes.c_void_p)]
 
 
 class PlanReport(ctypes.Structure):
@@ -126,10 +134,11 @@ def load():
     lib.opf_decl_dat.argtypes = [vp, i32, ctypes.c_int, ctypes.c_int, vp, i64, ctypes.c_char_p, P(i32)]
     lib.opf_par_loop.argtypes = [vp, ctypes.c_int, i32, ctypes.c_int, P(Arg), ctypes.c_int, P(Gbl),
                                  ctypes.c_int, vp]
-    lib.opf_edge_flux.argtypes = [vp, i32, i32, i32, i32, i32, d, ctypes.c_int, vp]
-    lib.opf_edge_flux_adjoint.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, d, ctypes.c_int, vp]
+    lib.opf_edge_flux.argtypes = [vp, i32, i32, i32, i32, i32, d, ctypes.c_int, ctypes.c_int, vp]
+    lib.opf_edge_flux_adjoint.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, d, ctypes.c_int,
+                                          ctypes.c_int, vp]
     lib.opf_edge_specrad.argtypes = [vp, i32, i32, i32, i32, i32, d, ctypes.c_int, vp]
-    lib.opf_rk_stage.argtypes = [vp, i32, i32, i32, i32, i32, d, vp, vp]
+    lib.opf_rk_stage.argtypes = [vp, i32, i32, i32, i32, i32, d, vp, ctypes.c_int, vp]
     lib.opf_dt_min.argtypes = [vp, i32, i32, i32, d, vp, vp]
     lib.opf_sync.argtypes = [vp, vp]
     lib.opf_check_finite.argtypes = [vp, vp, ctypes.c_int, vp]
@@ -203,10 +212,11 @@ class Context:
                                           name.encode(), ctypes.byref(out)), "opf_decl_map")
         return out.value
 
-    def plan(self, m, renumber="rcm", block_size=512, colour_sort=False, coords=None):
+    def plan(self, m, renumber="rcm", block_size=512, colour_sort=False, coords=None,
+             cluster_size=512, lane_groups=True):
         c = None if coords is None else np.ascontiguousarray(coords, dtype=np.float64)
-        opts = PlanOpts(RENUMBER[renumber], block_size, 1 if colour_sort else 0, 0,
-                        None if c is None else c.ctypes.data)
+        opts = PlanOpts(RENUMBER[renumber], block_size, 1 if colour_sort else 0, cluster_size,
+                        1 if lane_groups else 0, 0, None if c is None else c.ctypes.data)
         info = PlanInfo()
         self._check(self.lib.opf_plan(self._ctx, m, ctypes.byref(opts), ctypes.byref(info)),
                     "opf_plan")
@@ -229,7 +239,14 @@ class Context:
             return np.frombuffer(buf, dtype=dtype).copy()
 
         uoff = arr(v.unique_offsets, ctypes.c_int64, nb + 1, np.int64)
+        ncl = v.nclusters
+        soff = arr(v.cluster_seg_offsets, ctypes.c_int64, ncl + 1, np.int64) if ncl else \
+            np.zeros(1, np.int64)
+        nseg = int(soff[-1])
         return dict(nnodes=v.nnodes, nedges=E, nblocks=nb, nblock_colours=nc,
+                    cluster_size=v.cluster_size, nclusters=ncl, cluster_seg_offsets=soff,
+                    cluster_seg_start=arr(v.cluster_seg_start, ctypes.c_int32, nseg, np.int32),
+                    cluster_seg_len=arr(v.cluster_seg_len, ctypes.c_int32, nseg, np.int32),
                     block_size=v.block_size,
                     e2n=arr(v.e2n, ctypes.c_int32, 2 * E, np.int32).reshape(E, 2),
                     block_offsets=arr(v.block_offsets, ctypes.c_int64, nb + 1, np.int64),
@@ -285,24 +302,29 @@ class Context:
         self._check(self.lib.opf_par_loop(self._ctx, kernel, s, len(args), a, len(gbls), g, variant,
                                           _stream_ptr(stream, self.device)), "opf_par_loop")
 
-    def edge_flux(self, edges, e2n, q, n, res, gamma=1.4, variant=COLOURED, stream=None):
+    def edge_flux(self, edges, e2n, q, n, res, gamma=1.4, variant=COLOURED, res_access=INC,
+                  stream=None):
+        """res_access INC (res += sum), or WRITE (res = sum; OWNER variant only)."""
         self._check(self.lib.opf_edge_flux(self._ctx, edges, e2n, q, n, res, gamma, variant,
-                                           _stream_ptr(stream, self.device)), "opf_edge_flux")
+                                           res_access, _stream_ptr(stream, self.device)),
+                    "opf_edge_flux")
 
     def edge_flux_adjoint(self, edges, e2n, q, n, rbar, qbar, nbar, gamma=1.4, variant=COLOURED,
-                          stream=None):
+                          qbar_access=INC, stream=None):
         self._check(self.lib.opf_edge_flux_adjoint(self._ctx, edges, e2n, q, n, rbar, qbar, nbar,
-                                                   gamma, variant, _stream_ptr(stream, self.device)),
+                                                   gamma, variant, qbar_access,
+                                                   _stream_ptr(stream, self.device)),
                     "opf_edge_flux_adjoint")
 
     def edge_specrad(self, edges, e2n, q, n, lam, gamma=1.4, variant=COLOURED, stream=None):
         self._check(self.lib.opf_edge_specrad(self._ctx, edges, e2n, q, n, lam, gamma, variant,
                                               _stream_ptr(stream, self.device)), "opf_edge_specrad")
 
-    def rk_stage(self, nodes, q0, res, vol, q, alpha_dt, ss, stream=None):
-        """ss: float64 device tensor of 6 values, incremented by sum res^2."""
+    def rk_stage(self, nodes, q0, res, vol, q, alpha_dt, ss, res_access=RW, stream=None):
+        """ss: float64 device tensor of 6 values, incremented by sum res^2.
+        res_access RW zeroes res after use, READ leaves it."""
         self._check(self.lib.opf_rk_stage(self._ctx, nodes, q0, res, vol, q, float(alpha_dt),
-                                          ctypes.c_void_p(ss.data_ptr()),
+                                          ctypes.c_void_p(ss.data_ptr()), res_access,
                                           _stream_ptr(stream, self.device)), "opf_rk_stage")
 
     def dt_min(self, nodes, vol, lam, cfl, dt, stream=None):
@@ -331,17 +353,25 @@ class FluxProblem:
     FP32 (the residual, volumes and reductions stay FP64)."""
 
     def __init__(self, ctx, e2n, w, vol, q, fp32=False, renumber="rcm", block_size=512,
-                 colour_sort=False, coords=None, gamma=1.4, index_base=0):
+                 colour_sort=False, coords=None, gamma=1.4, index_base=0, like=None,
+                 cluster_size=512, lane_groups=True):
         self.ctx, self.gamma, self.fp32 = ctx, float(gamma), fp32
-        e2n = np.ascontiguousarray(e2n, dtype=np.int32)
-        self.N, self.E = int(np.asarray(vol).shape[0]), int(e2n.shape[0])
-        self.nodes = ctx.decl_set(self.N, "nodes")
-        self.edges = ctx.decl_set(self.E, "edges")
-        self.e2n = ctx.decl_map(self.edges, self.nodes, 2, e2n, index_base, "e2n")
-        self.info = ctx.plan(self.e2n, renumber=renumber, block_size=block_size,
-                             colour_sort=colour_sort, coords=coords)
-        self.node_new = ctx.get_perm(self.nodes, self.N)
-        self.edge_new = ctx.get_perm(self.edges, self.E)
+        if like is not None:  # same mesh, sets, map and plan; other dats
+            if like.ctx is not ctx:
+                raise ValueError("like= must be a problem on the same context")
+            for k in ("N", "E", "nodes", "edges", "e2n", "info", "node_new", "edge_new"):
+                setattr(self, k, getattr(like, k))
+        else:
+            e2n = np.ascontiguousarray(e2n, dtype=np.int32)
+            self.N, self.E = int(np.asarray(vol).shape[0]), int(e2n.shape[0])
+            self.nodes = ctx.decl_set(self.N, "nodes")
+            self.edges = ctx.decl_set(self.E, "edges")
+            self.e2n = ctx.decl_map(self.edges, self.nodes, 2, e2n, index_base, "e2n")
+            self.info = ctx.plan(self.e2n, renumber=renumber, block_size=block_size,
+                                 colour_sort=colour_sort, coords=coords,
+                                 cluster_size=cluster_size, lane_groups=lane_groups)
+            self.node_new = ctx.get_perm(self.nodes, self.N)
+            self.edge_new = ctx.get_perm(self.edges, self.E)
         dev = ctx.torch_device
         self.tdtype = torch.float32 if fp32 else torch.float64
         self.w_t = self.nodes_in(w, edges=True).to(self.tdtype)
@@ -375,10 +405,11 @@ class FluxProblem:
         return self.ctx.decl_dat(self.edges if edges else self.nodes, t, name)
 
     # -- loops -------------------------------------------------------------------
-    def residual(self, q_t, res_t, variant=COLOURED, stream=None):
-        """res_t += edge-flux residual of state q_t (both internal numbering)."""
+    def residual(self, q_t, res_t, variant=COLOURED, res_access=INC, stream=None):
+        """res_t += edge-flux residual of state q_t (both internal numbering);
+        res_access=WRITE (OWNER variant) overwrites instead."""
         self.ctx.edge_flux(self.edges, self.e2n, self.dat(q_t, "q"), self.w, self.dat(res_t, "res"),
-                           self.gamma, variant, stream)
+                           self.gamma, variant, res_access, stream)
 
     def compute_dt(self, cfl=0.5, variant=COLOURED, stream=None):
         """Global time step cfl * min_i vol_i / sum_e lambda_e of the current state."""
@@ -393,13 +424,15 @@ class FluxProblem:
         """One 5-stage iteration; the new state is left in self.qa.  self.ss
         (5, 6) receives each stage's per-variable sum of squared residuals."""
         qa, qb = self.dat(self.qa, "qa"), self.dat(self.qb, "qb")
+        # the owner variant writes each residual once: no zeroing pass needed
+        ra, rk = (WRITE, READ) if variant == OWNER else (INC, RW)
         self.ss.zero_()
         for k in range(5):
             src = qa if k == 0 else qb
             self.ctx.edge_flux(self.edges, self.e2n, src, self.w, self.res_d, self.gamma, variant,
-                               stream)
+                               ra, stream)
             self.ctx.rk_stage(self.nodes, qa, self.res_d, self.vol, qb, RK_ALPHA[k] * dt,
-                              self.ss[k], stream)
+                              self.ss[k], rk, stream)
         self.qa, self.qb = self.qb, self.qa
 
     def rms(self):

@@ -1,20 +1,31 @@
 // kernels.hip -- gfx950 kernels of the edge-flux path.
 //
-// Edge loops (Sec. 3.1 op_par_loop over edges with two OP_READ node arguments
-// through the edge->node map, one direct weight and two OP_INC node
-// increments) come in two forms:
-//   * coloured: one workgroup per mini-partition, one launch per partition
-//     colour (Sec. 4.1).  The partition's distinct nodes are staged into LDS
-//     (the Sec. 4.1.2 staging, affordable with 160 KB of LDS per CU), every
-//     thread evaluates its edges into registers, increments go into an LDS
-//     accumulator one edge colour at a time, and the partition then adds its
-//     accumulator to HBM with plain read-modify-write (partitions of one colour
-//     share no node).  Deterministic.
+// An edge loop is an op_par_loop over edges (Sec. 3.1) with OP_READ node
+// arguments through the edge->node map, one direct 3-vector weight and OP_INC
+// node increments.  Every kernel first turns a node's inputs into a "staged"
+// record once per node (state plus primitives: 1/rho, pressure, sound speed),
+// so the per-edge work needs no division or square root besides |n_e|.
+// Three ways to resolve the increments:
+//   * coloured (Sec. 4.1): one workgroup per mini-partition, one launch per
+//     partition colour.  The partition's distinct nodes are staged in LDS (the
+//     Sec. 4.1.2 staging; gfx950 has 160 KB of LDS per CU), increments go into
+//     an LDS accumulator one edge colour at a time (or with LDS FP64 atomics in
+//     the ablation variant), then the partition adds its accumulator to HBM
+//     with plain read-modify-write: partitions of one colour share no node.
 //   * atomic: one thread per edge, FP64 atomic adds straight to HBM.
-// Data are SoA (Sec. 4.1.2); every component is its own coalesced stream.
-// The direct explicit stage and its residual norm are one grid-stride pass
+//   * owner: one workgroup per contiguous cluster of K nodes runs every edge
+//     that touches the cluster (edges joining two clusters run in both), adds
+//     only into its own nodes' LDS accumulator (ds_add_f64) and writes each
+//     node's residual exactly once, coalesced.  Single launch, no partition
+//     colours, no HBM atomics -- the owner-compute rule of the paper's
+//     distributed back-end (redundant execution of halo edges, Sec. 3.2 and
+//     4.2) applied to the workgroups of one GPU.
+// Data are SoA (Sec. 4.1.2): every component is its own coalesced stream.
+// The direct stage update and its residual norm are one grid-stride pass
 // with a wavefront + LDS reduction per workgroup and a fixed-order second
 // pass over the per-workgroup partial sums.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace opf {
@@ -28,12 +39,73 @@ __device__ __forceinline__ float tsqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double tabs(double x) { return fabs(x); }
 __device__ __forceinline__ float tabs(float x) { return fabsf(x); }
 
+// ----------------------------------------------------------- edge math -- */
+
+// F = 1/2 (f(q_i) + f(q_j)).n - 1/2 lambda (q_j - q_i),
+// lambda = |1/2 (U_i + U_j)| + 1/2 (c_i + c_j) |n|, U = u.n; +F to node i,
+// -F to node j.  Staged record: q[0..5], 1/rho, p, c.
+struct OpFlux {
+    static constexpr int NIN = 6, NS = 9, NOUT = 6, NWOUT = 0, MODE = ANTI;
+    template <typename T>
+    __device__ static __forceinline__ void stage(const T *x, T *s, T gamma)
+    {
+#pragma unroll
+        for (int v = 0; v < 6; ++v) s[v] = x[v];
+        const T ir = T(1) / x[0];
+        const T p = (gamma - T(1)) * (x[4] - T(0.5) * (x[1] * x[1] + x[2] * x[2] + x[3] * x[3]) * ir);
+        s[6] = ir;
+        s[7] = p;
+        s[8] = tsqrt(gamma * p * ir);
+    }
+    template <typename T>
+    __device__ static __forceinline__ void edge(const T *a, const T *b, const T *n, T gamma,
+                                                double *yi, double *, double *)
+    {
+        const T h = T(0.5);
+        const T Ua = (a[1] * n[0] + a[2] * n[1] + a[3] * n[2]) * a[6];
+        const T Ub = (b[1] * n[0] + b[2] * n[1] + b[3] * n[2]) * b[6];
+        const T nn = tsqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        const T hl = h * (tabs(h * (Ua + Ub)) + h * (a[8] + b[8]) * nn);
+        yi[0] = (double)(h * (a[0] * Ua + b[0] * Ub) - hl * (b[0] - a[0]));
+        yi[1] = (double)(h * (a[1] * Ua + b[1] * Ub + (a[7] + b[7]) * n[0]) - hl * (b[1] - a[1]));
+        yi[2] = (double)(h * (a[2] * Ua + b[2] * Ub + (a[7] + b[7]) * n[1]) - hl * (b[2] - a[2]));
+        yi[3] = (double)(h * (a[3] * Ua + b[3] * Ub + (a[7] + b[7]) * n[2]) - hl * (b[3] - a[3]));
+        yi[4] = (double)(h * ((a[4] + a[7]) * Ua + (b[4] + b[7]) * Ub) - hl * (b[4] - a[4]));
+        yi[5] = (double)(h * (a[5] * Ua + b[5] * Ub) - hl * (b[5] - a[5]));
+    }
+};
+
+// lambda_e added to both end nodes (local time-step denominator).
+// Staged record: u[0..2], c.
+struct OpSpecrad {
+    static constexpr int NIN = 5, NS = 4, NOUT = 1, NWOUT = 0, MODE = SAME;
+    template <typename T>
+    __device__ static __forceinline__ void stage(const T *x, T *s, T gamma)
+    {
+        const T ir = T(1) / x[0];
+        s[0] = x[1] * ir;
+        s[1] = x[2] * ir;
+        s[2] = x[3] * ir;
+        const T p = (gamma - T(1)) * (x[4] - T(0.5) * (x[1] * s[0] + x[2] * s[1] + x[3] * s[2]));
+        s[3] = tsqrt(gamma * p * ir);
+    }
+    template <typename T>
+    __device__ static __forceinline__ void edge(const T *a, const T *b, const T *n, T,
+                                                double *yi, double *, double *)
+    {
+        const T h = T(0.5);
+        const T Ua = a[0] * n[0] + a[1] * n[1] + a[2] * n[2];
+        const T Ub = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
+        const T nn = tsqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        yi[0] = (double)(tabs(h * (Ua + Ub)) + h * (a[3] + b[3]) * nn);
+    }
+};
+
 template <typename T>
 struct Prim {
     T u0, u1, u2, p, c, U;
 };
 
-// Velocity, pressure (ideal gas), sound speed and normal velocity of a node.
 template <typename T>
 __device__ __forceinline__ void prim(const T *q, const T *n, T gamma, Prim<T> &s)
 {
@@ -45,45 +117,6 @@ __device__ __forceinline__ void prim(const T *q, const T *n, T gamma, Prim<T> &s
     s.c = tsqrt(gamma * s.p * ir);
     s.U = s.u0 * n[0] + s.u1 * n[1] + s.u2 * n[2];
 }
-
-// F = 1/2 (f(q_i) + f(q_j)).n - 1/2 lambda (q_j - q_i),
-// lambda = |1/2 (U_i + U_j)| + 1/2 (c_i + c_j) |n|; +F to node i, -F to node j.
-struct OpFlux {
-    static constexpr int NIN = 6, NOUT = 6, NWOUT = 0, MODE = ANTI;
-    template <typename T>
-    __device__ static __forceinline__ void edge(const T *qi, const T *qj, const T *n, T gamma,
-                                                double *yi, double *, double *)
-    {
-        Prim<T> a, b;
-        prim(qi, n, gamma, a);
-        prim(qj, n, gamma, b);
-        const T h = T(0.5);
-        const T nn = tsqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        const T hl = h * (tabs(h * (a.U + b.U)) + h * (a.c + b.c) * nn);
-        yi[0] = (double)(h * (qi[0] * a.U + qj[0] * b.U) - hl * (qj[0] - qi[0]));
-        yi[1] = (double)(h * (qi[1] * a.U + a.p * n[0] + qj[1] * b.U + b.p * n[0]) - hl * (qj[1] - qi[1]));
-        yi[2] = (double)(h * (qi[2] * a.U + a.p * n[1] + qj[2] * b.U + b.p * n[1]) - hl * (qj[2] - qi[2]));
-        yi[3] = (double)(h * (qi[3] * a.U + a.p * n[2] + qj[3] * b.U + b.p * n[2]) - hl * (qj[3] - qi[3]));
-        yi[4] = (double)(h * ((qi[4] + a.p) * a.U + (qj[4] + b.p) * b.U) - hl * (qj[4] - qi[4]));
-        yi[5] = (double)(h * (qi[5] * a.U + qj[5] * b.U) - hl * (qj[5] - qi[5]));
-    }
-};
-
-// lambda_e added to both end nodes (local time-step denominator).
-struct OpSpecrad {
-    static constexpr int NIN = 5, NOUT = 1, NWOUT = 0, MODE = SAME;
-    template <typename T>
-    __device__ static __forceinline__ void edge(const T *qi, const T *qj, const T *n, T gamma,
-                                                double *yi, double *, double *)
-    {
-        Prim<T> a, b;
-        prim(qi, n, gamma, a);
-        prim(qj, n, gamma, b);
-        const T h = T(0.5);
-        const T nn = tsqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        yi[0] = (double)(tabs(h * (a.U + b.U)) + h * (a.c + b.c) * nn);
-    }
-};
 
 // Reverse of one node's share of the flux: given fb = dL/df (= Fbar/2), Ub
 // (from lambda), cb (from lambda), accumulate into qb and nb.
@@ -128,11 +161,17 @@ __device__ __forceinline__ void node_reverse(const double *q, const Prim<double>
     qb[0] += rb;
 }
 
-// Reverse (adjoint) edge: inputs x = (q[6], rbar[6]) per node; with
+// Reverse (adjoint) edge: inputs (q[6], rbar[6]) per node; with
 // Fbar = rbar_i - rbar_j it returns qbar_i, qbar_j and nbar (direct).
 // Forward intermediates are recomputed, never stored.
 struct OpAdjoint {
-    static constexpr int NIN = 12, NOUT = 6, NWOUT = 3, MODE = GEN;
+    static constexpr int NIN = 12, NS = 12, NOUT = 6, NWOUT = 3, MODE = GEN;
+    template <typename T>
+    __device__ static __forceinline__ void stage(const T *x, T *s, T)
+    {
+#pragma unroll
+        for (int v = 0; v < 12; ++v) s[v] = x[v];
+    }
     template <typename T>
     __device__ static __forceinline__ void edge(const T *xi, const T *xj, const T *n, T gamma,
                                                 double *yi, double *yj, double *wo)
@@ -170,6 +209,8 @@ struct OpAdjoint {
     }
 };
 
+// ----------------------------------------------------------- plumbing -- */
+
 struct PlanPtrs {
     const int *block_off;
     const int *uniq_off;
@@ -179,6 +220,15 @@ struct PlanPtrs {
     const int *block_ncol;
     const int *colour_blocks;
     int umax;
+};
+
+struct OwnerPtrs {
+    const uint32_t *omap;
+    const int *seg_off;
+    const int *seg_start;
+    const int *seg_pre;
+    const int2 *seg_cl;
+    const int *total;
 };
 
 template <typename T>
@@ -208,38 +258,51 @@ __device__ __forceinline__ int xcd_map(int k, int n)
     return x * per + min(x, rem) + i;
 }
 
-template <typename T, class Op>
-__host__ __device__ constexpr size_t lds_x_bytes(int umax)
+__device__ __forceinline__ void lds_add(double *p, double v)
 {
-    return ((size_t)Op::NIN * umax * sizeof(T) + 15) & ~(size_t)15;
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <typename T, class Op>
-constexpr size_t lds_bytes(int umax)
+template <class Op, typename T>
+__device__ __forceinline__ void load_stage(const Arrays<T> &a, int g, T gamma, T *s)
 {
-    return lds_x_bytes<T, Op>(umax) + (size_t)Op::NOUT * umax * sizeof(double);
+    T x[Op::NIN];
+#pragma unroll
+    for (int v = 0; v < Op::NIN; ++v) x[v] = a.x[v][g];
+    Op::stage(x, s, gamma);
 }
 
-template <typename T, class Op, int NT, int EPT>
-__global__ __launch_bounds__(NT) void k_edge_lds(PlanPtrs p, Arrays<T> a, T gamma, int cbase,
-                                                 int ncb, int remap)
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+template <typename T, class Op>
+__host__ __device__ constexpr size_t stage_bytes(int rows) { return align16((size_t)Op::NS * rows * sizeof(T)); }
+
+template <typename T, class Op>
+constexpr size_t lds_bytes(int rows) { return stage_bytes<T, Op>(rows) + (size_t)Op::NOUT * rows * sizeof(double); }
+
+// ---------------------------------------------------- coloured kernel -- */
+
+template <typename T, class Op, int NT, int EPT, bool LDSAT>
+__global__ __launch_bounds__(NT) void k_edge_coloured(PlanPtrs p, Arrays<T> a, T gamma, int cbase,
+                                                      int ncb, int remap)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NY = Op::MODE == GEN ? 2 * Op::NOUT : Op::NOUT;
     const int umax = p.umax;
-    T *sx = reinterpret_cast<T *>(smem);
-    double *sy = reinterpret_cast<double *>(smem + lds_x_bytes<T, Op>(umax));
+    T *ss = reinterpret_cast<T *>(smem);
+    double *sy = reinterpret_cast<double *>(smem + stage_bytes<T, Op>(umax));
 
     const int k = remap ? xcd_map((int)blockIdx.x, ncb) : (int)blockIdx.x;
     const int b = p.colour_blocks[cbase + k];
     const int e0 = p.block_off[b], ne = p.block_off[b + 1] - e0;
     const int u0 = p.uniq_off[b], nu = p.uniq_off[b + 1] - u0;
 
-    // stage the partition's node data, clear its accumulator
+    // stage the partition's nodes, clear its accumulator
     for (int u = threadIdx.x; u < nu; u += NT) {
-        const int g = p.uniq[u0 + u];
+        T s[Op::NS];
+        load_stage<Op>(a, p.uniq[u0 + u], gamma, s);
 #pragma unroll
-        for (int v = 0; v < Op::NIN; ++v) sx[v * umax + u] = a.x[v][g];
+        for (int v = 0; v < Op::NS; ++v) ss[v * umax + u] = s[v];
 #pragma unroll
         for (int v = 0; v < Op::NOUT; ++v) sy[v * umax + u] = 0.0;
     }
@@ -257,39 +320,51 @@ __global__ __launch_bounds__(NT) void k_edge_lds(PlanPtrs p, Arrays<T> a, T gamm
             li[t] = (int)(l & 0xffffu);
             lj[t] = (int)(l >> 16);
             col[t] = p.ecol[e0 + e];
-            T xi[Op::NIN], xj[Op::NIN], n[3];
+            T si[Op::NS], sj[Op::NS], n[3];
 #pragma unroll
-            for (int v = 0; v < Op::NIN; ++v) {
-                xi[v] = sx[v * umax + li[t]];
-                xj[v] = sx[v * umax + lj[t]];
+            for (int v = 0; v < Op::NS; ++v) {
+                si[v] = ss[v * umax + li[t]];
+                sj[v] = ss[v * umax + lj[t]];
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) n[d] = a.w[d][e0 + e];
             double wo[3] = {0.0, 0.0, 0.0};
-            Op::edge(xi, xj, n, gamma, y[t], y[t] + Op::NOUT, wo);
+            Op::edge(si, sj, n, gamma, y[t], y[t] + (NY - Op::NOUT), wo);
             if (Op::NWOUT) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) a.wo[d][e0 + e] = wo[d];
             }
-        }
-    }
-
-    // increments, one edge colour at a time (same-colour edges share no node)
-    const int ncol = p.block_ncol[b];
-    for (int c = 0; c < ncol; ++c) {
-#pragma unroll
-        for (int t = 0; t < EPT; ++t) {
-            if (col[t] == c) {
+            if (LDSAT) {
 #pragma unroll
                 for (int v = 0; v < Op::NOUT; ++v) {
                     const double yi = y[t][v];
                     const double yj = Op::MODE == ANTI ? -yi : Op::MODE == SAME ? yi : y[t][Op::NOUT + v];
-                    sy[v * umax + li[t]] += yi;
-                    sy[v * umax + lj[t]] += yj;
+                    lds_add(&sy[v * umax + li[t]], yi);
+                    lds_add(&sy[v * umax + lj[t]], yj);
                 }
             }
         }
+    }
+    if (LDSAT) {
         __syncthreads();
+    } else {
+        // increments, one edge colour at a time (same-colour edges share no node)
+        const int ncol = p.block_ncol[b];
+        for (int c = 0; c < ncol; ++c) {
+#pragma unroll
+            for (int t = 0; t < EPT; ++t) {
+                if (col[t] == c) {
+#pragma unroll
+                    for (int v = 0; v < Op::NOUT; ++v) {
+                        const double yi = y[t][v];
+                        const double yj = Op::MODE == ANTI ? -yi : Op::MODE == SAME ? yi : y[t][Op::NOUT + v];
+                        sy[v * umax + li[t]] += yi;
+                        sy[v * umax + lj[t]] += yj;
+                    }
+                }
+            }
+            __syncthreads();
+        }
     }
 
     // add the partition's accumulator to HBM (no other partition of this
@@ -301,6 +376,8 @@ __global__ __launch_bounds__(NT) void k_edge_lds(PlanPtrs p, Arrays<T> a, T gamm
     }
 }
 
+// ------------------------------------------------------ atomic kernel -- */
+
 template <typename T, class Op>
 __global__ __launch_bounds__(256) void k_edge_atomic(const int2 *__restrict__ e2n, int E,
                                                      Arrays<T> a, T gamma, int remap)
@@ -309,18 +386,15 @@ __global__ __launch_bounds__(256) void k_edge_atomic(const int2 *__restrict__ e2
     const int e = blk * 256 + (int)threadIdx.x;
     if (e >= E) return;
     const int2 ij = e2n[e];
-    T xi[Op::NIN], xj[Op::NIN], n[3];
-#pragma unroll
-    for (int v = 0; v < Op::NIN; ++v) {
-        xi[v] = a.x[v][ij.x];
-        xj[v] = a.x[v][ij.y];
-    }
+    T si[Op::NS], sj[Op::NS], n[3];
+    load_stage<Op>(a, ij.x, gamma, si);
+    load_stage<Op>(a, ij.y, gamma, sj);
 #pragma unroll
     for (int d = 0; d < 3; ++d) n[d] = a.w[d][e];
     constexpr int NY = Op::MODE == GEN ? 2 * Op::NOUT : Op::NOUT;
     double y[NY];
     double wo[3] = {0.0, 0.0, 0.0};
-    Op::edge(xi, xj, n, gamma, y, y + Op::NOUT, wo);
+    Op::edge(si, sj, n, gamma, y, y + (NY - Op::NOUT), wo);
 #pragma unroll
     for (int v = 0; v < Op::NOUT; ++v) {
         const double yi = y[v];
@@ -331,6 +405,136 @@ __global__ __launch_bounds__(256) void k_edge_atomic(const int2 *__restrict__ e2
     if (Op::NWOUT) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) a.wo[d][e] = wo[d];
+    }
+}
+
+// ------------------------------------------------------- owner kernel -- */
+
+// Packed owner map: per edge two 16-bit fields (first, second endpoint); bit 15
+// says which cluster of the edge's segment (0: the smaller, 1: the larger
+// cluster id) the endpoint lies in, bits 0..14 its offset inside that cluster.
+__device__ __forceinline__ int owner_node(uint32_t f, int2 cl, int K, int &cid)
+{
+    cid = (f & 0x8000u) ? cl.y : cl.x;
+    return cid * K + (int)(f & 0x7fffu);
+}
+
+template <typename T, class Op, int NT, int B>
+__global__ __launch_bounds__(NT) void k_edge_owner(OwnerPtrs p, Arrays<T> a, T gamma, int N,
+                                                   int K, int ncl, int remap, int overwrite)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_start[kMaxClusterSegments];
+    __shared__ int s_pre[kMaxClusterSegments + 1];
+    __shared__ int2 s_cl[kMaxClusterSegments];
+    constexpr int NY = Op::MODE == GEN ? 2 * Op::NOUT : Op::NOUT;
+    T *ss = reinterpret_cast<T *>(smem);
+    double *sy = reinterpret_cast<double *>(smem + stage_bytes<T, Op>(K));
+
+    const int c = remap ? xcd_map((int)blockIdx.x, ncl) : (int)blockIdx.x;
+    const int v0 = c * K, nown = min(K, N - v0);
+    const int s0 = p.seg_off[c], ns = p.seg_off[c + 1] - s0;
+    for (int t = threadIdx.x; t < ns; t += NT) {
+        s_start[t] = p.seg_start[s0 + t];
+        s_pre[t] = p.seg_pre[s0 + t];
+        s_cl[t] = p.seg_cl[s0 + t];
+    }
+    if (threadIdx.x == 0) s_pre[ns] = p.total[c];
+    // stage the owned nodes (contiguous ids: coalesced), clear the accumulator
+    for (int v = threadIdx.x; v < nown; v += NT) {
+        T st[Op::NS];
+        load_stage<Op>(a, v0 + v, gamma, st);
+#pragma unroll
+        for (int k = 0; k < Op::NS; ++k) ss[k * K + v] = st[k];
+#pragma unroll
+        for (int k = 0; k < Op::NOUT; ++k) sy[k * K + v] = 0.0;
+    }
+    __syncthreads();
+
+    const int total = s_pre[ns];
+    // cursor over the cluster's segments; edge positions only grow
+    int sc = 0;
+    {
+        int lo = 0, hi = ns - 1;
+        const int k = min((int)threadIdx.x, max(total - 1, 0));
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pre[mid] <= k)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        sc = lo;
+    }
+    for (int k0 = threadIdx.x; k0 < total; k0 += NT * B) {
+        // resolve B edges and issue all their global loads first
+        int eid[B], sg[B];
+        uint32_t m[B];
+        T w[B][3];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int k = k0 + b * NT;
+            sg[b] = -1;
+            eid[b] = 0;
+            if (k < total) {
+                while (sc + 1 < ns && s_pre[sc + 1] <= k) ++sc;
+                sg[b] = sc;
+                eid[b] = s_start[sc] + (k - s_pre[sc]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (sg[b] >= 0) {
+                m[b] = p.omap[eid[b]];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) w[b][d] = a.w[d][eid[b]];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (sg[b] < 0) continue;
+            const int2 cl = s_cl[sg[b]];
+            int ci, cj;
+            const int gi = owner_node(m[b] & 0xffffu, cl, K, ci);
+            const int gj = owner_node(m[b] >> 16, cl, K, cj);
+            const bool oi = ci == c, oj = cj == c;
+            T si[Op::NS], sj[Op::NS];
+            if (oi) {
+#pragma unroll
+                for (int v = 0; v < Op::NS; ++v) si[v] = ss[v * K + (gi - v0)];
+            } else {
+                load_stage<Op>(a, gi, gamma, si);
+            }
+            if (oj) {
+#pragma unroll
+                for (int v = 0; v < Op::NS; ++v) sj[v] = ss[v * K + (gj - v0)];
+            } else {
+                load_stage<Op>(a, gj, gamma, sj);
+            }
+            double y[NY];
+            double wo[3] = {0.0, 0.0, 0.0};
+            Op::edge(si, sj, w[b], gamma, y, y + (NY - Op::NOUT), wo);
+#pragma unroll
+            for (int v = 0; v < Op::NOUT; ++v) {
+                const double yi = y[v];
+                const double yj = Op::MODE == ANTI ? -yi : Op::MODE == SAME ? yi : y[Op::NOUT + v];
+                if (oi) lds_add(&sy[v * K + (gi - v0)], yi);
+                if (oj) lds_add(&sy[v * K + (gj - v0)], yj);
+            }
+            // a direct output is written by the smaller cluster of the segment only
+            if (Op::NWOUT && cl.x == c) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) a.wo[d][eid[b]] = wo[d];
+            }
+        }
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < nown; v += NT) {
+#pragma unroll
+        for (int k = 0; k < Op::NOUT; ++k) {
+            double *dst = a.y[k] + v0 + v;
+            *dst = overwrite ? sy[k * K + v] : *dst + sy[k * K + v];
+        }
     }
 }
 
@@ -364,7 +568,7 @@ struct RkPtrs {
 
 template <typename T>
 __global__ __launch_bounds__(kRkThreads) void k_rk_stage(int N, RkPtrs<T> a, double alpha_dt,
-                                                         double *partial)
+                                                         double *partial, int keep_res)
 {
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int stride = (int)gridDim.x * kRkThreads;
@@ -375,7 +579,7 @@ __global__ __launch_bounds__(kRkThreads) void k_rk_stage(int N, RkPtrs<T> a, dou
             const double r = a.res[v][i];
             acc[v] += r * r;
             a.q[v][i] = (T)((double)a.q0[v][i] - alpha_dt * r / vi);
-            a.res[v][i] = 0.0;
+            if (!keep_res) a.res[v][i] = 0.0;
         }
     }
     block_sum<6>(acc, partial + 6 * blockIdx.x);
@@ -441,9 +645,9 @@ PlanPtrs plan_ptrs(const DevPlan &P)
                     P.colour_blocks, P.umax};
 }
 
-template <typename T, class Op, int NT, int EPT>
-int run_lds(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
-            const LaunchOpts &lo)
+template <typename T, class Op, int NT, int EPT, bool LDSAT>
+int run_coloured(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
+                 const LaunchOpts &lo)
 {
     const size_t lds = lds_bytes<T, Op>(P.umax);
     const Arrays<T> ta = typed<T>(a);
@@ -451,23 +655,23 @@ int run_lds(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
     for (int c = 0; c < P.nc; ++c) {
         const int n = P.colour_off[c + 1] - P.colour_off[c];
         if (n <= 0) continue;
-        hipLaunchKernelGGL((k_edge_lds<T, Op, NT, EPT>), dim3(n), dim3(NT), lds, st, pp, ta,
-                           (T)gamma, P.colour_off[c], n, lo.xcd_remap);
+        hipLaunchKernelGGL((k_edge_coloured<T, Op, NT, EPT, LDSAT>), dim3(n), dim3(NT), lds, st,
+                           pp, ta, (T)gamma, P.colour_off[c], n, lo.xcd_remap);
     }
     return (int)hipGetLastError();
 }
 
-template <typename T, class Op>
-int run_lds_bs(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
-               const LaunchOpts &lo)
+template <typename T, class Op, bool LDSAT>
+int run_coloured_bs(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
+                    const LaunchOpts &lo)
 {
     switch (P.block_size) {
-    case 64: return run_lds<T, Op, 64, 1>(P, a, gamma, st, lo);
-    case 128: return run_lds<T, Op, 128, 1>(P, a, gamma, st, lo);
-    case 256: return run_lds<T, Op, 256, 1>(P, a, gamma, st, lo);
-    case 512: return run_lds<T, Op, 256, 2>(P, a, gamma, st, lo);
-    case 1024: return run_lds<T, Op, 256, 4>(P, a, gamma, st, lo);
-    case 2048: return run_lds<T, Op, 256, 8>(P, a, gamma, st, lo);
+    case 64: return run_coloured<T, Op, 64, 1, LDSAT>(P, a, gamma, st, lo);
+    case 128: return run_coloured<T, Op, 128, 1, LDSAT>(P, a, gamma, st, lo);
+    case 256: return run_coloured<T, Op, 256, 1, LDSAT>(P, a, gamma, st, lo);
+    case 512: return run_coloured<T, Op, 256, 2, LDSAT>(P, a, gamma, st, lo);
+    case 1024: return run_coloured<T, Op, 256, 4, LDSAT>(P, a, gamma, st, lo);
+    case 2048: return run_coloured<T, Op, 256, 8, LDSAT>(P, a, gamma, st, lo);
     default: return (int)hipErrorInvalidValue;
     }
 }
@@ -484,48 +688,93 @@ int run_atomic(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t 
 }
 
 template <typename T, class Op>
-int run_edge(int variant, const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
-             const LaunchOpts &lo)
+int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
+              const LaunchOpts &lo)
 {
-    return variant == 1 ? run_atomic<T, Op>(P, a, gamma, st, lo)
-                        : run_lds_bs<T, Op>(P, a, gamma, st, lo);
+    if (!P.owner_ok || P.ncl <= 0) return (int)hipErrorInvalidValue;
+    const size_t lds = lds_bytes<T, Op>(P.K);
+    const OwnerPtrs op{P.omap, P.seg_off, P.seg_start, P.seg_pre, P.seg_cl, P.cl_total};
+    hipLaunchKernelGGL((k_edge_owner<T, Op, kOwnerThreads, kOwnerBatch>), dim3(P.ncl),
+                       dim3(kOwnerThreads), lds,
+                       st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
+    return (int)hipGetLastError();
 }
 
 template <typename T, class Op>
-int raise_limits(size_t bytes)
+int run_edge(int variant, const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
+             const LaunchOpts &lo)
+{
+    switch (variant) {
+    case V_COLOURED: return run_coloured_bs<T, Op, false>(P, a, gamma, st, lo);
+    case V_COLOURED_LDS_ATOMIC: return run_coloured_bs<T, Op, true>(P, a, gamma, st, lo);
+    case V_ATOMIC: return run_atomic<T, Op>(P, a, gamma, st, lo);
+    case V_OWNER: return run_owner<T, Op>(P, a, gamma, st, lo);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+// Lets kernel f use up to `total` bytes of LDS, static part included.
+int raise_one(const void *f, size_t total)
+{
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, f);
+    if (e != hipSuccess) return (int)e;
+    if (attr.sharedSizeBytes >= total) return 0;
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(total - attr.sharedSizeBytes));
+    return (int)e;
+}
+
+template <typename T, class Op, bool LDSAT>
+int raise_coloured(size_t bytes)
 {
     const void *fns[] = {
-        reinterpret_cast<const void *>(&k_edge_lds<T, Op, 64, 1>),
-        reinterpret_cast<const void *>(&k_edge_lds<T, Op, 128, 1>),
-        reinterpret_cast<const void *>(&k_edge_lds<T, Op, 256, 1>),
-        reinterpret_cast<const void *>(&k_edge_lds<T, Op, 256, 2>),
-        reinterpret_cast<const void *>(&k_edge_lds<T, Op, 256, 4>),
-        reinterpret_cast<const void *>(&k_edge_lds<T, Op, 256, 8>)};
+        reinterpret_cast<const void *>(&k_edge_coloured<T, Op, 64, 1, LDSAT>),
+        reinterpret_cast<const void *>(&k_edge_coloured<T, Op, 128, 1, LDSAT>),
+        reinterpret_cast<const void *>(&k_edge_coloured<T, Op, 256, 1, LDSAT>),
+        reinterpret_cast<const void *>(&k_edge_coloured<T, Op, 256, 2, LDSAT>),
+        reinterpret_cast<const void *>(&k_edge_coloured<T, Op, 256, 4, LDSAT>),
+        reinterpret_cast<const void *>(&k_edge_coloured<T, Op, 256, 8, LDSAT>)};
     for (const void *f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return (int)e;
+        int e = raise_one(f, bytes);
+        if (e) return e;
     }
     return 0;
 }
 
+template <typename T, class Op>
+int raise_all(size_t bytes)
+{
+    int rc = raise_coloured<T, Op, false>(bytes);
+    if (!rc) rc = raise_coloured<T, Op, true>(bytes);
+    if (!rc)
+        rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, kOwnerBatch>),
+                       bytes);
+    return rc;
+}
+
 }  // namespace
 
-size_t edge_lds_bytes(int op, bool fp32, int umax)
+size_t edge_lds_bytes(int op, bool fp32, int variant, int umax, int K)
 {
-    if (op == OP_ADJOINT) return lds_bytes<double, OpAdjoint>(umax);
+    if (variant == V_ATOMIC) return 0;
+    const int rows = variant == V_OWNER ? K : umax;
+    // the owner kernel also holds its segment table in static LDS
+    const size_t fixed =
+        variant == V_OWNER ? align16(sizeof(int) * (2 * kMaxClusterSegments + 1) + sizeof(int2) * kMaxClusterSegments) : 0;
+    if (op == OP_ADJOINT) return fixed + lds_bytes<double, OpAdjoint>(rows);
     if (op == OP_SPECRAD)
-        return fp32 ? lds_bytes<float, OpSpecrad>(umax) : lds_bytes<double, OpSpecrad>(umax);
-    return fp32 ? lds_bytes<float, OpFlux>(umax) : lds_bytes<double, OpFlux>(umax);
+        return fixed + (fp32 ? lds_bytes<float, OpSpecrad>(rows) : lds_bytes<double, OpSpecrad>(rows));
+    return fixed + (fp32 ? lds_bytes<float, OpFlux>(rows) : lds_bytes<double, OpFlux>(rows));
 }
 
 int set_lds_limit(size_t bytes)
 {
-    int rc = 0;
-    if (!rc) rc = raise_limits<double, OpFlux>(bytes);
-    if (!rc) rc = raise_limits<float, OpFlux>(bytes);
-    if (!rc) rc = raise_limits<double, OpSpecrad>(bytes);
-    if (!rc) rc = raise_limits<float, OpSpecrad>(bytes);
-    if (!rc) rc = raise_limits<double, OpAdjoint>(bytes);
+    int rc = raise_all<double, OpFlux>(bytes);
+    if (!rc) rc = raise_all<float, OpFlux>(bytes);
+    if (!rc) rc = raise_all<double, OpSpecrad>(bytes);
+    if (!rc) rc = raise_all<float, OpSpecrad>(bytes);
+    if (!rc) rc = raise_all<double, OpAdjoint>(bytes);
     return rc;
 }
 
@@ -548,7 +797,7 @@ int launch_edge(int op, bool fp32, int variant, const DevPlan &P, const EdgeArra
 
 template <typename T>
 static int run_rk(int N, const NodeArrays &a, double alpha_dt, double *ss, double *partial,
-                  hipStream_t st)
+                  bool keep_res, hipStream_t st)
 {
     RkPtrs<T> p;
     for (int v = 0; v < 6; ++v) {
@@ -559,16 +808,16 @@ static int run_rk(int N, const NodeArrays &a, double alpha_dt, double *ss, doubl
     p.vol = a.vol;
     const int grid = std::min(kRkBlocks, std::max(1, (N + kRkThreads - 1) / kRkThreads));
     hipLaunchKernelGGL((k_rk_stage<T>), dim3(grid), dim3(kRkThreads), 0, st, N, p, alpha_dt,
-                       partial);
+                       partial, keep_res ? 1 : 0);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, grid, partial, ss);
     return (int)hipGetLastError();
 }
 
 int launch_rk_stage(bool fp32, int N, const NodeArrays &a, double alpha_dt, double *ss,
-                    double *partial, hipStream_t st)
+                    double *partial, bool keep_res, hipStream_t st)
 {
-    return fp32 ? run_rk<float>(N, a, alpha_dt, ss, partial, st)
-                : run_rk<double>(N, a, alpha_dt, ss, partial, st);
+    return fp32 ? run_rk<float>(N, a, alpha_dt, ss, partial, keep_res, st)
+                : run_rk<double>(N, a, alpha_dt, ss, partial, keep_res, st);
 }
 
 int launch_dt_min(int N, const double *vol, const double *lam, double cfl, double *dt,

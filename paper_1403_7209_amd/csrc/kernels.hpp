@@ -11,18 +11,34 @@ namespace gpu {
 
 enum EdgeOpKind { OP_FLUX = 0, OP_ADJOINT = 1, OP_SPECRAD = 2 };
 
+// Execution variants of an edge loop (values match opf_variant).
+enum Variant { V_COLOURED = 0, V_ATOMIC = 1, V_OWNER = 2, V_COLOURED_LDS_ATOMIC = 3 };
+
+constexpr int kMaxClusterSegments = 256;
+constexpr int kOwnerThreads = 512;
+constexpr int kOwnerBatch = 4;  // edges each owner thread resolves before computing
+
 // Device copy of an execution plan (internal numbering, int32 offsets).
 struct DevPlan {
     int N = 0, E = 0, nb = 0, nc = 0, umax = 0, block_size = 0;
-    const int2 *e2n = nullptr;            // [E] endpoint pairs
-    const int *block_off = nullptr;       // [nb+1]
-    const int *uniq_off = nullptr;        // [nb+1]
-    const int *uniq = nullptr;            // [sum U]
-    const uint32_t *lidx = nullptr;       // [E] two 16-bit local indices
-    const uint8_t *ecol = nullptr;        // [E]
-    const int *block_ncol = nullptr;      // [nb]
-    const int *colour_blocks = nullptr;   // [nb]
-    std::vector<int> colour_off;          // host copy [nc+1]
+    const int2 *e2n = nullptr;           // [E] endpoint pairs
+    const int *block_off = nullptr;      // [nb+1]
+    const int *uniq_off = nullptr;       // [nb+1]
+    const int *uniq = nullptr;           // [sum U]
+    const uint32_t *lidx = nullptr;      // [E] two 16-bit local indices
+    const uint8_t *ecol = nullptr;       // [E]
+    const int *block_ncol = nullptr;     // [nb]
+    const int *colour_blocks = nullptr;  // [nb]
+    std::vector<int> colour_off;         // host copy [nc+1]
+    // owner clusters
+    int K = 0, ncl = 0;
+    bool owner_ok = false;
+    const int *seg_off = nullptr;    // [ncl+1]
+    const int *seg_start = nullptr;  // first edge of each segment
+    const int *seg_pre = nullptr;    // edges of the cluster before this segment
+    const int2 *seg_cl = nullptr;    // (smaller, larger) cluster joined by the segment
+    const int *cl_total = nullptr;   // [ncl] edges of each cluster
+    const uint32_t *omap = nullptr;  // [E] packed owner map (cluster flag + offset)
 };
 
 // Component pointers of the arrays an edge loop touches (SoA: one pointer per
@@ -35,7 +51,8 @@ struct EdgeArrays {
 };
 
 struct LaunchOpts {
-    int xcd_remap = 1;  // map consecutive partitions of a colour to one XCD
+    int xcd_remap = 1;  // give each XCD a contiguous range of partitions/clusters
+    int overwrite = 0;  // owner variant: res = sum instead of res += sum
 };
 
 // Returns 0 or a hipError_t value.
@@ -49,21 +66,21 @@ struct NodeArrays {
     void *q[6] = {};
 };
 
-// q = q0 - alpha_dt * res / vol, res = 0, ss[v] += sum res^2 (two passes,
-// deterministic).  `partial` holds kRkBlocks * 6 doubles.
+// q = q0 - alpha_dt * res / vol, ss[v] += sum res^2 (two passes, deterministic),
+// res = 0 unless keep_res.  `partial` holds kRkBlocks * 6 doubles.
 constexpr int kRkThreads = 256;
 constexpr int kRkBlocks = 2048;
 int launch_rk_stage(bool fp32, int N, const NodeArrays &a, double alpha_dt, double *ss,
-                    double *partial, hipStream_t stream);
+                    double *partial, bool keep_res, hipStream_t stream);
 
 // dt = min(dt, cfl * min_i vol_i / lam_i); `partial` holds kRkBlocks doubles.
 int launch_dt_min(int N, const double *vol, const double *lam, double cfl, double *dt,
                   double *partial, hipStream_t stream);
 
-// LDS bytes one partition of an edge loop needs.
-size_t edge_lds_bytes(int op, bool fp32, int umax);
+// LDS bytes (dynamic and static) of one workgroup of an edge loop.
+size_t edge_lds_bytes(int op, bool fp32, int variant, int umax, int K);
 
-// Raises the dynamic-LDS limit of every coloured kernel instance to `bytes`.
+// Lets every edge kernel instance use up to `bytes` of LDS in total.
 int set_lds_limit(size_t bytes);
 
 }  // namespace gpu

@@ -7,6 +7,7 @@
 // the kernel's fixed signature before launching it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -155,6 +156,50 @@ int upload_plan(opf_ctx *ctx, PlanRec &pr)
     D.block_size = P.block_size;
     D.colour_off.assign(P.colour_off.begin(), P.colour_off.end());
     int rc = OPF_OK;
+    D.K = P.cluster_size;
+    D.ncl = (int)P.nclusters();
+    D.owner_ok = P.owner_ok && D.ncl > 0;
+    std::vector<int> seg_off, seg_start, seg_pre, cl_total;
+    std::vector<int2> seg_cl;
+    std::vector<uint32_t> omap;
+    if (D.owner_ok && P.cluster_size > 32768) D.owner_ok = false;
+    if (D.owner_ok) {
+        const int K = P.cluster_size;
+        omap.resize(P.E);
+        for (int64_t k = 0; k < P.E; ++k) {
+            const int32_t a = P.e2n[2 * k], b = P.e2n[2 * k + 1];
+            const int32_t cb = std::max(a, b) / K;
+            const bool split = a / K != b / K;
+            const uint32_t fa = (uint32_t)(a % K) | ((split && a / K == cb) ? 0x8000u : 0u);
+            const uint32_t fb = (uint32_t)(b % K) | ((split && b / K == cb) ? 0x8000u : 0u);
+            omap[k] = fa | (fb << 16);
+        }
+        seg_cl.resize(P.cl_seg_start.size());
+        for (size_t t = 0; t < seg_cl.size(); ++t) {
+            const int64_t k = P.cl_seg_start[t];
+            const int32_t a = P.e2n[2 * k], b = P.e2n[2 * k + 1];
+            seg_cl[t] = make_int2(std::min(a, b) / K, std::max(a, b) / K);
+        }
+        seg_off.resize(D.ncl + 1);
+        for (int c = 0; c <= D.ncl; ++c) seg_off[c] = (int)P.cl_seg_off[c];
+        seg_start.assign(P.cl_seg_start.begin(), P.cl_seg_start.end());
+        seg_pre.resize(P.cl_seg_start.size());
+        cl_total.resize(D.ncl);
+        for (int c = 0; c < D.ncl; ++c) {
+            int acc = 0;
+            for (int64_t k = P.cl_seg_off[c]; k < P.cl_seg_off[c + 1]; ++k) {
+                seg_pre[k] = acc;
+                acc += P.cl_seg_len[k];
+            }
+            cl_total[c] = acc;
+        }
+        if (!rc) rc = upload(ctx, pr, seg_off, D.seg_off);
+        if (!rc) rc = upload(ctx, pr, seg_start, D.seg_start);
+        if (!rc) rc = upload(ctx, pr, seg_pre, D.seg_pre);
+        if (!rc) rc = upload(ctx, pr, cl_total, D.cl_total);
+        if (!rc) rc = upload(ctx, pr, seg_cl, D.seg_cl);
+        if (!rc) rc = upload(ctx, pr, omap, D.omap);
+    }
     if (!rc) rc = upload(ctx, pr, e2n, D.e2n);
     if (!rc) rc = upload(ctx, pr, block_off, D.block_off);
     if (!rc) rc = upload(ctx, pr, uniq_off, D.uniq_off);
@@ -235,7 +280,7 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
     if (nargs != want_args || !args)
         return ctx->fail(OPF_EINVAL, "expected " + std::to_string(want_args) + " arguments");
     if (ngbl != 1 || !gbls) return ctx->fail(OPF_EINVAL, "expected one global (gamma)");
-    if (variant != OPF_V_COLOURED && variant != OPF_V_ATOMIC)
+    if (variant < OPF_V_COLOURED || variant > OPF_V_COLOURED_LDS_ATOMIC)
         return ctx->fail(OPF_EINVAL, "unknown variant");
     const opf_map m = args[0].map;
     if (!ctx->map_ok(m)) return ctx->fail(OPF_EINVAL, "argument 0: invalid map");
@@ -261,6 +306,15 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
     } else {
         w.push_back({nodes, 0, m, yd, OPF_F64, OPF_INC});
         w.push_back({nodes, 1, m, yd, OPF_F64, OPF_INC});
+    }
+    // The owner variant writes every node's total exactly once, so it also
+    // accepts WRITE on the node increments (res = sum, no prior zeroing).
+    const int yslot = kernel == OPF_K_EDGE_FLUX_ADJ ? 5 : 3;
+    bool overwrite = false;
+    if (variant == OPF_V_OWNER && args[yslot].access == OPF_WRITE &&
+        args[yslot + 1].access == OPF_WRITE) {
+        w[yslot].access = w[yslot + 1].access = OPF_WRITE;
+        overwrite = true;
     }
     for (int k = 0; k < nargs && !rc; ++k) rc = check_arg(ctx, args[k], w[k], k);
     if (rc) return rc;
@@ -289,11 +343,14 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
                    : kernel == OPF_K_EDGE_FLUX_ADJ ? opf::gpu::OP_ADJOINT
                                                    : opf::gpu::OP_SPECRAD;
     const bool fp32 = T == OPF_F32;
-    if (variant == OPF_V_COLOURED) {
-        const size_t lds = opf::gpu::edge_lds_bytes(op, fp32, pr.dev.umax);
+    if (variant == OPF_V_OWNER && !pr.dev.owner_ok)
+        return ctx->fail(OPF_EINVAL, "the plan has no owner clusters (cluster_size 0, or a "
+                                     "cluster touching more than 256 edge segments)");
+    if (variant != OPF_V_ATOMIC) {
+        const size_t lds = opf::gpu::edge_lds_bytes(op, fp32, variant, pr.dev.umax, pr.dev.K);
         if (lds > ctx->max_lds)
-            return ctx->fail(OPF_EINVAL, "partition needs " + std::to_string(lds) +
-                                             " B of LDS; use a smaller block size");
+            return ctx->fail(OPF_EINVAL, "a workgroup needs " + std::to_string(lds) +
+                                             " B of LDS; use a smaller block or cluster size");
         if (lds > ctx->lds_limit) {
             int e = opf::gpu::set_lds_limit(ctx->max_lds);
             if (e) return hip_fail(ctx, (hipError_t)e, "raising the LDS limit");
@@ -317,6 +374,7 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
     }
     const double gamma = *static_cast<const double *>(gbls[0].ptr);
     opf::gpu::LaunchOpts lo;
+    lo.overwrite = overwrite ? 1 : 0;
     int e = opf::gpu::launch_edge(op, fp32, variant, pr.dev, ea, gamma, st, lo);
     if (e) return hip_fail(ctx, (hipError_t)e, "edge loop launch");
     return OPF_OK;
@@ -331,8 +389,9 @@ int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *a
         if (ngbl != 2 || !gbls) return ctx->fail(OPF_EINVAL, "expected 2 globals");
         if (!ctx->dat_ok(args[0].dat)) return ctx->fail(OPF_EINVAL, "argument 0: invalid dat");
         const int T = ctx->dats[args[0].dat].type;
+        const bool keep_res = args[1].access == OPF_READ;
         const Want w[4] = {{s, -1, OPF_ID, 6, T, OPF_READ},
-                           {s, -1, OPF_ID, 6, OPF_F64, OPF_RW},
+                           {s, -1, OPF_ID, 6, OPF_F64, keep_res ? OPF_READ : OPF_RW},
                            {s, -1, OPF_ID, 1, OPF_F64, OPF_READ},
                            {s, -1, OPF_ID, 6, T, OPF_WRITE}};
         for (int k = 0; k < 4 && !rc; ++k) rc = check_arg(ctx, args[k], w[k], k);
@@ -354,7 +413,8 @@ int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *a
         na.vol = static_cast<const double *>(vol.ptr);
         const double adt = *static_cast<const double *>(gbls[0].ptr);
         int e = opf::gpu::launch_rk_stage(T == OPF_F32, (int)ctx->sets[s].size, na, adt,
-                                          static_cast<double *>(gbls[1].ptr), ctx->scratch, st);
+                                          static_cast<double *>(gbls[1].ptr), ctx->scratch,
+                                          keep_res, st);
         if (e) return hip_fail(ctx, (hipError_t)e, "RK stage launch");
         return OPF_OK;
     }
@@ -394,8 +454,8 @@ int opf_init(opf_ctx **out, int hip_device)
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return OPF_EDEVICE;
         ctx->max_lds = prop.sharedMemPerBlock;
-        if (prop.maxSharedMemoryPerMultiProcessor > ctx->max_lds)
-            ctx->max_lds = std::min<size_t>(prop.maxSharedMemoryPerMultiProcessor, 160 * 1024);
+        ctx->lds_limit = prop.sharedMemPerBlock;
+        if (prop.sharedMemPerBlockOptin > ctx->max_lds) ctx->max_lds = prop.sharedMemPerBlockOptin;
     }
     ctx->device = hip_device;
     *out = ctx.release();
@@ -502,6 +562,8 @@ int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info
         po.renumber = opts->renumber;
         po.block_size = opts->block_size;
         po.colour_sort = opts->colour_sort;
+        po.cluster_size = opts->cluster_size;
+        po.lane_groups = opts->lane_groups;
         po.coords = opts->coords;
     }
     auto t0 = std::chrono::steady_clock::now();
@@ -548,6 +610,10 @@ int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info
         info->bandwidth_after = P.bandwidth_after;
         info->plan_seconds = secs;
         info->device_bytes = pr->device_bytes;
+        info->nclusters = P.nclusters();
+        info->owner_edge_visits = P.owner_edge_visits;
+        info->max_cluster_segments = P.max_cluster_segments;
+        info->owner_ok = P.owner_ok ? 1 : 0;
     }
     ctx->plans[map] = std::move(pr);
     return OPF_OK;
@@ -590,6 +656,11 @@ int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out)
     out->unique_offsets = P.uniq_off.data();
     out->unique_nodes = P.uniq.data();
     out->local_idx = P.lidx.data();
+    out->cluster_size = P.cluster_size;
+    out->nclusters = P.nclusters();
+    out->cluster_seg_offsets = P.cl_seg_off.data();
+    out->cluster_seg_start = P.cl_seg_start.data();
+    out->cluster_seg_len = P.cl_seg_len.data();
     return OPF_OK;
 }
 
@@ -647,7 +718,7 @@ int opf_par_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *
 }
 
 int opf_edge_flux(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n, opf_dat res,
-                  double gamma, int variant, void *stream)
+                  double gamma, int variant, int res_access, void *stream)
 {
     if (!ctx) return OPF_EINVAL;
     if (!ctx->dat_ok(q) || !ctx->dat_ok(n) || !ctx->dat_ok(res))
@@ -656,23 +727,23 @@ int opf_edge_flux(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n
     const opf_arg a[5] = {{q, 0, e2n, 6, T, OPF_READ},
                           {q, 1, e2n, 6, T, OPF_READ},
                           {n, -1, OPF_ID, 3, TN, OPF_READ},
-                          {res, 0, e2n, 6, OPF_F64, OPF_INC},
-                          {res, 1, e2n, 6, OPF_F64, OPF_INC}};
+                          {res, 0, e2n, 6, OPF_F64, res_access},
+                          {res, 1, e2n, 6, OPF_F64, res_access}};
     const opf_gbl g[1] = {{&gamma, 1, OPF_F64, OPF_READ, 0}};
     return opf_par_loop(ctx, OPF_K_EDGE_FLUX, edges, 5, a, 1, g, variant, stream);
 }
 
 int opf_edge_flux_adjoint(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
                           opf_dat rbar, opf_dat qbar, opf_dat nbar, double gamma, int variant,
-                          void *stream)
+                          int qbar_access, void *stream)
 {
     if (!ctx) return OPF_EINVAL;
     if (!ctx->dat_ok(q) || !ctx->dat_ok(n)) return ctx->fail(OPF_EINVAL, "invalid dat handle");
     const int T = ctx->dats[q].type, TN = ctx->dats[n].type;
     const opf_arg a[8] = {{q, 0, e2n, 6, T, OPF_READ},          {q, 1, e2n, 6, T, OPF_READ},
                           {n, -1, OPF_ID, 3, TN, OPF_READ},       {rbar, 0, e2n, 6, OPF_F64, OPF_READ},
-                          {rbar, 1, e2n, 6, OPF_F64, OPF_READ},   {qbar, 0, e2n, 6, OPF_F64, OPF_INC},
-                          {qbar, 1, e2n, 6, OPF_F64, OPF_INC},    {nbar, -1, OPF_ID, 3, OPF_F64, OPF_WRITE}};
+                          {rbar, 1, e2n, 6, OPF_F64, OPF_READ},   {qbar, 0, e2n, 6, OPF_F64, qbar_access},
+                          {qbar, 1, e2n, 6, OPF_F64, qbar_access}, {nbar, -1, OPF_ID, 3, OPF_F64, OPF_WRITE}};
     const opf_gbl g[1] = {{&gamma, 1, OPF_F64, OPF_READ, 0}};
     return opf_par_loop(ctx, OPF_K_EDGE_FLUX_ADJ, edges, 8, a, 1, g, variant, stream);
 }
@@ -693,13 +764,13 @@ int opf_edge_specrad(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_da
 }
 
 int opf_rk_stage(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol, opf_dat q,
-                 double alpha_dt, double *ss_dev, void *stream)
+                 double alpha_dt, double *ss_dev, int res_access, void *stream)
 {
     if (!ctx) return OPF_EINVAL;
     if (!ctx->dat_ok(q0)) return ctx->fail(OPF_EINVAL, "invalid dat handle");
     const int T = ctx->dats[q0].type;
     const opf_arg a[4] = {{q0, -1, OPF_ID, 6, T, OPF_READ},
-                          {res, -1, OPF_ID, 6, OPF_F64, OPF_RW},
+                          {res, -1, OPF_ID, 6, OPF_F64, res_access},
                           {vol, -1, OPF_ID, 1, OPF_F64, OPF_READ},
                           {q, -1, OPF_ID, 6, T, OPF_WRITE}};
     const opf_gbl g[2] = {{&alpha_dt, 1, OPF_F64, OPF_READ, 0}, {ss_dev, 6, OPF_F64, OPF_INC, 1}};

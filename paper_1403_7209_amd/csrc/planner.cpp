@@ -169,6 +169,11 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
         err = "block_size must be a power of two in [64, 2048]";
         return OPF_EINVAL;
     }
+    const int K = opt.cluster_size;
+    if (K != 0 && (K < 64 || K > 4096)) {
+        err = "cluster_size must be 0 (no owner clusters) or in [64, 4096]";
+        return OPF_EINVAL;
+    }
     if (opt.renumber < 0 || opt.renumber > 2) {
         err = "unknown renumbering method";
         return OPF_EINVAL;
@@ -190,6 +195,7 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
     P.N = N;
     P.E = E;
     P.block_size = BS;
+    P.cluster_size = K;
 
     auto t0 = std::chrono::steady_clock::now();
     auto lap = [&](int k) {
@@ -233,6 +239,13 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
         for (int64_t i = 0; i < N; ++i)
             std::sort(order.begin() + cnt[i], order.begin() + cnt[i + 1],
                       [&](int32_t x, int32_t y) { return hi(x) != hi(y) ? hi(x) < hi(y) : x < y; });
+        // group the edges of each cluster of smaller endpoints by the cluster of
+        // their larger endpoint: one contiguous segment per cluster pair
+        for (int64_t c0 = 0; K > 0 && c0 < N; c0 += K) {
+            const int64_t c1 = std::min<int64_t>(c0 + K, N);
+            std::stable_sort(order.begin() + cnt[c0], order.begin() + cnt[c1],
+                             [&](int32_t x, int32_t y) { return hi(x) / K < hi(y) / K; });
+        }
     }
     P.e2n.resize(2 * E);
     for (int64_t k = 0; k < E; ++k) {
@@ -241,6 +254,66 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
     }
 
     lap(1);
+    // (2b) inside each cluster-pair segment, order edges into groups of 64 that
+    // share no node (first fit over up to 64 x 64 open groups), so that the 64
+    // lanes of a wavefront running 64 consecutive edges update 128 distinct nodes
+    if (K > 0 && opt.lane_groups) {
+        std::vector<uint64_t> mask(N, 0);  // per node: groups of the current window
+        std::vector<int32_t> touched, grp_of, ord;
+        std::vector<int32_t> gsize;
+        int64_t k = 0;
+        while (k < E) {
+            auto key = [&](int64_t t) {
+                const int32_t a = P.node_new[e2n_user[2 * order[t]]], b = P.node_new[e2n_user[2 * order[t] + 1]];
+                return std::make_pair(std::min(a, b) / K, std::max(a, b) / K);
+            };
+            const auto kk = key(k);
+            int64_t k1 = k + 1;
+            while (k1 < E && key(k1) == kk) ++k1;
+            const int64_t n = k1 - k;
+            if (n > 64) {
+                grp_of.assign(n, -1);
+                int base = 0;  // first group of the current window of 64 groups
+                int64_t left = n;
+                while (left > 0) {
+                    gsize.assign(64, 0);
+                    uint64_t full = 0;
+                    for (int32_t v : touched) mask[v] = 0;
+                    touched.clear();
+                    for (int64_t t = 0; t < n && full != ~0ULL; ++t) {
+                        if (grp_of[t] >= 0) continue;
+                        const int32_t a = P.node_new[e2n_user[2 * order[k + t]]];
+                        const int32_t b = P.node_new[e2n_user[2 * order[k + t] + 1]];
+                        const uint64_t busy = mask[a] | mask[b] | full;
+                        if (busy == ~0ULL) continue;
+                        const int g = __builtin_ctzll(~busy);
+                        if (!mask[a]) touched.push_back(a);
+                        if (!mask[b]) touched.push_back(b);
+                        mask[a] |= 1ULL << g;
+                        mask[b] |= 1ULL << g;
+                        if (++gsize[g] == 64) full |= 1ULL << g;
+                        grp_of[t] = base + g;
+                        --left;
+                    }
+                    base += 64;
+                }
+                for (int32_t v : touched) mask[v] = 0;
+                touched.clear();
+                ord.resize(n);
+                std::iota(ord.begin(), ord.end(), 0);
+                std::stable_sort(ord.begin(), ord.end(),
+                                 [&](int32_t x, int32_t y) { return grp_of[x] < grp_of[y]; });
+                std::vector<int32_t> tmp(order.begin() + k, order.begin() + k1);
+                for (int64_t t = 0; t < n; ++t) order[k + t] = tmp[ord[t]];
+            }
+            k = k1;
+        }
+        for (int64_t t = 0; t < E; ++t) {
+            P.e2n[2 * t] = P.node_new[e2n_user[2 * order[t]]];
+            P.e2n[2 * t + 1] = P.node_new[e2n_user[2 * order[t] + 1]];
+        }
+    }
+
     // (3) mini-partitions of consecutive edges
     const int64_t nb = (E + BS - 1) / BS;
     P.block_off.resize(nb + 1);
@@ -325,6 +398,47 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
     }
     P.edge_new.resize(E);
     for (int64_t k = 0; k < E; ++k) P.edge_new[order[k]] = (int32_t)k;
+
+    // owner clusters: segments of constant (cluster(min), cluster(max)); a
+    // partition may have reordered edges by colour, so segments are formed on
+    // the final order and a pair may yield more than one segment
+    if (K > 0) {
+        const int64_t ncl = P.nclusters();
+        std::vector<std::vector<std::pair<int32_t, int32_t>>> segs(ncl);
+        int64_t k = 0;
+        while (k < E) {
+            const int32_t a = std::min(P.e2n[2 * k], P.e2n[2 * k + 1]) / K;
+            const int32_t b = std::max(P.e2n[2 * k], P.e2n[2 * k + 1]) / K;
+            int64_t k1 = k + 1;
+            while (k1 < E && std::min(P.e2n[2 * k1], P.e2n[2 * k1 + 1]) / K == a &&
+                   std::max(P.e2n[2 * k1], P.e2n[2 * k1 + 1]) / K == b)
+                ++k1;
+            const std::pair<int32_t, int32_t> sg((int32_t)k, (int32_t)(k1 - k));
+            if (a == b)
+                segs[a].insert(segs[a].begin(), sg);
+            else {
+                segs[a].push_back(sg);
+                segs[b].push_back(sg);
+            }
+            k = k1;
+        }
+        P.cl_seg_off.assign(ncl + 1, 0);
+        P.max_cluster_segments = 0;
+        for (int64_t c = 0; c < ncl; ++c) {
+            P.cl_seg_off[c + 1] = P.cl_seg_off[c] + (int64_t)segs[c].size();
+            P.max_cluster_segments = std::max<int32_t>(P.max_cluster_segments, (int32_t)segs[c].size());
+        }
+        P.cl_seg_start.resize(P.cl_seg_off[ncl]);
+        P.cl_seg_len.resize(P.cl_seg_off[ncl]);
+        P.owner_edge_visits = 0;
+        for (int64_t c = 0; c < ncl; ++c)
+            for (size_t s = 0; s < segs[c].size(); ++s) {
+                P.cl_seg_start[P.cl_seg_off[c] + s] = segs[c][s].first;
+                P.cl_seg_len[P.cl_seg_off[c] + s] = segs[c][s].second;
+                P.owner_edge_visits += segs[c][s].second;
+            }
+        P.owner_ok = P.max_cluster_segments <= kMaxClusterSegments;
+    }
     lap(2);
 
     // (4) colour the partitions greedily: lowest colour unused by any partition
@@ -493,6 +607,31 @@ VerifyResult verify_plan(const Plan &P, const int32_t *e2n_user)
                 lm[li] |= bit;
                 lm[lj] |= bit;
             }
+        }
+    }
+    // (8) owner clusters: every edge is in the work of exactly the clusters of
+    // its two endpoints (once when both are in one cluster)
+    if (P.cluster_size > 0) {
+        const int K = P.cluster_size;
+        const int64_t ncl = P.nclusters();
+        if ((int64_t)P.cl_seg_off.size() != ncl + 1 || P.cl_seg_off[0] != 0 ||
+            P.cl_seg_off[ncl] != (int64_t)P.cl_seg_start.size())
+            return fail(8, -1, "cluster segment offsets are inconsistent");
+        std::vector<uint8_t> seen(E, 0);
+        for (int64_t c = 0; c < ncl; ++c)
+            for (int64_t s = P.cl_seg_off[c]; s < P.cl_seg_off[c + 1]; ++s) {
+                const int64_t k0 = P.cl_seg_start[s], n = P.cl_seg_len[s];
+                if (k0 < 0 || n < 1 || k0 + n > E) return fail(8, c, "segment outside the edge set");
+                for (int64_t k = k0; k < k0 + n; ++k) {
+                    const int64_t a = P.e2n[2 * k] / K, b = P.e2n[2 * k + 1] / K;
+                    if (a != c && b != c) return fail(8, k, "edge listed for a cluster it does not touch");
+                    if (seen[k] == 255) return fail(8, k, "edge listed too often");
+                    ++seen[k];
+                }
+            }
+        for (int64_t k = 0; k < E; ++k) {
+            const int want = (P.e2n[2 * k] / K == P.e2n[2 * k + 1] / K) ? 1 : 2;
+            if (seen[k] != want) return fail(8, k, "edge missing from its clusters' work");
         }
     }
     return r;

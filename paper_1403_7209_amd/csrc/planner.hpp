@@ -16,10 +16,15 @@ namespace opf {
 
 constexpr int kMaxBlockColours = 1024;
 
+constexpr int kMaxClusterSegments = 256;
+
 struct PlanOptions {
     int renumber = 1;  // 0 none, 1 RCM, 2 Morton
     int block_size = 512;
     int colour_sort = 0;
+    int cluster_size = 512;          // nodes per owner cluster; 0 = no owner clusters
+    int lane_groups = 1;             // reorder each cluster-pair segment into groups of
+                                     // 64 edges that share no node
     const double *coords = nullptr;  // SoA 3 x N
 };
 
@@ -45,6 +50,18 @@ struct Plan {
     int32_t min_blocks_per_colour = 0;
     int64_t bandwidth_before = 0, bandwidth_after = 0;
     double phase_seconds[4] = {0, 0, 0, 0};  // renumber, edge order, partitions, colours
+    // Owner clusters: cluster c owns internal nodes [c*K, min((c+1)*K, N)).
+    // Edges are ordered so that those joining clusters (x, y), x <= y, form one
+    // contiguous segment; cluster c's work is every segment with x == c or
+    // y == c, the (c, c) segment first.
+    int32_t cluster_size = 0;
+    int32_t max_cluster_segments = 0;
+    bool owner_ok = false;              // every cluster fits kMaxClusterSegments
+    std::vector<int64_t> cl_seg_off;    // [ncl+1] into cl_seg_start / cl_seg_len
+    std::vector<int32_t> cl_seg_start;  // first internal edge of each segment
+    std::vector<int32_t> cl_seg_len;    // edges in the segment
+    int64_t owner_edge_visits = 0;      // sum over clusters of their edges
+    int64_t nclusters() const { return cluster_size ? (N + cluster_size - 1) / cluster_size : 0; }
     int64_t nblocks() const { return (int64_t)block_colour.size(); }
 };
 

@@ -21,11 +21,20 @@ DEV = "cuda:0"
 TOL64, TOL32 = 1e-12, 1e-5
 
 
-def problem(m, q, fp32=False, renumber="rcm", block_size=512, colour_sort=False):
+ALL_VARIANTS = (pk.COLOURED, pk.ATOMIC, pk.OWNER, pk.COLOURED_LDS_ATOMIC)
+
+
+def problem(m, q, fp32=False, renumber="rcm", block_size=512, colour_sort=False,
+            cluster_size=512, lane_groups=True):
     ctx = pk.Context(DEV)
     coords = m.xyz if renumber == "morton" else None
     return pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, fp32=fp32, renumber=renumber,
-                          block_size=block_size, colour_sort=colour_sort, coords=coords)
+                          block_size=block_size, colour_sort=colour_sort, coords=coords,
+                          cluster_size=cluster_size, lane_groups=lane_groups)
+
+
+def variants(p):
+    return [v for v in ALL_VARIANTS if v != pk.OWNER or p.info["owner_ok"]]
 
 
 def gpu_residual(p, variant):
@@ -35,14 +44,14 @@ def gpu_residual(p, variant):
     return p.nodes_out(res)
 
 
-@pytest.mark.parametrize("variant", [pk.COLOURED, pk.ATOMIC], ids=["coloured", "atomic"])
+@pytest.mark.parametrize("variant", ALL_VARIANTS, ids=["coloured", "atomic", "owner", "ldsatomic"])
 @pytest.mark.parametrize("case", flux_hand_cases(), ids=lambda c: c[0])
 def test_two_node_hand_cases(case, variant):
     name, qi, qj, n, F = case
     print(f"[two-node {name}]", flush=True)
     ctx = pk.Context(DEV)
     p = pk.FluxProblem(ctx, np.array([[0, 1]], np.int32), n.reshape(3, 1), np.ones(2),
-                       np.stack([qi, qj], 1), block_size=64)
+                       np.stack([qi, qj], 1), block_size=64, cluster_size=64)
     res = gpu_residual(p, variant)
     assert np.abs(res[:, 0] - F).max() <= 1e-14 * np.abs(F).max()
     assert np.array_equal(res[:, 1], -res[:, 0])
@@ -65,21 +74,41 @@ def small(request):
     return request.param, m, q, res
 
 
-@pytest.mark.parametrize("renumber,bs,csort", [("rcm", 512, False), ("rcm", 64, True),
-                                               ("morton", 2048, False), ("none", 256, False)])
-def test_residual_small(small, renumber, bs, csort):
+@pytest.mark.parametrize("renumber,bs,csort,K,lg", [("rcm", 512, False, 512, True),
+                                                    ("rcm", 64, True, 64, True),
+                                                    ("morton", 2048, False, 1024, False),
+                                                    ("morton", 256, False, 0, False),
+                                                    ("none", 256, False, 128, True)])
+def test_residual_small(small, renumber, bs, csort, K, lg):
     name, m, q, ref = small
-    print(f"[residual {name} {renumber} bs={bs} sort={csort}]", flush=True)
-    p = problem(m, q, renumber=renumber, block_size=bs, colour_sort=csort)
-    for variant in (pk.COLOURED, pk.ATOMIC):
+    print(f"[residual {name} {renumber} bs={bs} sort={csort} K={K} groups={lg}]", flush=True)
+    p = problem(m, q, renumber=renumber, block_size=bs, colour_sort=csort, cluster_size=K,
+                lane_groups=lg)
+    assert p.info["owner_ok"] == (K > 0 and p.info["max_cluster_segments"] <= 256)
+    for variant in variants(p):
         res = gpu_residual(p, variant)
         assert report(f"variant {variant}", normwise(res, ref), TOL64)
     # OP_INC accumulates into what is already there
-    res = torch.zeros((6, p.N), dtype=torch.float64, device=DEV)
-    p.residual(p.qa, res)
-    p.residual(p.qa, res)
-    p.ctx.sync()
-    assert normwise(p.nodes_out(res), 2 * ref) <= TOL64
+    for variant in variants(p):
+        res = torch.zeros((6, p.N), dtype=torch.float64, device=DEV)
+        p.residual(p.qa, res, variant)
+        p.residual(p.qa, res, variant)
+        p.ctx.sync()
+        assert normwise(p.nodes_out(res), 2 * ref) <= TOL64
+    if p.info["owner_ok"]:
+        # WRITE overwrites whatever the residual held
+        res = torch.full((6, p.N), 1e30, dtype=torch.float64, device=DEV)
+        p.residual(p.qa, res, pk.OWNER, res_access=pk.WRITE)
+        p.ctx.sync()
+        assert report("owner WRITE", normwise(p.nodes_out(res), ref), TOL64)
+    else:
+        with pytest.raises(pk.OpfError):
+            gpu_residual(p, pk.OWNER)
+    # WRITE is refused where a node's total is not formed in one place
+    with pytest.raises(pk.OpfError) as e:
+        p.residual(p.qa, torch.zeros((6, p.N), dtype=torch.float64, device=DEV), pk.COLOURED,
+                   res_access=pk.WRITE)
+    assert e.value.status == pk.EACCESS
 
 
 def test_coloured_is_bitwise_deterministic(small):
@@ -113,7 +142,7 @@ def test_time_step(small):
     name, m, q, _ = small
     p = problem(m, q)
     dt_ref = oracle.dt(m.e2n, q, m.w, m.vol)
-    for variant in (pk.COLOURED, pk.ATOMIC):
+    for variant in variants(p):
         dt = p.compute_dt(0.5, variant)
         assert abs(dt - dt_ref) <= TOL64 * dt_ref
 
@@ -127,7 +156,7 @@ def test_rk_iteration(small):
     for _ in range(2):
         q_ref, s = oracle.rk_iteration(m.e2n, q_ref, m.w, m.vol, dt)
         ss_ref.append(s)
-    for variant in (pk.COLOURED, pk.ATOMIC):
+    for variant in ALL_VARIANTS:
         p = problem(m, q)
         for it in range(2):
             p.rk_iteration(dt, variant)
@@ -143,15 +172,17 @@ def test_fp32_storage_stage(small):
     w32 = m.w.astype(np.float32).astype(np.float64)
     ref = oracle.residual(m.e2n, q32, w32)
     p = problem(m, q, fp32=True)
-    for variant in (pk.COLOURED, pk.ATOMIC):
+    for variant in variants(p):
         res = gpu_residual(p, variant)
         assert report(f"fp32 residual v{variant}", normwise(res, ref), TOL32)
     dt = oracle.dt(m.e2n, q32, w32, m.vol)
     q1_ref, ss_ref = oracle.rk_iteration(m.e2n, q32, w32, m.vol, dt)
-    p.rk_iteration(dt)
-    p.ctx.sync()
-    assert report("fp32 state", normwise(p.nodes_out(p.qa), q1_ref), TOL32)
-    assert report("fp32 rms", normwise(p.rms(), np.sqrt(ss_ref / m.N)), TOL32)
+    for variant in (pk.COLOURED, pk.OWNER):
+        p = problem(m, q, fp32=True)
+        p.rk_iteration(dt, variant)
+        p.ctx.sync()
+        assert report(f"fp32 state v{variant}", normwise(p.nodes_out(p.qa), q1_ref), TOL32)
+        assert report(f"fp32 rms v{variant}", normwise(p.rms(), np.sqrt(ss_ref / m.N)), TOL32)
 
 
 def test_adjoint(small):
@@ -161,7 +192,7 @@ def test_adjoint(small):
     qbar_ref, wbar_ref = oracle.adjoint(m.e2n, q, m.w, rbar)
     p = problem(m, q)
     rb = p.nodes_in(rbar)
-    for variant in (pk.COLOURED, pk.ATOMIC):
+    for variant in variants(p):
         qbar = torch.zeros((6, p.N), dtype=torch.float64, device=DEV)
         nbar = torch.empty((3, p.E), dtype=torch.float64, device=DEV)
         p.ctx.edge_flux_adjoint(p.edges, p.e2n, p.dat(p.qa), p.w, p.dat(rb), p.dat(qbar),
@@ -169,6 +200,14 @@ def test_adjoint(small):
         p.ctx.sync()
         assert report(f"qbar v{variant}", normwise(p.nodes_out(qbar), qbar_ref), TOL64)
         assert report(f"nbar v{variant}", normwise(p.nodes_out(nbar, edges=True), wbar_ref), TOL64)
+    if p.info["owner_ok"]:
+        qbar = torch.full((6, p.N), -7.0, dtype=torch.float64, device=DEV)
+        nbar = torch.full((3, p.E), -7.0, dtype=torch.float64, device=DEV)
+        p.ctx.edge_flux_adjoint(p.edges, p.e2n, p.dat(p.qa), p.w, p.dat(rb), p.dat(qbar),
+                                p.dat(nbar, edges=True), p.gamma, pk.OWNER, pk.WRITE)
+        p.ctx.sync()
+        assert report("qbar owner WRITE", normwise(p.nodes_out(qbar), qbar_ref), TOL64)
+        assert normwise(p.nodes_out(nbar, edges=True), wbar_ref) <= TOL64
 
 
 def test_autograd_dot_product_and_gradcheck():
@@ -206,6 +245,16 @@ def test_argument_checks_on_device():
     with pytest.raises(pk.OpfError) as e:  # q must not alias q0
         p.ctx.rk_stage(p.nodes, p.dat(p.qa), p.res_d, p.vol, p.dat(p.qa), 0.1, ss)
     assert e.value.status == pk.EINVAL
+    with pytest.raises(pk.OpfError) as e:  # the stage never increments the residual
+        p.ctx.rk_stage(p.nodes, p.dat(p.qa), p.res_d, p.vol, p.dat(p.qb), 0.1, ss,
+                       res_access=pk.INC)
+    assert e.value.status == pk.EACCESS
+    # READ leaves the residual in place for a following WRITE edge loop
+    res = torch.ones((6, p.N), dtype=torch.float64, device=DEV)
+    p.ctx.rk_stage(p.nodes, p.dat(p.qa), p.dat(res), p.vol, p.dat(p.qb), 0.1, ss,
+                   res_access=pk.READ)
+    p.ctx.sync()
+    assert bool((res == 1.0).all())
     nanq = p.qa.clone()
     nanq[0, 0] = float("nan")
     res = torch.zeros((6, p.N), dtype=torch.float64, device=DEV)

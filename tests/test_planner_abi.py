@@ -1,0 +1,263 @@
+"""Host-side tests of the C ABI: exports, declarations, the planner's integer
+properties (checked here independently of the library's own verifier) and
+the error paths that need no GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import meshgen
+import paper_1403_7209_amd as pk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "opflux.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(opf_\w+)\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(pk.LIB_PATH)
+    names = declared_symbols()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(pk.SYMBOLS)
+
+
+def host_problem(m, **kw):
+    ctx = pk.Context(None)
+    nodes = ctx.decl_set(m.N, "nodes")
+    edges = ctx.decl_set(m.E, "edges")
+    mp = ctx.decl_map(edges, nodes, 2, m.e2n, 0, "e2n")
+    info = ctx.plan(mp, coords=m.xyz, **kw)
+    return ctx, nodes, edges, mp, info
+
+
+def check_plan_properties(m, ctx, nodes, edges, mp):
+    """Independent numpy check of the plan's properties 1-8."""
+    v = ctx.plan_view(mp)
+    node_new = ctx.get_perm(nodes, m.N)
+    edge_new = ctx.get_perm(edges, m.E)
+    # 1, 2: bijections; the internal map is the relabelled user map, orientation kept
+    assert np.array_equal(np.sort(node_new), np.arange(m.N))
+    assert np.array_equal(np.sort(edge_new), np.arange(m.E))
+    e2n = v["e2n"]
+    assert np.array_equal(e2n[edge_new], node_new[m.e2n])
+    # 5: partitions are contiguous edge ranges of at most block_size edges
+    off = v["block_offsets"]
+    assert off[0] == 0 and off[-1] == m.E
+    sizes = np.diff(off)
+    assert sizes.min() >= 1 and sizes.max() <= v["block_size"]
+    bcol = v["block_colour"]
+    coff = v["colour_offsets"]
+    assert np.array_equal(np.sort(v["colour_blocks"]), np.arange(v["nblocks"]))
+    for c in range(v["nblock_colours"]):
+        blocks = v["colour_blocks"][coff[c]:coff[c + 1]]
+        assert len(blocks) > 0 and np.all(bcol[blocks] == c)
+    blk_of_edge = np.repeat(np.arange(v["nblocks"]), sizes)
+    # 6: local indices resolve to the map's nodes
+    uoff = v["unique_offsets"]
+    uniq = v["unique_nodes"]
+    loc = v["local_idx"].astype(np.int64)
+    for s in range(2):
+        assert np.array_equal(uniq[uoff[blk_of_edge] + loc[:, s]], e2n[:, s])
+    # 3: partitions of one colour share no node
+    pair_col = np.repeat(bcol, np.diff(uoff))
+    key = pair_col.astype(np.int64) * m.N + uniq
+    assert len(np.unique(key)) == len(key)
+    # 4: inside a partition, edges of one colour share no node
+    ecol = v["elem_colour"].astype(np.int64)
+    both = np.concatenate([e2n[:, 0], e2n[:, 1]]).astype(np.int64)
+    k4 = (np.concatenate([blk_of_edge, blk_of_edge]) * 256 + np.concatenate([ecol, ecol])) * m.N + both
+    assert len(np.unique(k4)) == len(k4)
+    assert np.all(ecol < v["block_ncolours"][blk_of_edge])
+    # 8: every edge is run by exactly the owner clusters of its endpoints
+    K = v["cluster_size"]
+    if K:
+        cnt = np.zeros(m.E, np.int64)
+        soff = v["cluster_seg_offsets"]
+        st, ln = v["cluster_seg_start"], v["cluster_seg_len"]
+        for c in range(v["nclusters"]):
+            for s in range(soff[c], soff[c + 1]):
+                ks = np.arange(st[s], st[s] + ln[s])
+                cl = e2n[ks] // K
+                assert np.all((cl[:, 0] == c) | (cl[:, 1] == c))
+                cnt[ks] += 1
+        want = np.where(e2n[:, 0] // K == e2n[:, 1] // K, 1, 2)
+        assert np.array_equal(cnt, want)
+
+
+@pytest.mark.parametrize("renumber,bs,K,lg,csort", [("rcm", 512, 512, True, False),
+                                                    ("morton", 64, 64, True, True),
+                                                    ("none", 256, 0, False, False),
+                                                    ("morton", 2048, 4096, False, False)])
+def test_plan_properties(renumber, bs, K, lg, csort):
+    m = meshgen.build_mesh(8, 1, 0.25)
+    ctx, nodes, edges, mp, info = host_problem(m, renumber=renumber, block_size=bs,
+                                               cluster_size=K, lane_groups=lg,
+                                               colour_sort=csort)
+    assert ctx.plan_verify(mp)["ok"]
+    check_plan_properties(m, ctx, nodes, edges, mp)
+    assert info["nblocks"] == -(-m.E // bs)
+    if K:
+        assert info["owner_edge_visits"] >= m.E
+
+
+def test_renumbering_reduces_bandwidth_and_verifier_on_config_a():
+    m = meshgen.config_mesh("A")
+    _, _, _, _, info = host_problem(m, renumber="rcm")
+    assert info["bandwidth_after"] < info["bandwidth_before"] / 4
+    ctx, nodes, edges, mp, info = host_problem(m, renumber="morton", block_size=256)
+    check_plan_properties(m, ctx, nodes, edges, mp)
+    # block colours per partition set are of the order the paper reports (tens)
+    assert 2 <= info["nblock_colours"] <= 64
+
+
+def test_lane_groups_make_wavefront_endpoints_distinct():
+    m = meshgen.build_mesh(16, 1, 0.25)
+    K = 512
+    rates = {}
+    for lg in (False, True):
+        ctx, nodes, edges, mp, info = host_problem(m, renumber="morton", cluster_size=K,
+                                                   lane_groups=lg)
+        v = ctx.plan_view(mp)
+        e2n = v["e2n"]
+        soff, st, ln = v["cluster_seg_offsets"], v["cluster_seg_start"], v["cluster_seg_len"]
+        rep = tot = 0
+        for c in range(v["nclusters"]):
+            visits = np.concatenate([np.arange(st[s], st[s] + ln[s])
+                                     for s in range(soff[c], soff[c + 1])])
+            for w0 in range(0, len(visits), 64):
+                ends = e2n[visits[w0:w0 + 64]].ravel()
+                own = ends[ends // K == c]
+                tot += len(own)
+                rep += len(own) - len(np.unique(own))
+        rates[lg] = rep / tot
+    assert rates[True] < 0.5 * rates[False]
+
+
+def test_declaration_errors():
+    ctx = pk.Context(None)
+    with pytest.raises(pk.OpfError) as e:
+        ctx.decl_set(0)
+    assert e.value.status == pk.ESIZE
+    nodes = ctx.decl_set(4, "nodes")
+    edges = ctx.decl_set(3, "edges")
+    with pytest.raises(pk.OpfError) as e:  # entry outside the target set
+        ctx.decl_map(edges, nodes, 2, np.array([[0, 1], [1, 2], [2, 4]]), 0, "bad")
+    assert e.value.status == pk.ERANGE
+    # a 1-based map (as in the paper's Fortran declarations) is accepted with index_base 1
+    mp = ctx.decl_map(edges, nodes, 2, np.array([[1, 2], [2, 3], [3, 4]]), 1, "e2n")
+    ctx.plan(mp, block_size=64, cluster_size=64)
+    v = ctx.plan_view(mp)
+    node_new = ctx.get_perm(nodes, 4)
+    edge_new = ctx.get_perm(edges, 3)
+    assert np.array_equal(v["e2n"][edge_new], node_new[np.array([[0, 1], [1, 2], [2, 3]])])
+    with pytest.raises(pk.OpfError) as e:
+        ctx.decl_map(edges, nodes, 2, np.zeros((3, 2)), 2, "base2")
+    assert e.value.status == pk.EINVAL
+
+
+def test_plan_errors_and_stale_plans():
+    ctx = pk.Context(None)
+    nodes = ctx.decl_set(3, "nodes")
+    edges = ctx.decl_set(2, "edges")
+    loop = ctx.decl_map(edges, nodes, 2, np.array([[0, 1], [2, 2]]), 0, "loop")
+    with pytest.raises(pk.OpfError) as e:  # an edge joining a node to itself
+        ctx.plan(loop)
+    assert e.value.status == pk.EINVAL
+    ok = ctx.decl_map(edges, nodes, 2, np.array([[0, 1], [1, 2]]), 0, "loop")  # redeclared
+    assert ok == loop
+    with pytest.raises(pk.OpfError) as e:
+        ctx.plan(ok, block_size=100)  # not a power of two
+    assert e.value.status == pk.EINVAL
+    with pytest.raises(pk.OpfError) as e:
+        ctx.plan(ok, renumber="morton")  # Morton needs coordinates
+    assert e.value.status == pk.EINVAL
+    ctx.plan(ok, block_size=64, cluster_size=64)
+    assert ctx.plan_verify(ok)["ok"]
+    # re-declaring the map makes the plan stale: loops refuse it (host context:
+    # the argument checks run before the device is touched)
+    ctx.decl_map(edges, nodes, 2, np.array([[1, 0], [1, 2]]), 0, "loop")
+    # a new map on sets a plan has renumbered would mix numberings: refused
+    with pytest.raises(pk.OpfError) as e:
+        ctx.decl_map(edges, nodes, 2, np.array([[0, 1], [1, 2]]), 0, "other")
+    assert e.value.status == pk.ESTATE
+    # plans are for arity-2 maps (the paper's cell->node example has arity 3)
+    c2 = pk.Context(None)
+    cells = c2.decl_set(2, "cells")
+    verts = c2.decl_set(4, "nodes")
+    tri = c2.decl_map(cells, verts, 3, np.array([[0, 1, 2], [1, 2, 3]]), 0, "pcell")
+    with pytest.raises(pk.OpfError) as e:
+        c2.plan(tri)
+    assert e.value.status == pk.EINVAL
+
+
+def test_loop_argument_checks_without_device():
+    ctx = pk.Context(None)
+    nodes = ctx.decl_set(3, "nodes")
+    edges = ctx.decl_set(2, "edges")
+    mp = ctx.decl_map(edges, nodes, 2, np.array([[0, 1], [1, 2]]), 0, "e2n")
+    ctx.plan(mp, block_size=64, cluster_size=64)
+    # host-only dats: NULL pointers are accepted on a host context
+    lib = ctx.lib
+    out = ctypes.c_int32()
+
+    def dat(s, dim, typ, ld):
+        assert lib.opf_decl_dat(ctx._ctx, s, dim, typ, None, ld, b"d", ctypes.byref(out)) == 0
+        return out.value
+
+    q = dat(nodes, 6, pk.F64, 3)
+    n = dat(edges, 3, pk.F64, 2)
+    res = dat(nodes, 6, pk.F64, 3)
+    res32 = dat(nodes, 6, pk.F32, 3)
+    assert lib.opf_decl_dat(ctx._ctx, nodes, 6, pk.F64, None, 2, b"short", ctypes.byref(out)) == pk.ESIZE
+    assert lib.opf_decl_dat(ctx._ctx, nodes, 6, 7, None, 3, b"type", ctypes.byref(out)) == pk.ETYPE
+    g = ctypes.c_double(1.4)
+
+    def flux(args, gbl_dim=1, variant=pk.COLOURED):
+        a = (pk.Arg * len(args))(*[pk.Arg(*x) for x in args])
+        gb = (pk.Gbl * 1)(pk.Gbl(ctypes.addressof(g), gbl_dim, pk.F64, pk.READ, 0))
+        return lib.opf_par_loop(ctx._ctx, pk.K_EDGE_FLUX, edges, len(args), a, 1, gb, variant, None)
+
+    good = [(q, 0, mp, 6, pk.F64, pk.READ), (q, 1, mp, 6, pk.F64, pk.READ),
+            (n, -1, pk.ID, 3, pk.F64, pk.READ), (res, 0, mp, 6, pk.F64, pk.INC),
+            (res, 1, mp, 6, pk.F64, pk.INC)]
+    assert flux(good) == pk.EDEVICE  # well-formed, but no device on this context
+    bad_access = list(good)
+    bad_access[3] = (res, 0, mp, 6, pk.F64, pk.READ)
+    assert flux(bad_access) == pk.EACCESS
+    bad_type = list(good)
+    bad_type[3] = (res32, 0, mp, 6, pk.F32, pk.INC)
+    bad_type[4] = (res32, 1, mp, 6, pk.F32, pk.INC)
+    assert flux(bad_type) == pk.ETYPE
+    bad_dim = list(good)
+    bad_dim[2] = (n, -1, pk.ID, 2, pk.F64, pk.READ)
+    assert flux(bad_dim) == pk.ESIZE
+    bad_map = list(good)
+    bad_map[2] = (n, 0, mp, 3, pk.F64, pk.READ)
+    assert flux(bad_map) == pk.EINVAL
+    assert flux(good[:4]) == pk.EINVAL
+    assert flux(good, gbl_dim=2) == pk.ESIZE
+    # WRITE increments only with the owner variant
+    w = list(good)
+    w[3] = (res, 0, mp, 6, pk.F64, pk.WRITE)
+    w[4] = (res, 1, mp, 6, pk.F64, pk.WRITE)
+    assert flux(w, variant=pk.COLOURED) == pk.EACCESS
+    assert flux(w, variant=pk.OWNER) == pk.EDEVICE
+    assert "host-only" in lib.opf_last_error(ctx._ctx).decode()
+    # a stale plan is refused
+    ctx.decl_map(edges, nodes, 2, np.array([[0, 2], [1, 2]]), 0, "e2n")
+    assert flux(good) == pk.ESTATE
+
+
+def test_finalize_accepts_null_and_init_rejects_bad_device():
+    lib = pk.load()
+    assert lib.opf_finalize(None) == 0
+    c = ctypes.c_void_p()
+    assert lib.opf_init(ctypes.byref(c), -5) == pk.EINVAL
