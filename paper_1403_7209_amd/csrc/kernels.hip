@@ -28,6 +28,22 @@
 
 #include "kernels.hpp"
 
+// Tuning of the owner kernel per (type, op): edges each thread resolves before
+// computing (B), and the waves per SIMD the register allocator must allow
+// (0: no constraint).  Occupancy, not bandwidth per wave, limits these loops.
+#ifndef OPF_FLUX64_BATCH
+#define OPF_FLUX64_BATCH 2
+#endif
+#ifndef OPF_FLUX64_WAVES
+#define OPF_FLUX64_WAVES 6
+#endif
+#ifndef OPF_ADJ_BATCH
+#define OPF_ADJ_BATCH 1
+#endif
+#ifndef OPF_ADJ_WAVES
+#define OPF_ADJ_WAVES 0
+#endif
+
 namespace opf {
 namespace gpu {
 namespace {
@@ -43,34 +59,40 @@ __device__ __forceinline__ float tabs(float x) { return fabsf(x); }
 
 // F = 1/2 (f(q_i) + f(q_j)).n - 1/2 lambda (q_j - q_i),
 // lambda = |1/2 (U_i + U_j)| + 1/2 (c_i + c_j) |n|, U = u.n; +F to node i,
-// -F to node j.  Staged record: q[0..5], 1/rho, p, c.
+// -F to node j.  Staged record: rho, u[0..2], rho E, rho phi, p, c (the
+// momentum is rebuilt as rho u).
 struct OpFlux {
-    static constexpr int NIN = 6, NS = 9, NOUT = 6, NWOUT = 0, MODE = ANTI;
+    static constexpr int NIN = 6, NS = 8, NOUT = 6, NWOUT = 0, MODE = ANTI;
     template <typename T>
     __device__ static __forceinline__ void stage(const T *x, T *s, T gamma)
     {
-#pragma unroll
-        for (int v = 0; v < 6; ++v) s[v] = x[v];
         const T ir = T(1) / x[0];
-        const T p = (gamma - T(1)) * (x[4] - T(0.5) * (x[1] * x[1] + x[2] * x[2] + x[3] * x[3]) * ir);
-        s[6] = ir;
-        s[7] = p;
-        s[8] = tsqrt(gamma * p * ir);
+        s[0] = x[0];
+        s[1] = x[1] * ir;
+        s[2] = x[2] * ir;
+        s[3] = x[3] * ir;
+        s[4] = x[4];
+        s[5] = x[5];
+        const T p = (gamma - T(1)) * (x[4] - T(0.5) * (x[1] * s[1] + x[2] * s[2] + x[3] * s[3]));
+        s[6] = p;
+        s[7] = tsqrt(gamma * p * ir);
     }
     template <typename T>
     __device__ static __forceinline__ void edge(const T *a, const T *b, const T *n, T gamma,
                                                 double *yi, double *, double *)
     {
         const T h = T(0.5);
-        const T Ua = (a[1] * n[0] + a[2] * n[1] + a[3] * n[2]) * a[6];
-        const T Ub = (b[1] * n[0] + b[2] * n[1] + b[3] * n[2]) * b[6];
+        const T Ua = a[1] * n[0] + a[2] * n[1] + a[3] * n[2];
+        const T Ub = b[1] * n[0] + b[2] * n[1] + b[3] * n[2];
         const T nn = tsqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        const T hl = h * (tabs(h * (Ua + Ub)) + h * (a[8] + b[8]) * nn);
-        yi[0] = (double)(h * (a[0] * Ua + b[0] * Ub) - hl * (b[0] - a[0]));
-        yi[1] = (double)(h * (a[1] * Ua + b[1] * Ub + (a[7] + b[7]) * n[0]) - hl * (b[1] - a[1]));
-        yi[2] = (double)(h * (a[2] * Ua + b[2] * Ub + (a[7] + b[7]) * n[1]) - hl * (b[2] - a[2]));
-        yi[3] = (double)(h * (a[3] * Ua + b[3] * Ub + (a[7] + b[7]) * n[2]) - hl * (b[3] - a[3]));
-        yi[4] = (double)(h * ((a[4] + a[7]) * Ua + (b[4] + b[7]) * Ub) - hl * (b[4] - a[4]));
+        const T hl = h * (tabs(h * (Ua + Ub)) + h * (a[7] + b[7]) * nn);
+        const T ma = a[0] * Ua, mb = b[0] * Ub;  // mass fluxes
+        const T pp = a[6] + b[6];
+        yi[0] = (double)(h * (ma + mb) - hl * (b[0] - a[0]));
+        yi[1] = (double)(h * (ma * a[1] + mb * b[1] + pp * n[0]) - hl * (b[0] * b[1] - a[0] * a[1]));
+        yi[2] = (double)(h * (ma * a[2] + mb * b[2] + pp * n[1]) - hl * (b[0] * b[2] - a[0] * a[2]));
+        yi[3] = (double)(h * (ma * a[3] + mb * b[3] + pp * n[2]) - hl * (b[0] * b[3] - a[0] * a[3]));
+        yi[4] = (double)(h * ((a[4] + a[6]) * Ua + (b[4] + b[6]) * Ub) - hl * (b[4] - a[4]));
         yi[5] = (double)(h * (a[5] * Ua + b[5] * Ub) - hl * (b[5] - a[5]));
     }
 };
@@ -209,6 +231,19 @@ struct OpAdjoint {
     }
 };
 
+template <typename T, class Op>
+struct OwnerTune {
+    static constexpr int B = 2, WAVES = 0;
+};
+template <>
+struct OwnerTune<double, OpFlux> {
+    static constexpr int B = OPF_FLUX64_BATCH, WAVES = OPF_FLUX64_WAVES;
+};
+template <>
+struct OwnerTune<double, OpAdjoint> {
+    static constexpr int B = OPF_ADJ_BATCH, WAVES = OPF_ADJ_WAVES;
+};
+
 // ----------------------------------------------------------- plumbing -- */
 
 struct PlanPtrs {
@@ -263,22 +298,78 @@ __device__ __forceinline__ void lds_add(double *p, double v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Element idx of an array at a uniform base, addressed with a 32-bit byte
+// offset (idx * sizeof(T) < 2^32), so that no 64-bit address arithmetic runs
+// per lane.
+template <typename T>
+__device__ __forceinline__ T ld(const T *base, int idx)
+{
+    const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(T);
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+
+template <typename T>
+__device__ __forceinline__ void st(T *base, int idx, T v)
+{
+    const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(T);
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
+}
+
 template <class Op, typename T>
 __device__ __forceinline__ void load_stage(const Arrays<T> &a, int g, T gamma, T *s)
 {
     T x[Op::NIN];
 #pragma unroll
-    for (int v = 0; v < Op::NIN; ++v) x[v] = a.x[v][g];
+    for (int v = 0; v < Op::NIN; ++v) x[v] = ld(a.x[v], g);
     Op::stage(x, s, gamma);
+}
+
+// LDS node records of NS values (NS * sizeof(T) a multiple of 16 bytes) are
+// kept as W planes of 16-byte words: plane k holds word k of every record.  A
+// wavefront gathering records of random nodes then spreads each 16-byte read
+// over all 8 word positions of the 128-byte LDS row, and every read is one
+// ds_read_b128.  Accumulators are NOUT planes of doubles.
+template <typename T, int NS>
+struct Rec {
+    static_assert((NS * sizeof(T)) % 16 == 0, "record must be a multiple of 16 bytes");
+    static constexpr int W = NS * (int)sizeof(T) / 16;
+};
+
+template <typename T, int NS>
+__device__ __forceinline__ void lds_get(const T *base, int rows, int idx, T *out)
+{
+    constexpr int W = Rec<T, NS>::W;
+    const uint4 *src = reinterpret_cast<const uint4 *>(base);
+    uint4 tmp[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) tmp[k] = src[k * rows + idx];
+    __builtin_memcpy(out, tmp, sizeof(tmp));
+}
+
+template <typename T, int NS>
+__device__ __forceinline__ void lds_put(T *base, int rows, int idx, const T *in)
+{
+    constexpr int W = Rec<T, NS>::W;
+    uint4 tmp[W];
+    __builtin_memcpy(tmp, in, sizeof(tmp));
+    uint4 *dst = reinterpret_cast<uint4 *>(base);
+#pragma unroll
+    for (int k = 0; k < W; ++k) dst[k * rows + idx] = tmp[k];
 }
 
 __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
 template <typename T, class Op>
-__host__ __device__ constexpr size_t stage_bytes(int rows) { return align16((size_t)Op::NS * rows * sizeof(T)); }
+__host__ __device__ constexpr size_t stage_bytes(int rows)
+{
+    return (size_t)Rec<T, Op::NS>::W * 16 * rows;
+}
 
 template <typename T, class Op>
-constexpr size_t lds_bytes(int rows) { return stage_bytes<T, Op>(rows) + (size_t)Op::NOUT * rows * sizeof(double); }
+constexpr size_t lds_bytes(int rows)
+{
+    return stage_bytes<T, Op>(rows) + (size_t)Op::NOUT * rows * sizeof(double);
+}
 
 // ---------------------------------------------------- coloured kernel -- */
 
@@ -301,8 +392,7 @@ __global__ __launch_bounds__(NT) void k_edge_coloured(PlanPtrs p, Arrays<T> a, T
     for (int u = threadIdx.x; u < nu; u += NT) {
         T s[Op::NS];
         load_stage<Op>(a, p.uniq[u0 + u], gamma, s);
-#pragma unroll
-        for (int v = 0; v < Op::NS; ++v) ss[v * umax + u] = s[v];
+        lds_put<T, Op::NS>(ss, umax, u, s);
 #pragma unroll
         for (int v = 0; v < Op::NOUT; ++v) sy[v * umax + u] = 0.0;
     }
@@ -321,13 +411,10 @@ __global__ __launch_bounds__(NT) void k_edge_coloured(PlanPtrs p, Arrays<T> a, T
             lj[t] = (int)(l >> 16);
             col[t] = p.ecol[e0 + e];
             T si[Op::NS], sj[Op::NS], n[3];
+            lds_get<T, Op::NS>(ss, umax, li[t], si);
+            lds_get<T, Op::NS>(ss, umax, lj[t], sj);
 #pragma unroll
-            for (int v = 0; v < Op::NS; ++v) {
-                si[v] = ss[v * umax + li[t]];
-                sj[v] = ss[v * umax + lj[t]];
-            }
-#pragma unroll
-            for (int d = 0; d < 3; ++d) n[d] = a.w[d][e0 + e];
+            for (int d = 0; d < 3; ++d) n[d] = ld(a.w[d], e0 + e);
             double wo[3] = {0.0, 0.0, 0.0};
             Op::edge(si, sj, n, gamma, y[t], y[t] + (NY - Op::NOUT), wo);
             if (Op::NWOUT) {
@@ -390,7 +477,7 @@ __global__ __launch_bounds__(256) void k_edge_atomic(const int2 *__restrict__ e2
     load_stage<Op>(a, ij.x, gamma, si);
     load_stage<Op>(a, ij.y, gamma, sj);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) n[d] = a.w[d][e];
+    for (int d = 0; d < 3; ++d) n[d] = ld(a.w[d], e);
     constexpr int NY = Op::MODE == GEN ? 2 * Op::NOUT : Op::NOUT;
     double y[NY];
     double wo[3] = {0.0, 0.0, 0.0};
@@ -419,10 +506,13 @@ __device__ __forceinline__ int owner_node(uint32_t f, int2 cl, int K, int &cid)
     return cid * K + (int)(f & 0x7fffu);
 }
 
-template <typename T, class Op, int NT, int B>
-__global__ __launch_bounds__(NT) void k_edge_owner(OwnerPtrs p, Arrays<T> a, T gamma, int N,
-                                                   int K, int ncl, int remap, int overwrite)
+__host__ __device__ constexpr int owner_acc_rows(int K) { return K; }
+
+template <typename T, class Op, int NT>
+__global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>::WAVES : 1)) void k_edge_owner(
+    OwnerPtrs p, Arrays<T> a, T gamma, int N, int K, int ncl, int remap, int overwrite)
 {
+    constexpr int B = OwnerTune<T, Op>::B;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_start[kMaxClusterSegments];
     __shared__ int s_pre[kMaxClusterSegments + 1];
@@ -430,6 +520,7 @@ __global__ __launch_bounds__(NT) void k_edge_owner(OwnerPtrs p, Arrays<T> a, T g
     constexpr int NY = Op::MODE == GEN ? 2 * Op::NOUT : Op::NOUT;
     T *ss = reinterpret_cast<T *>(smem);
     double *sy = reinterpret_cast<double *>(smem + stage_bytes<T, Op>(K));
+    const int AR = owner_acc_rows(K);
 
     const int c = remap ? xcd_map((int)blockIdx.x, ncl) : (int)blockIdx.x;
     const int v0 = c * K, nown = min(K, N - v0);
@@ -442,12 +533,11 @@ __global__ __launch_bounds__(NT) void k_edge_owner(OwnerPtrs p, Arrays<T> a, T g
     if (threadIdx.x == 0) s_pre[ns] = p.total[c];
     // stage the owned nodes (contiguous ids: coalesced), clear the accumulator
     for (int v = threadIdx.x; v < nown; v += NT) {
-        T st[Op::NS];
-        load_stage<Op>(a, v0 + v, gamma, st);
+        T rec[Op::NS];
+        load_stage<Op>(a, v0 + v, gamma, rec);
+        lds_put<T, Op::NS>(ss, K, v, rec);
 #pragma unroll
-        for (int k = 0; k < Op::NS; ++k) ss[k * K + v] = st[k];
-#pragma unroll
-        for (int k = 0; k < Op::NOUT; ++k) sy[k * K + v] = 0.0;
+        for (int k = 0; k < Op::NOUT; ++k) sy[k * AR + v] = 0.0;
     }
     __syncthreads();
 
@@ -485,9 +575,9 @@ __global__ __launch_bounds__(NT) void k_edge_owner(OwnerPtrs p, Arrays<T> a, T g
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             if (sg[b] >= 0) {
-                m[b] = p.omap[eid[b]];
+                m[b] = ld(p.omap, eid[b]);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) w[b][d] = a.w[d][eid[b]];
+                for (int d = 0; d < 3; ++d) w[b][d] = ld(a.w[d], eid[b]);
             }
         }
 #pragma unroll
@@ -499,18 +589,14 @@ __global__ __launch_bounds__(NT) void k_edge_owner(OwnerPtrs p, Arrays<T> a, T g
             const int gj = owner_node(m[b] >> 16, cl, K, cj);
             const bool oi = ci == c, oj = cj == c;
             T si[Op::NS], sj[Op::NS];
-            if (oi) {
-#pragma unroll
-                for (int v = 0; v < Op::NS; ++v) si[v] = ss[v * K + (gi - v0)];
-            } else {
+            if (oi)
+                lds_get<T, Op::NS>(ss, K, gi - v0, si);
+            else
                 load_stage<Op>(a, gi, gamma, si);
-            }
-            if (oj) {
-#pragma unroll
-                for (int v = 0; v < Op::NS; ++v) sj[v] = ss[v * K + (gj - v0)];
-            } else {
+            if (oj)
+                lds_get<T, Op::NS>(ss, K, gj - v0, sj);
+            else
                 load_stage<Op>(a, gj, gamma, sj);
-            }
             double y[NY];
             double wo[3] = {0.0, 0.0, 0.0};
             Op::edge(si, sj, w[b], gamma, y, y + (NY - Op::NOUT), wo);
@@ -518,13 +604,13 @@ __global__ __launch_bounds__(NT) void k_edge_owner(OwnerPtrs p, Arrays<T> a, T g
             for (int v = 0; v < Op::NOUT; ++v) {
                 const double yi = y[v];
                 const double yj = Op::MODE == ANTI ? -yi : Op::MODE == SAME ? yi : y[Op::NOUT + v];
-                if (oi) lds_add(&sy[v * K + (gi - v0)], yi);
-                if (oj) lds_add(&sy[v * K + (gj - v0)], yj);
+                if (oi) lds_add(&sy[v * AR + (gi - v0)], yi);
+                if (oj) lds_add(&sy[v * AR + (gj - v0)], yj);
             }
             // a direct output is written by the smaller cluster of the segment only
             if (Op::NWOUT && cl.x == c) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) a.wo[d][eid[b]] = wo[d];
+                for (int d = 0; d < 3; ++d) st(a.wo[d], eid[b], wo[d]);
             }
         }
     }
@@ -532,8 +618,8 @@ __global__ __launch_bounds__(NT) void k_edge_owner(OwnerPtrs p, Arrays<T> a, T g
     for (int v = threadIdx.x; v < nown; v += NT) {
 #pragma unroll
         for (int k = 0; k < Op::NOUT; ++k) {
-            double *dst = a.y[k] + v0 + v;
-            *dst = overwrite ? sy[k * K + v] : *dst + sy[k * K + v];
+            const double acc = sy[k * AR + v];
+            st(a.y[k], v0 + v, overwrite ? acc : ld(a.y[k], v0 + v) + acc);
         }
     }
 }
@@ -688,14 +774,19 @@ int run_atomic(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t 
 }
 
 template <typename T, class Op>
+constexpr size_t owner_dyn_lds(int K)
+{
+    return stage_bytes<T, Op>(K) + (size_t)Op::NOUT * owner_acc_rows(K) * sizeof(double);
+}
+
+template <typename T, class Op>
 int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
               const LaunchOpts &lo)
 {
     if (!P.owner_ok || P.ncl <= 0) return (int)hipErrorInvalidValue;
-    const size_t lds = lds_bytes<T, Op>(P.K);
+    const size_t lds = owner_dyn_lds<T, Op>(P.K);
     const OwnerPtrs op{P.omap, P.seg_off, P.seg_start, P.seg_pre, P.seg_cl, P.cl_total};
-    hipLaunchKernelGGL((k_edge_owner<T, Op, kOwnerThreads, kOwnerBatch>), dim3(P.ncl),
-                       dim3(kOwnerThreads), lds,
+    hipLaunchKernelGGL((k_edge_owner<T, Op, kOwnerThreads>), dim3(P.ncl), dim3(kOwnerThreads), lds,
                        st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
     return (int)hipGetLastError();
 }
@@ -748,9 +839,18 @@ int raise_all(size_t bytes)
     int rc = raise_coloured<T, Op, false>(bytes);
     if (!rc) rc = raise_coloured<T, Op, true>(bytes);
     if (!rc)
-        rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, kOwnerBatch>),
-                       bytes);
+        rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads>), bytes);
     return rc;
+}
+
+size_t owner_lds_bytes(int op, bool fp32, int K)
+{
+    const size_t fixed =
+        align16(sizeof(int) * (2 * kMaxClusterSegments + 1) + sizeof(int2) * kMaxClusterSegments);
+    if (op == OP_ADJOINT) return fixed + owner_dyn_lds<double, OpAdjoint>(K);
+    if (op == OP_SPECRAD)
+        return fixed + (fp32 ? owner_dyn_lds<float, OpSpecrad>(K) : owner_dyn_lds<double, OpSpecrad>(K));
+    return fixed + (fp32 ? owner_dyn_lds<float, OpFlux>(K) : owner_dyn_lds<double, OpFlux>(K));
 }
 
 }  // namespace
@@ -758,14 +858,12 @@ int raise_all(size_t bytes)
 size_t edge_lds_bytes(int op, bool fp32, int variant, int umax, int K)
 {
     if (variant == V_ATOMIC) return 0;
-    const int rows = variant == V_OWNER ? K : umax;
-    // the owner kernel also holds its segment table in static LDS
-    const size_t fixed =
-        variant == V_OWNER ? align16(sizeof(int) * (2 * kMaxClusterSegments + 1) + sizeof(int2) * kMaxClusterSegments) : 0;
-    if (op == OP_ADJOINT) return fixed + lds_bytes<double, OpAdjoint>(rows);
+    if (variant == V_OWNER) return owner_lds_bytes(op, fp32, K);
+    const int rows = umax;
+    if (op == OP_ADJOINT) return lds_bytes<double, OpAdjoint>(rows);
     if (op == OP_SPECRAD)
-        return fixed + (fp32 ? lds_bytes<float, OpSpecrad>(rows) : lds_bytes<double, OpSpecrad>(rows));
-    return fixed + (fp32 ? lds_bytes<float, OpFlux>(rows) : lds_bytes<double, OpFlux>(rows));
+        return fp32 ? lds_bytes<float, OpSpecrad>(rows) : lds_bytes<double, OpSpecrad>(rows);
+    return fp32 ? lds_bytes<float, OpFlux>(rows) : lds_bytes<double, OpFlux>(rows);
 }
 
 int set_lds_limit(size_t bytes)

@@ -16,7 +16,6 @@ enum Variant { V_COLOURED = 0, V_ATOMIC = 1, V_OWNER = 2, V_COLOURED_LDS_ATOMIC 
 
 constexpr int kMaxClusterSegments = 256;
 constexpr int kOwnerThreads = 512;
-constexpr int kOwnerBatch = 4;  // edges each owner thread resolves before computing
 
 // Device copy of an execution plan (internal numbering, int32 offsets).
 struct DevPlan {

@@ -1,0 +1,166 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (owner variant, Morton renumbering, clusters of 512 nodes), against
+the FP64 oracle: whole arrays where the oracle finishes in seconds, sampled
+outputs computed one by one where it does not (the adjoint), and properties
+that hold at any size for the 100-iteration FP32 trajectory.
+"""
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+import paper_1403_7209_amd as pk
+from tests._util import normwise, report
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+BENCH = dict(renumber="morton", block_size=512, cluster_size=512)
+
+
+@pytest.fixture(scope="module")
+def mesh_e():
+    print("[building the 160^3 layered mesh]", flush=True)
+    m = meshgen.config_mesh("E")
+    q = meshgen.state(m.N, m.perm)
+    return m, q
+
+
+@pytest.fixture(scope="module")
+def prob_e(mesh_e):
+    m, q = mesh_e
+    ctx = pk.Context(DEV)
+    p64 = pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, coords=m.xyz, **BENCH)
+    p32 = pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, fp32=True, like=p64)
+    return p64, p32
+
+
+def test_plan_at_full_size(prob_e, mesh_e):
+    p64, _ = prob_e
+    m, _ = mesh_e
+    assert p64.ctx.plan_verify(p64.e2n)["ok"]
+    assert p64.info["owner_ok"]
+    assert m.E <= p64.info["owner_edge_visits"] <= 1.4 * m.E
+
+
+def test_fp64_residual_full(prob_e, mesh_e):
+    p64, _ = prob_e
+    m, q = mesh_e
+    print("[E: oracle residual]", flush=True)
+    ref = oracle.residual(m.e2n, q, m.w)
+    for variant, acc in ((pk.OWNER, pk.WRITE), (pk.OWNER, pk.INC), (pk.COLOURED, pk.INC)):
+        res = torch.full((6, m.N), 0.0 if acc == pk.INC else 7.0, dtype=torch.float64, device=DEV)
+        p64.residual(p64.qa, res, variant, acc)
+        p64.ctx.sync()
+        assert report(f"E residual v{variant} acc{acc}", normwise(p64.nodes_out(res), ref), 1e-12)
+
+
+def test_fp32_residual_full(prob_e, mesh_e):
+    _, p32 = prob_e
+    m, q = mesh_e
+    q32 = q.astype(np.float32).astype(np.float64)
+    w32 = m.w.astype(np.float32).astype(np.float64)
+    ref = oracle.residual(m.e2n, q32, w32)
+    res = torch.empty((6, m.N), dtype=torch.float64, device=DEV)
+    p32.residual(p32.qa, res, pk.OWNER, pk.WRITE)
+    p32.ctx.sync()
+    assert report("E fp32 residual", normwise(p32.nodes_out(res), ref), 1e-5)
+
+
+def test_time_step_and_rk_iteration_full(prob_e, mesh_e):
+    p64, _ = prob_e
+    m, q = mesh_e
+    dt_ref = oracle.dt(m.e2n, q, m.w, m.vol)
+    dt = p64.compute_dt(0.5, pk.OWNER)
+    assert abs(dt - dt_ref) <= 1e-12 * dt_ref
+    print("[E: oracle RK iteration]", flush=True)
+    q1, ss = oracle.rk_iteration(m.e2n, q, m.w, m.vol, dt_ref)
+    qa0 = p64.qa.clone()
+    p64.rk_iteration(dt_ref, pk.OWNER)
+    p64.ctx.sync()
+    assert report("E state after one iteration", normwise(p64.nodes_out(p64.qa), q1), 1e-12)
+    assert report("E stage rms", normwise(p64.rms(), np.sqrt(ss / m.N)), 1e-12)
+    p64.qa.copy_(qa0)
+
+
+def test_adjoint_sampled_full(prob_e, mesh_e):
+    """qbar at sampled nodes and nbar at sampled edges, each formed one by one
+    from the oracle's exact edge Jacobians."""
+    p64, _ = prob_e
+    m, q = mesh_e
+    rbar = meshgen.normal(6 * m.N, purpose=21).reshape(6, m.N)
+    rb = p64.nodes_in(rbar)
+    qbar = torch.empty((6, m.N), dtype=torch.float64, device=DEV)
+    nbar = torch.empty((3, m.E), dtype=torch.float64, device=DEV)
+    p64.ctx.edge_flux_adjoint(p64.edges, p64.e2n, p64.dat(p64.qa), p64.w, p64.dat(rb),
+                              p64.dat(qbar), p64.dat(nbar, edges=True), p64.gamma, pk.OWNER,
+                              pk.WRITE)
+    p64.ctx.sync()
+    qbar_h = p64.nodes_out(qbar)
+    nbar_h = p64.nodes_out(nbar, edges=True)
+    rng = np.random.default_rng(64)
+    nodes = rng.choice(m.N, 48, replace=False)
+    inc = np.zeros(m.N, bool)
+    inc[nodes] = True
+    sel = np.nonzero(inc[m.e2n[:, 0]] | inc[m.e2n[:, 1]])[0]
+    ref_q = {int(v): np.zeros(6) for v in nodes}
+    for e in sel:
+        i, j = m.e2n[e]
+        _, J = oracle.edge_jacobian(q[:, i], q[:, j], m.w[:, e])
+        Fb = rbar[:, i] - rbar[:, j]
+        if inc[i]:
+            ref_q[int(i)] += J[:, 0:6].T @ Fb
+        if inc[j]:
+            ref_q[int(j)] += J[:, 6:12].T @ Fb
+    got = np.stack([qbar_h[:, v] for v in nodes], 1)
+    ref = np.stack([ref_q[int(v)] for v in nodes], 1)
+    assert report("E qbar (48 sampled nodes)", normwise(got, ref), 1e-12)
+    edges = rng.choice(m.E, 64, replace=False)
+    ref_n = []
+    for e in edges:
+        i, j = m.e2n[e]
+        _, J = oracle.edge_jacobian(q[:, i], q[:, j], m.w[:, e])
+        ref_n.append(J[:, 12:15].T @ (rbar[:, i] - rbar[:, j]))
+    assert report("E nbar (64 sampled edges)", normwise(nbar_h[:, edges], np.stack(ref_n, 1)), 1e-12)
+
+
+def test_fp32_trajectory_100_iterations():
+    """The FP32-storage form over 100 iterations against the FP64 oracle
+    trajectory on a 20^3 box (the oracle runs 500 residuals in seconds), and on
+    the 1M-node jittered box against the FP64 GPU trajectory (an invariant at
+    any size: the two forms stay within 1e-5 of each other)."""
+    m = meshgen.config_mesh("A")
+    q = meshgen.state(m.N, m.perm)
+    q32 = q.astype(np.float32).astype(np.float64)
+    w32 = m.w.astype(np.float32).astype(np.float64)
+    dt = oracle.dt(m.e2n, q32, w32, m.vol)
+    ref = q32.copy()
+    for _ in range(100):
+        ref, _ = oracle.rk_iteration(m.e2n, ref, m.w, m.vol, dt)
+    ctx = pk.Context(DEV)
+    p32 = pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, fp32=True, coords=m.xyz, **BENCH)
+    for _ in range(100):
+        p32.rk_iteration(dt, pk.OWNER)
+    ctx.sync()
+    assert report("A fp32 100-iteration state", normwise(p32.nodes_out(p32.qa), ref), 1e-5)
+
+    print("[1M-node jittered box: FP32 vs FP64 trajectories]", flush=True)
+    mb = meshgen.config_mesh("C")
+    qb = meshgen.state(mb.N, mb.perm)
+    ctx = pk.Context(DEV)
+    p64 = pk.FluxProblem(ctx, mb.e2n, mb.w, mb.vol, qb, coords=mb.xyz, **BENCH)
+    p32 = pk.FluxProblem(ctx, mb.e2n, mb.w, mb.vol, qb, fp32=True, like=p64)
+    dt = p64.compute_dt(0.5, pk.OWNER)
+    errs = []
+    for it in range(100):
+        p64.rk_iteration(dt, pk.OWNER)
+        p32.rk_iteration(dt, pk.OWNER)
+        if it % 20 == 19:
+            a = p64.qa.double()
+            b = p32.qa.double()
+            errs.append(float(((a - b).abs().amax(dim=1) / a.abs().amax(dim=1)).max()))
+    ctx.sync()
+    print(f"  FP32 vs FP64 state error every 20 iterations: {errs}", flush=True)
+    assert max(errs) <= 1e-5
+    assert ctx.check_finite(p64.ss) and ctx.check_finite(p32.ss)
