@@ -118,7 +118,8 @@ int opf_set_allocator(opf_ctx *ctx, void *(*alloc_fn)(void *user, size_t bytes),
 
 /* ------------------------------------------------------- declarations -- */
 
-/* Declares a set of `size` elements, 0 < size < 2^31 (Sec. 3.1, op_decl_set).
+/* Declares a set of `size` elements, 0 < size < 2^29 (Sec. 3.1, op_decl_set;
+ * the kernels address one component of a dat with 32-bit byte offsets).
  * `name` may be NULL.  Errors: OPF_EINVAL, OPF_ESIZE. */
 int opf_decl_set(opf_ctx *ctx, int64_t size, const char *name, opf_set *out);
 
@@ -160,8 +161,9 @@ typedef struct {
     int64_t device_bytes;       /* device memory held by the plan                 */
     int64_t nclusters;          /* owner clusters (0 without clusters)            */
     int64_t owner_edge_visits;  /* edges run by the OWNER variant (>= E)          */
-    int32_t max_cluster_segments;
-    int32_t owner_ok;           /* 1 when the OWNER variant can run               */
+    int32_t max_cluster_segments; /* most cluster-pair segments of one cluster    */
+    int32_t owner_ok;           /* 1 when the plan has owner clusters (the OWNER
+                                   variant can run)                               */
 } opf_plan_info;
 
 /* Builds the execution plan of an arity-2 map (edges -> nodes) on the host
@@ -201,13 +203,20 @@ typedef struct {
     const int64_t *cluster_seg_offsets; /* [nclusters+1] into the two arrays below  */
     const int32_t *cluster_seg_start;   /* first edge of each segment of a cluster  */
     const int32_t *cluster_seg_len;     /* edges in the segment                     */
+    /* The same work as the OWNER variant reads it: cluster c runs the edges
+     * [cluster_range[2c], cluster_range[2c] + cluster_range[2c+1]) -- the edges
+     * whose smaller end it owns when they are contiguous, else an empty range --
+     * then cluster_list_edges[cluster_list_offsets[c] .. [c+1]), ascending. */
+    const int32_t *cluster_range;         /* [2 nclusters]                         */
+    const int64_t *cluster_list_offsets;  /* [nclusters+1]                         */
+    const int32_t *cluster_list_edges;
 } opf_plan_view;
 
 int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out);
 
 typedef struct {
     int32_t ok;        /* 1 when every property holds                         */
-    int32_t property;  /* first violated property 1..7, 0 if none            */
+    int32_t property;  /* first violated property 1..8, 0 if none            */
     int64_t where;     /* element (node, edge or partition) of the violation  */
     char message[160];
 } opf_plan_report;
@@ -219,7 +228,8 @@ typedef struct {
  * contiguous edge ranges of at most block_size edges, grouped by colour;
  * (6) local indices resolve to the map's nodes; (7) colour counts fit their
  * types; (8) every edge is in the work of exactly the owner clusters of its
- * two endpoints.  Works without a GPU.  Errors: OPF_EPLAN (report filled),
+ * two endpoints, in the segments and in the visit lists alike.  Works without
+ * a GPU.  Errors: OPF_EPLAN (report filled),
  * OPF_ESTATE (no plan). */
 int opf_plan_verify(const opf_ctx *ctx, opf_map map, opf_plan_report *report);
 

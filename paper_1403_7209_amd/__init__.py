@@ -82,7 +82,8 @@ class PlanView(ctypes.Structure):
                 ("unique_nodes", ctypes.c_void_p), ("local_idx", ctypes.c_void_p),
                 ("cluster_size", ctypes.c_int64), ("nclusters", ctypes.c_int64),
                 ("cluster_seg_offsets", ctypes.c_void_p), ("cluster_seg_start", ctypes.c_void_p),
-                ("cluster_seg_len", ctypes.c_void_p)]
+                ("cluster_seg_len", ctypes.c_void_p), ("cluster_range", ctypes.c_void_p),
+                ("cluster_list_offsets", ctypes.c_void_p), ("cluster_list_edges", ctypes.c_void_p)]
 
 
 class PlanReport(ctypes.Structure):
@@ -243,10 +244,17 @@ class Context:
         soff = arr(v.cluster_seg_offsets, ctypes.c_int64, ncl + 1, np.int64) if ncl else \
             np.zeros(1, np.int64)
         nseg = int(soff[-1])
+        loff = arr(v.cluster_list_offsets, ctypes.c_int64, ncl + 1, np.int64) if ncl else \
+            np.zeros(1, np.int64)
         return dict(nnodes=v.nnodes, nedges=E, nblocks=nb, nblock_colours=nc,
                     cluster_size=v.cluster_size, nclusters=ncl, cluster_seg_offsets=soff,
                     cluster_seg_start=arr(v.cluster_seg_start, ctypes.c_int32, nseg, np.int32),
                     cluster_seg_len=arr(v.cluster_seg_len, ctypes.c_int32, nseg, np.int32),
+                    cluster_range=arr(v.cluster_range, ctypes.c_int32, 2 * ncl,
+                                      np.int32).reshape(ncl, 2),
+                    cluster_list_offsets=loff,
+                    cluster_list_edges=arr(v.cluster_list_edges, ctypes.c_int32, int(loff[-1]),
+                                           np.int32),
                     block_size=v.block_size,
                     e2n=arr(v.e2n, ctypes.c_int32, 2 * E, np.int32).reshape(E, 2),
                     block_offsets=arr(v.block_offsets, ctypes.c_int64, nb + 1, np.int64),

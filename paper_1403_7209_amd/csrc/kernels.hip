@@ -258,12 +258,10 @@ struct PlanPtrs {
 };
 
 struct OwnerPtrs {
-    const uint32_t *omap;
-    const int *seg_off;
-    const int *seg_start;
-    const int *seg_pre;
-    const int2 *seg_cl;
-    const int *total;
+    const int2 *e2n;
+    const int2 *prim;     // [ncl] (first edge, count) of the cluster's contiguous range
+    const int *sec_off;   // [ncl+1]
+    const int *sec_eid;   // the cluster's other edges
 };
 
 template <typename T>
@@ -356,8 +354,6 @@ __device__ __forceinline__ void lds_put(T *base, int rows, int idx, const T *in)
 #pragma unroll
     for (int k = 0; k < W; ++k) dst[k * rows + idx] = tmp[k];
 }
-
-__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
 template <typename T, class Op>
 __host__ __device__ constexpr size_t stage_bytes(int rows)
@@ -497,15 +493,11 @@ __global__ __launch_bounds__(256) void k_edge_atomic(const int2 *__restrict__ e2
 
 // ------------------------------------------------------- owner kernel -- */
 
-// Packed owner map: per edge two 16-bit fields (first, second endpoint); bit 15
-// says which cluster of the edge's segment (0: the smaller, 1: the larger
-// cluster id) the endpoint lies in, bits 0..14 its offset inside that cluster.
-__device__ __forceinline__ int owner_node(uint32_t f, int2 cl, int K, int &cid)
-{
-    cid = (f & 0x8000u) ? cl.y : cl.x;
-    return cid * K + (int)(f & 0x7fffu);
-}
-
+// One workgroup per cluster of K consecutive nodes.  It runs every edge with
+// an end in the cluster: first the contiguous range of edges whose smaller end
+// it owns, then the listed edges whose larger end it owns.  A cut edge thus
+// runs in both of its clusters; each adds only to its own end, in LDS, and
+// writes its nodes' totals once.
 __host__ __device__ constexpr int owner_acc_rows(int K) { return K; }
 
 template <typename T, class Op, int NT>
@@ -514,9 +506,6 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
 {
     constexpr int B = OwnerTune<T, Op>::B;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_start[kMaxClusterSegments];
-    __shared__ int s_pre[kMaxClusterSegments + 1];
-    __shared__ int2 s_cl[kMaxClusterSegments];
     constexpr int NY = Op::MODE == GEN ? 2 * Op::NOUT : Op::NOUT;
     T *ss = reinterpret_cast<T *>(smem);
     double *sy = reinterpret_cast<double *>(smem + stage_bytes<T, Op>(K));
@@ -524,13 +513,9 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
 
     const int c = remap ? xcd_map((int)blockIdx.x, ncl) : (int)blockIdx.x;
     const int v0 = c * K, nown = min(K, N - v0);
-    const int s0 = p.seg_off[c], ns = p.seg_off[c + 1] - s0;
-    for (int t = threadIdx.x; t < ns; t += NT) {
-        s_start[t] = p.seg_start[s0 + t];
-        s_pre[t] = p.seg_pre[s0 + t];
-        s_cl[t] = p.seg_cl[s0 + t];
-    }
-    if (threadIdx.x == 0) s_pre[ns] = p.total[c];
+    const int2 pr = p.prim[c];
+    const int sb = p.sec_off[c];
+    const int total = pr.y + (p.sec_off[c + 1] - sb);
     // stage the owned nodes (contiguous ids: coalesced), clear the accumulator
     for (int v = threadIdx.x; v < nown; v += NT) {
         T rec[Op::NS];
@@ -541,62 +526,42 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
     }
     __syncthreads();
 
-    const int total = s_pre[ns];
-    // cursor over the cluster's segments; edge positions only grow
-    int sc = 0;
-    {
-        int lo = 0, hi = ns - 1;
-        const int k = min((int)threadIdx.x, max(total - 1, 0));
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_pre[mid] <= k)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        sc = lo;
-    }
     for (int k0 = threadIdx.x; k0 < total; k0 += NT * B) {
         // resolve B edges and issue all their global loads first
-        int eid[B], sg[B];
-        uint32_t m[B];
-        T w[B][3];
+        int eid[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int k = k0 + b * NT;
-            sg[b] = -1;
-            eid[b] = 0;
-            if (k < total) {
-                while (sc + 1 < ns && s_pre[sc + 1] <= k) ++sc;
-                sg[b] = sc;
-                eid[b] = s_start[sc] + (k - s_pre[sc]);
-            }
+            eid[b] = -1;
+            if (k < pr.y)
+                eid[b] = pr.x + k;
+            else if (k < total)
+                eid[b] = ld(p.sec_eid, sb + (k - pr.y));
         }
+        int2 ij[B];
+        T w[B][3];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            if (sg[b] >= 0) {
-                m[b] = ld(p.omap, eid[b]);
+            if (eid[b] >= 0) {
+                ij[b] = ld(p.e2n, eid[b]);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) w[b][d] = ld(a.w[d], eid[b]);
             }
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            if (sg[b] < 0) continue;
-            const int2 cl = s_cl[sg[b]];
-            int ci, cj;
-            const int gi = owner_node(m[b] & 0xffffu, cl, K, ci);
-            const int gj = owner_node(m[b] >> 16, cl, K, cj);
-            const bool oi = ci == c, oj = cj == c;
+            if (eid[b] < 0) continue;
+            const int li = ij[b].x - v0, lj = ij[b].y - v0;
+            const bool oi = (unsigned)li < (unsigned)nown, oj = (unsigned)lj < (unsigned)nown;
             T si[Op::NS], sj[Op::NS];
             if (oi)
-                lds_get<T, Op::NS>(ss, K, gi - v0, si);
+                lds_get<T, Op::NS>(ss, K, li, si);
             else
-                load_stage<Op>(a, gi, gamma, si);
+                load_stage<Op>(a, ij[b].x, gamma, si);
             if (oj)
-                lds_get<T, Op::NS>(ss, K, gj - v0, sj);
+                lds_get<T, Op::NS>(ss, K, lj, sj);
             else
-                load_stage<Op>(a, gj, gamma, sj);
+                load_stage<Op>(a, ij[b].y, gamma, sj);
             double y[NY];
             double wo[3] = {0.0, 0.0, 0.0};
             Op::edge(si, sj, w[b], gamma, y, y + (NY - Op::NOUT), wo);
@@ -604,11 +569,11 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
             for (int v = 0; v < Op::NOUT; ++v) {
                 const double yi = y[v];
                 const double yj = Op::MODE == ANTI ? -yi : Op::MODE == SAME ? yi : y[Op::NOUT + v];
-                if (oi) lds_add(&sy[v * AR + (gi - v0)], yi);
-                if (oj) lds_add(&sy[v * AR + (gj - v0)], yj);
+                if (oi) lds_add(&sy[v * AR + li], yi);
+                if (oj) lds_add(&sy[v * AR + lj], yj);
             }
-            // a direct output is written by the smaller cluster of the segment only
-            if (Op::NWOUT && cl.x == c) {
+            // a direct output is written by the cluster of the smaller end only
+            if (Op::NWOUT && (ij[b].x < ij[b].y ? oi : oj)) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) st(a.wo[d], eid[b], wo[d]);
             }
@@ -785,7 +750,7 @@ int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t s
 {
     if (!P.owner_ok || P.ncl <= 0) return (int)hipErrorInvalidValue;
     const size_t lds = owner_dyn_lds<T, Op>(P.K);
-    const OwnerPtrs op{P.omap, P.seg_off, P.seg_start, P.seg_pre, P.seg_cl, P.cl_total};
+    const OwnerPtrs op{P.e2n, P.prim, P.sec_off, P.sec_eid};
     hipLaunchKernelGGL((k_edge_owner<T, Op, kOwnerThreads>), dim3(P.ncl), dim3(kOwnerThreads), lds,
                        st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
     return (int)hipGetLastError();
@@ -845,12 +810,9 @@ int raise_all(size_t bytes)
 
 size_t owner_lds_bytes(int op, bool fp32, int K)
 {
-    const size_t fixed =
-        align16(sizeof(int) * (2 * kMaxClusterSegments + 1) + sizeof(int2) * kMaxClusterSegments);
-    if (op == OP_ADJOINT) return fixed + owner_dyn_lds<double, OpAdjoint>(K);
-    if (op == OP_SPECRAD)
-        return fixed + (fp32 ? owner_dyn_lds<float, OpSpecrad>(K) : owner_dyn_lds<double, OpSpecrad>(K));
-    return fixed + (fp32 ? owner_dyn_lds<float, OpFlux>(K) : owner_dyn_lds<double, OpFlux>(K));
+    if (op == OP_ADJOINT) return owner_dyn_lds<double, OpAdjoint>(K);
+    if (op == OP_SPECRAD) return fp32 ? owner_dyn_lds<float, OpSpecrad>(K) : owner_dyn_lds<double, OpSpecrad>(K);
+    return fp32 ? owner_dyn_lds<float, OpFlux>(K) : owner_dyn_lds<double, OpFlux>(K);
 }
 
 }  // namespace

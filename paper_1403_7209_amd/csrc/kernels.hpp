@@ -14,7 +14,6 @@ enum EdgeOpKind { OP_FLUX = 0, OP_ADJOINT = 1, OP_SPECRAD = 2 };
 // Execution variants of an edge loop (values match opf_variant).
 enum Variant { V_COLOURED = 0, V_ATOMIC = 1, V_OWNER = 2, V_COLOURED_LDS_ATOMIC = 3 };
 
-constexpr int kMaxClusterSegments = 256;
 constexpr int kOwnerThreads = 512;
 
 // Device copy of an execution plan (internal numbering, int32 offsets).
@@ -29,15 +28,13 @@ struct DevPlan {
     const int *block_ncol = nullptr;     // [nb]
     const int *colour_blocks = nullptr;  // [nb]
     std::vector<int> colour_off;         // host copy [nc+1]
-    // owner clusters
+    // owner clusters: cluster c runs edges [prim[c].x, prim[c].x + prim[c].y),
+    // then sec_eid[sec_off[c] .. sec_off[c+1])
     int K = 0, ncl = 0;
     bool owner_ok = false;
-    const int *seg_off = nullptr;    // [ncl+1]
-    const int *seg_start = nullptr;  // first edge of each segment
-    const int *seg_pre = nullptr;    // edges of the cluster before this segment
-    const int2 *seg_cl = nullptr;    // (smaller, larger) cluster joined by the segment
-    const int *cl_total = nullptr;   // [ncl] edges of each cluster
-    const uint32_t *omap = nullptr;  // [E] packed owner map (cluster flag + offset)
+    const int2 *prim = nullptr;    // [ncl]
+    const int *sec_off = nullptr;  // [ncl+1]
+    const int *sec_eid = nullptr;  // [sec_off[ncl]]
 };
 
 // Component pointers of the arrays an edge loop touches (SoA: one pointer per

@@ -159,46 +159,16 @@ int upload_plan(opf_ctx *ctx, PlanRec &pr)
     D.K = P.cluster_size;
     D.ncl = (int)P.nclusters();
     D.owner_ok = P.owner_ok && D.ncl > 0;
-    std::vector<int> seg_off, seg_start, seg_pre, cl_total;
-    std::vector<int2> seg_cl;
-    std::vector<uint32_t> omap;
-    if (D.owner_ok && P.cluster_size > 32768) D.owner_ok = false;
+    std::vector<int2> prim;
+    std::vector<int> sec_off;
     if (D.owner_ok) {
-        const int K = P.cluster_size;
-        omap.resize(P.E);
-        for (int64_t k = 0; k < P.E; ++k) {
-            const int32_t a = P.e2n[2 * k], b = P.e2n[2 * k + 1];
-            const int32_t cb = std::max(a, b) / K;
-            const bool split = a / K != b / K;
-            const uint32_t fa = (uint32_t)(a % K) | ((split && a / K == cb) ? 0x8000u : 0u);
-            const uint32_t fb = (uint32_t)(b % K) | ((split && b / K == cb) ? 0x8000u : 0u);
-            omap[k] = fa | (fb << 16);
-        }
-        seg_cl.resize(P.cl_seg_start.size());
-        for (size_t t = 0; t < seg_cl.size(); ++t) {
-            const int64_t k = P.cl_seg_start[t];
-            const int32_t a = P.e2n[2 * k], b = P.e2n[2 * k + 1];
-            seg_cl[t] = make_int2(std::min(a, b) / K, std::max(a, b) / K);
-        }
-        seg_off.resize(D.ncl + 1);
-        for (int c = 0; c <= D.ncl; ++c) seg_off[c] = (int)P.cl_seg_off[c];
-        seg_start.assign(P.cl_seg_start.begin(), P.cl_seg_start.end());
-        seg_pre.resize(P.cl_seg_start.size());
-        cl_total.resize(D.ncl);
-        for (int c = 0; c < D.ncl; ++c) {
-            int acc = 0;
-            for (int64_t k = P.cl_seg_off[c]; k < P.cl_seg_off[c + 1]; ++k) {
-                seg_pre[k] = acc;
-                acc += P.cl_seg_len[k];
-            }
-            cl_total[c] = acc;
-        }
-        if (!rc) rc = upload(ctx, pr, seg_off, D.seg_off);
-        if (!rc) rc = upload(ctx, pr, seg_start, D.seg_start);
-        if (!rc) rc = upload(ctx, pr, seg_pre, D.seg_pre);
-        if (!rc) rc = upload(ctx, pr, cl_total, D.cl_total);
-        if (!rc) rc = upload(ctx, pr, seg_cl, D.seg_cl);
-        if (!rc) rc = upload(ctx, pr, omap, D.omap);
+        prim.resize(D.ncl);
+        sec_off.resize(D.ncl + 1);
+        for (int c = 0; c < D.ncl; ++c) prim[c] = make_int2(P.cl_prim[2 * c], P.cl_prim[2 * c + 1]);
+        for (int c = 0; c <= D.ncl; ++c) sec_off[c] = (int)P.cl_sec_off[c];
+        if (!rc) rc = upload(ctx, pr, prim, D.prim);
+        if (!rc) rc = upload(ctx, pr, sec_off, D.sec_off);
+        if (!rc) rc = upload(ctx, pr, P.cl_sec_eid, D.sec_eid);
     }
     if (!rc) rc = upload(ctx, pr, e2n, D.e2n);
     if (!rc) rc = upload(ctx, pr, block_off, D.block_off);
@@ -494,8 +464,8 @@ int opf_set_allocator(opf_ctx *ctx, void *(*alloc_fn)(void *, size_t), void (*fr
 int opf_decl_set(opf_ctx *ctx, int64_t size, const char *name, opf_set *out)
 {
     if (!ctx || !out) return ctx ? ctx->fail(OPF_EINVAL, "out is NULL") : OPF_EINVAL;
-    if (size <= 0 || size >= ((int64_t)1 << 31))
-        return ctx->fail(OPF_ESIZE, "set size must be in (0, 2^31)");
+    if (size <= 0 || size >= ((int64_t)1 << 29))
+        return ctx->fail(OPF_ESIZE, "set size must be in (0, 2^29)");
     SetRec s;
     s.size = size;
     s.name = name ? name : "";
@@ -661,6 +631,9 @@ int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out)
     out->cluster_seg_offsets = P.cl_seg_off.data();
     out->cluster_seg_start = P.cl_seg_start.data();
     out->cluster_seg_len = P.cl_seg_len.data();
+    out->cluster_range = P.cl_prim.data();
+    out->cluster_list_offsets = P.cl_sec_off.data();
+    out->cluster_list_edges = P.cl_sec_eid.data();
     return OPF_OK;
 }
 

@@ -437,7 +437,44 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
                 P.cl_seg_len[P.cl_seg_off[c] + s] = segs[c][s].second;
                 P.owner_edge_visits += segs[c][s].second;
             }
-        P.owner_ok = P.max_cluster_segments <= kMaxClusterSegments;
+        // visit lists: the contiguous range of edges whose smaller end lies in
+        // the cluster, then every other edge that touches it
+        std::vector<int64_t> first(ncl, -1), last(ncl, -1), cnt(ncl, 0);
+        for (int64_t e = 0; e < E; ++e) {
+            const int64_t a = std::min(P.e2n[2 * e], P.e2n[2 * e + 1]) / K;
+            if (first[a] < 0) first[a] = e;
+            last[a] = e;
+            ++cnt[a];
+        }
+        P.cl_prim.assign(2 * ncl, 0);
+        for (int64_t c = 0; c < ncl; ++c)
+            if (cnt[c] > 0 && last[c] - first[c] + 1 == cnt[c]) {
+                P.cl_prim[2 * c] = (int32_t)first[c];
+                P.cl_prim[2 * c + 1] = (int32_t)cnt[c];
+            }
+        auto in_prim = [&](int64_t c, int64_t e) {
+            return e >= P.cl_prim[2 * c] && e < (int64_t)P.cl_prim[2 * c] + P.cl_prim[2 * c + 1];
+        };
+        P.cl_sec_off.assign(ncl + 1, 0);
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<int64_t> fill(P.cl_sec_off.begin(), P.cl_sec_off.end() - 1);
+            for (int64_t e = 0; e < E; ++e) {
+                const int64_t a = P.e2n[2 * e] / K, b = P.e2n[2 * e + 1] / K;
+                const int64_t cs[2] = {a, b};
+                for (int t = 0; t < (a == b ? 1 : 2); ++t) {
+                    if (in_prim(cs[t], e)) continue;
+                    if (pass == 0)
+                        ++P.cl_sec_off[cs[t] + 1];
+                    else
+                        P.cl_sec_eid[fill[cs[t]]++] = (int32_t)e;
+                }
+            }
+            if (pass == 0) {
+                for (int64_t c = 0; c < ncl; ++c) P.cl_sec_off[c + 1] += P.cl_sec_off[c];
+                P.cl_sec_eid.resize(P.cl_sec_off[ncl]);
+            }
+        }
+        P.owner_ok = true;
     }
     lap(2);
 
@@ -632,6 +669,33 @@ VerifyResult verify_plan(const Plan &P, const int32_t *e2n_user)
         for (int64_t k = 0; k < E; ++k) {
             const int want = (P.e2n[2 * k] / K == P.e2n[2 * k + 1] / K) ? 1 : 2;
             if (seen[k] != want) return fail(8, k, "edge missing from its clusters' work");
+        }
+        // the visit lists hold the same work
+        if ((int64_t)P.cl_prim.size() != 2 * ncl || (int64_t)P.cl_sec_off.size() != ncl + 1 ||
+            P.cl_sec_off[0] != 0 || P.cl_sec_off[ncl] != (int64_t)P.cl_sec_eid.size())
+            return fail(8, -1, "cluster visit lists are inconsistent");
+        std::fill(seen.begin(), seen.end(), 0);
+        auto visit = [&](int64_t c, int64_t k) -> bool {
+            if (k < 0 || k >= E) return false;
+            const int64_t a = P.e2n[2 * k] / K, b = P.e2n[2 * k + 1] / K;
+            if ((a != c && b != c) || seen[k] == 255) return false;
+            ++seen[k];
+            return true;
+        };
+        for (int64_t c = 0; c < ncl; ++c) {
+            const int64_t p0 = P.cl_prim[2 * c], pn = P.cl_prim[2 * c + 1];
+            if (pn < 0) return fail(8, c, "negative visit range");
+            for (int64_t k = p0; k < p0 + pn; ++k)
+                if (!visit(c, k)) return fail(8, k, "visit range holds an edge of another cluster");
+            for (int64_t s = P.cl_sec_off[c]; s < P.cl_sec_off[c + 1]; ++s) {
+                if (s > P.cl_sec_off[c] && P.cl_sec_eid[s] <= P.cl_sec_eid[s - 1])
+                    return fail(8, c, "visit list not ascending");
+                if (!visit(c, P.cl_sec_eid[s])) return fail(8, s, "visit list holds an edge of another cluster");
+            }
+        }
+        for (int64_t k = 0; k < E; ++k) {
+            const int want = (P.e2n[2 * k] / K == P.e2n[2 * k + 1] / K) ? 1 : 2;
+            if (seen[k] != want) return fail(8, k, "edge missing from its clusters' visit lists");
         }
     }
     return r;

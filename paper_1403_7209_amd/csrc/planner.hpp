@@ -16,8 +16,6 @@ namespace opf {
 
 constexpr int kMaxBlockColours = 1024;
 
-constexpr int kMaxClusterSegments = 256;
-
 struct PlanOptions {
     int renumber = 1;  // 0 none, 1 RCM, 2 Morton
     int block_size = 512;
@@ -56,11 +54,18 @@ struct Plan {
     // y == c, the (c, c) segment first.
     int32_t cluster_size = 0;
     int32_t max_cluster_segments = 0;
-    bool owner_ok = false;              // every cluster fits kMaxClusterSegments
+    bool owner_ok = false;              // the plan has owner clusters
     std::vector<int64_t> cl_seg_off;    // [ncl+1] into cl_seg_start / cl_seg_len
     std::vector<int32_t> cl_seg_start;  // first internal edge of each segment
     std::vector<int32_t> cl_seg_len;    // edges in the segment
     int64_t owner_edge_visits = 0;      // sum over clusters of their edges
+    // The same work as visit lists: cluster c runs the edges
+    // [cl_prim[2c], cl_prim[2c] + cl_prim[2c+1]) (the edges whose smaller end
+    // it owns, when they are contiguous; else an empty range), then the edges
+    // cl_sec_eid[cl_sec_off[c] .. cl_sec_off[c+1]) in ascending order.
+    std::vector<int32_t> cl_prim;     // [2 ncl]
+    std::vector<int64_t> cl_sec_off;  // [ncl+1]
+    std::vector<int32_t> cl_sec_eid;
     int64_t nclusters() const { return cluster_size ? (N + cluster_size - 1) / cluster_size : 0; }
     int64_t nblocks() const { return (int64_t)block_colour.size(); }
 };
@@ -77,7 +82,7 @@ struct VerifyResult {
     std::string message;
 };
 
-// Bit-exact check of the plan's properties (1..7) against the user map.
+// Bit-exact check of the plan's properties (1..8) against the user map.
 VerifyResult verify_plan(const Plan &plan, const int32_t *e2n_user);
 
 }  // namespace opf

@@ -84,7 +84,7 @@ def test_residual_small(small, renumber, bs, csort, K, lg):
     print(f"[residual {name} {renumber} bs={bs} sort={csort} K={K} groups={lg}]", flush=True)
     p = problem(m, q, renumber=renumber, block_size=bs, colour_sort=csort, cluster_size=K,
                 lane_groups=lg)
-    assert p.info["owner_ok"] == (K > 0 and p.info["max_cluster_segments"] <= 256)
+    assert p.info["owner_ok"] == (K > 0)
     for variant in variants(p):
         res = gpu_residual(p, variant)
         assert report(f"variant {variant}", normwise(res, ref), TOL64)

@@ -90,6 +90,28 @@ def check_plan_properties(m, ctx, nodes, edges, mp):
                 cnt[ks] += 1
         want = np.where(e2n[:, 0] // K == e2n[:, 1] // K, 1, 2)
         assert np.array_equal(cnt, want)
+        # the visit lists hold the same work: the contiguous range of edges
+        # whose smaller end the cluster owns (or nothing), then the rest ascending
+        cmin = e2n.min(axis=1) // K
+        rng, loff, led = v["cluster_range"], v["cluster_list_offsets"], v["cluster_list_edges"]
+        cnt[:] = 0
+        contiguous = 0
+        for c in range(v["nclusters"]):
+            mine = np.nonzero(cmin == c)[0]
+            r0, rn = rng[c]
+            if rn:
+                assert rn == len(mine) and r0 == mine[0] and mine[-1] == r0 + rn - 1
+                contiguous += 1
+            else:
+                assert len(mine) == 0 or mine[-1] - mine[0] + 1 != len(mine)
+            rest = led[loff[c]:loff[c + 1]]
+            assert np.all(np.diff(rest) > 0)
+            ks = np.concatenate([np.arange(r0, r0 + rn), rest]).astype(np.int64)
+            cl = e2n[ks] // K
+            assert np.all((cl[:, 0] == c) | (cl[:, 1] == c))
+            cnt[ks] += 1
+        assert np.array_equal(cnt, want)
+        return contiguous / v["nclusters"]
 
 
 @pytest.mark.parametrize("renumber,bs,K,lg,csort", [("rcm", 512, 512, True, False),
@@ -102,10 +124,13 @@ def test_plan_properties(renumber, bs, K, lg, csort):
                                                cluster_size=K, lane_groups=lg,
                                                colour_sort=csort)
     assert ctx.plan_verify(mp)["ok"]
-    check_plan_properties(m, ctx, nodes, edges, mp)
+    contiguous = check_plan_properties(m, ctx, nodes, edges, mp)
     assert info["nblocks"] == -(-m.E // bs)
     if K:
         assert info["owner_edge_visits"] >= m.E
+        assert info["owner_ok"]
+        # without the colour sort every cluster's own edges form one range
+        assert csort or contiguous == 1.0
 
 
 def test_renumbering_reduces_bandwidth_and_verifier_on_config_a():
@@ -127,11 +152,12 @@ def test_lane_groups_make_wavefront_endpoints_distinct():
                                                    lane_groups=lg)
         v = ctx.plan_view(mp)
         e2n = v["e2n"]
-        soff, st, ln = v["cluster_seg_offsets"], v["cluster_seg_start"], v["cluster_seg_len"]
+        rng, loff, led = v["cluster_range"], v["cluster_list_offsets"], v["cluster_list_edges"]
         rep = tot = 0
         for c in range(v["nclusters"]):
-            visits = np.concatenate([np.arange(st[s], st[s] + ln[s])
-                                     for s in range(soff[c], soff[c + 1])])
+            # the order in which the owner kernel's lanes take the cluster's edges
+            visits = np.concatenate([np.arange(rng[c, 0], rng[c, 0] + rng[c, 1]),
+                                     led[loff[c]:loff[c + 1]]])
             for w0 in range(0, len(visits), 64):
                 ends = e2n[visits[w0:w0 + 64]].ravel()
                 own = ends[ends // K == c]
@@ -145,6 +171,9 @@ def test_declaration_errors():
     ctx = pk.Context(None)
     with pytest.raises(pk.OpfError) as e:
         ctx.decl_set(0)
+    assert e.value.status == pk.ESIZE
+    with pytest.raises(pk.OpfError) as e:
+        ctx.decl_set(1 << 29)  # beyond 32-bit byte offsets of FP64 components
     assert e.value.status == pk.ESIZE
     nodes = ctx.decl_set(4, "nodes")
     edges = ctx.decl_set(3, "edges")
