@@ -50,8 +50,25 @@ namespace {
 
 enum Mode { ANTI = 0, SAME = 1, GEN = 2 };
 
-__device__ __forceinline__ double tsqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float tsqrt(float x) { return sqrtf(x); }
+// Reciprocal and square root from the hardware approximations (relative error
+// about 2^-24).  FP64 refines each by one Newton (Goldschmidt) step, which
+// squares the error: a few ulp, far inside the loop's tolerance, at a third of
+// the instructions of the correctly rounded sequences.  FP32 uses them as they
+// are (about 1 ulp).  Arguments are densities, squared sound speeds and squared
+// face areas: non-negative; a zero square root comes out as 0.
+__device__ __forceinline__ double trcp(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float trcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double tsqrt(double x)
+{
+    const double r = __builtin_amdgcn_rsq(fmax(x, 1e-300));
+    const double g = x * r, h = 0.5 * r;
+    return fma(g, fma(-g, h, 0.5), g);
+}
+__device__ __forceinline__ float tsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double tabs(double x) { return fabs(x); }
 __device__ __forceinline__ float tabs(float x) { return fabsf(x); }
 
@@ -66,7 +83,7 @@ struct OpFlux {
     template <typename T>
     __device__ static __forceinline__ void stage(const T *x, T *s, T gamma)
     {
-        const T ir = T(1) / x[0];
+        const T ir = trcp(x[0]);
         s[0] = x[0];
         s[1] = x[1] * ir;
         s[2] = x[2] * ir;
@@ -104,7 +121,7 @@ struct OpSpecrad {
     template <typename T>
     __device__ static __forceinline__ void stage(const T *x, T *s, T gamma)
     {
-        const T ir = T(1) / x[0];
+        const T ir = trcp(x[0]);
         s[0] = x[1] * ir;
         s[1] = x[2] * ir;
         s[2] = x[3] * ir;
@@ -131,7 +148,7 @@ struct Prim {
 template <typename T>
 __device__ __forceinline__ void prim(const T *q, const T *n, T gamma, Prim<T> &s)
 {
-    const T ir = T(1) / q[0];
+    const T ir = trcp(q[0]);
     s.u0 = q[1] * ir;
     s.u1 = q[2] * ir;
     s.u2 = q[3] * ir;
@@ -162,8 +179,8 @@ __device__ __forceinline__ void node_reverse(const double *q, const Prim<double>
     // U = u.n
     double ub0 = Ub * n[0], ub1 = Ub * n[1], ub2 = Ub * n[2];
     // c = sqrt(gamma p / rho)
-    const double ir = 1.0 / q[0];
-    const double sb = cb / (2.0 * s.c);
+    const double ir = trcp(q[0]);
+    const double sb = 0.5 * cb * trcp(s.c);
     pb += sb * gamma * ir;
     double rb = -sb * (s.c * s.c) * ir;
     // p = (gamma - 1)(q4 - ke/2), ke = q1 u0 + q2 u1 + q3 u2
@@ -205,7 +222,7 @@ struct OpAdjoint {
         Prim<double> a, b;
         prim(qi, n, gamma, a);
         prim(qj, n, gamma, b);
-        const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        const double nn = tsqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
         const double A = 0.5 * (a.U + b.U);
         const double lam = fabs(A) + 0.5 * (a.c + b.c) * nn;
         // F_v = (f_i,v + f_j,v)/2 - lam/2 (q_j,v - q_i,v)
@@ -220,9 +237,10 @@ struct OpAdjoint {
         const double Ab = (signbit(A) ? -1.0 : 1.0) * lamb;
         const double cb = 0.5 * nn * lamb;
         const double nnb = 0.5 * (a.c + b.c) * lamb;
-        wo[0] = nnb * n[0] / nn;
-        wo[1] = nnb * n[1] / nn;
-        wo[2] = nnb * n[2] / nn;
+        const double inn = nnb * trcp(nn);
+        wo[0] = inn * n[0];
+        wo[1] = inn * n[1];
+        wo[2] = inn * n[2];
         double fb[6];
 #pragma unroll
         for (int v = 0; v < 6; ++v) fb[v] = 0.5 * Fb[v];
