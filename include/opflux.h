@@ -86,8 +86,14 @@ typedef enum {
                            once; single launch, no colours (owner-compute as in
                            Sec. 3.2, at workgroup level).  LDS accumulation uses
                            FP64 LDS atomics, so the summation order varies      */
-    OPF_V_COLOURED_LDS_ATOMIC = 3 /* as COLOURED, with LDS atomics in place of
-                           the edge colours inside a partition                  */
+    OPF_V_COLOURED_LDS_ATOMIC = 3, /* as COLOURED, with LDS atomics in place
+                           of the edge colours inside a partition               */
+    OPF_V_FLAT = 4      /* one level of colours over the whole edge set (no
+                           partitions, no staging): one launch per colour, one
+                           thread per edge, plain read-add-write of both ends in
+                           HBM -- the single-level counterpart of the Sec. 4.1
+                           plan; deterministic.  Unavailable (OPF_EINVAL) when
+                           the map needs more than 128 colours                  */
 } opf_variant;
 
 typedef enum { OPF_RENUM_NONE = 0, OPF_RENUM_RCM = 1, OPF_RENUM_MORTON = 2 } opf_renumber;
@@ -164,6 +170,8 @@ typedef struct {
     int32_t max_cluster_segments; /* most cluster-pair segments of one cluster    */
     int32_t owner_ok;           /* 1 when the plan has owner clusters (the OWNER
                                    variant can run)                               */
+    int32_t flat_colours;       /* colours of the flat colouring                  */
+    int32_t flat_ok;            /* 1 when the FLAT variant can run (<= 128)       */
 } opf_plan_info;
 
 /* Builds the execution plan of an arity-2 map (edges -> nodes) on the host
@@ -210,13 +218,18 @@ typedef struct {
     const int32_t *cluster_range;         /* [2 nclusters]                         */
     const int64_t *cluster_list_offsets;  /* [nclusters+1]                         */
     const int32_t *cluster_list_edges;
+    /* Flat colouring: edges flat_edges[flat_offsets[c] .. [c+1]) have colour c
+     * (ascending); NULL when the FLAT variant is unavailable. */
+    int64_t nflat_colours;
+    const int64_t *flat_offsets;  /* [nflat_colours+1]                          */
+    const int32_t *flat_edges;    /* [E]                                        */
 } opf_plan_view;
 
 int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out);
 
 typedef struct {
     int32_t ok;        /* 1 when every property holds                         */
-    int32_t property;  /* first violated property 1..8, 0 if none            */
+    int32_t property;  /* first violated property 1..9, 0 if none            */
     int64_t where;     /* element (node, edge or partition) of the violation  */
     char message[160];
 } opf_plan_report;
@@ -228,8 +241,9 @@ typedef struct {
  * contiguous edge ranges of at most block_size edges, grouped by colour;
  * (6) local indices resolve to the map's nodes; (7) colour counts fit their
  * types; (8) every edge is in the work of exactly the owner clusters of its
- * two endpoints, in the segments and in the visit lists alike.  Works without
- * a GPU.  Errors: OPF_EPLAN (report filled),
+ * two endpoints, in the segments and in the visit lists alike; (9) every edge
+ * has exactly one flat colour and edges of one flat colour share no node.
+ * Works without a GPU.  Errors: OPF_EPLAN (report filled),
  * OPF_ESTATE (no plan). */
 int opf_plan_verify(const opf_ctx *ctx, opf_map map, opf_plan_report *report);
 

@@ -18,7 +18,7 @@ import torch
 from . import _build
 
 __all__ = ["Context", "OpfError", "FluxProblem", "EdgeFluxFunction", "RK_ALPHA", "load",
-           "COLOURED", "ATOMIC", "OWNER", "COLOURED_LDS_ATOMIC", "VARIANTS"]
+           "COLOURED", "ATOMIC", "OWNER", "COLOURED_LDS_ATOMIC", "FLAT", "VARIANTS"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = _build.LIB
@@ -31,9 +31,9 @@ STATUS = {0: "OPF_OK", -1: "OPF_EINVAL", -2: "OPF_ERANGE", -3: "OPF_ESIZE", -4: 
 F64, F32 = 0, 1
 READ, WRITE, RW, INC, MIN = 0, 1, 2, 3, 4
 K_EDGE_FLUX, K_EDGE_FLUX_ADJ, K_RK_STAGE, K_EDGE_SPECRAD, K_DT_MIN = 0, 1, 2, 3, 4
-COLOURED, ATOMIC, OWNER, COLOURED_LDS_ATOMIC = 0, 1, 2, 3
+COLOURED, ATOMIC, OWNER, COLOURED_LDS_ATOMIC, FLAT = 0, 1, 2, 3, 4
 VARIANTS = {"coloured": COLOURED, "atomic": ATOMIC, "owner": OWNER,
-            "coloured-lds-atomic": COLOURED_LDS_ATOMIC}
+            "coloured-lds-atomic": COLOURED_LDS_ATOMIC, "flat": FLAT}
 RENUMBER = {"none": 0, "rcm": 1, "morton": 2}
 ID = -1
 
@@ -69,7 +69,8 @@ class PlanInfo(ctypes.Structure):
                 ("bandwidth_after", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("nclusters", ctypes.c_int64),
                 ("owner_edge_visits", ctypes.c_int64), ("max_cluster_segments", ctypes.c_int32),
-                ("owner_ok", ctypes.c_int32)]
+                ("owner_ok", ctypes.c_int32), ("flat_colours", ctypes.c_int32),
+                ("flat_ok", ctypes.c_int32)]
 
 
 class PlanView(ctypes.Structure):
@@ -83,7 +84,9 @@ class PlanView(ctypes.Structure):
                 ("cluster_size", ctypes.c_int64), ("nclusters", ctypes.c_int64),
                 ("cluster_seg_offsets", ctypes.c_void_p), ("cluster_seg_start", ctypes.c_void_p),
                 ("cluster_seg_len", ctypes.c_void_p), ("cluster_range", ctypes.c_void_p),
-                ("cluster_list_offsets", ctypes.c_void_p), ("cluster_list_edges", ctypes.c_void_p)]
+                ("cluster_list_offsets", ctypes.c_void_p), ("cluster_list_edges", ctypes.c_void_p),
+                ("nflat_colours", ctypes.c_int64), ("flat_offsets", ctypes.c_void_p),
+                ("flat_edges", ctypes.c_void_p)]
 
 
 class PlanReport(ctypes.Structure):
@@ -265,7 +268,12 @@ class Context:
                     block_ncolours=arr(v.block_ncolours, ctypes.c_int32, nb, np.int32),
                     unique_offsets=uoff,
                     unique_nodes=arr(v.unique_nodes, ctypes.c_int32, int(uoff[-1]), np.int32),
-                    local_idx=arr(v.local_idx, ctypes.c_uint16, 2 * E, np.uint16).reshape(E, 2))
+                    local_idx=arr(v.local_idx, ctypes.c_uint16, 2 * E, np.uint16).reshape(E, 2),
+                    nflat_colours=v.nflat_colours,
+                    flat_offsets=arr(v.flat_offsets, ctypes.c_int64, v.nflat_colours + 1,
+                                     np.int64) if v.nflat_colours else None,
+                    flat_edges=arr(v.flat_edges, ctypes.c_int32, E, np.int32)
+                    if v.nflat_colours else None)
 
     def plan_verify(self, m):
         rep = PlanReport()

@@ -5,7 +5,7 @@
 // node increments.  Every kernel first turns a node's inputs into a "staged"
 // record once per node (state plus primitives: 1/rho, pressure, sound speed),
 // so the per-edge work needs no division or square root besides |n_e|.
-// Three ways to resolve the increments:
+// Four ways to resolve the increments:
 //   * coloured (Sec. 4.1): one workgroup per mini-partition, one launch per
 //     partition colour.  The partition's distinct nodes are staged in LDS (the
 //     Sec. 4.1.2 staging; gfx950 has 160 KB of LDS per CU), increments go into
@@ -13,6 +13,9 @@
 //     the ablation variant), then the partition adds its accumulator to HBM
 //     with plain read-modify-write: partitions of one colour share no node.
 //   * atomic: one thread per edge, FP64 atomic adds straight to HBM.
+//   * flat: one level of edge colours over the whole mesh, one launch per
+//     colour, one thread per edge, plain read-add-write in HBM (the
+//     single-level counterpart of the Sec. 4.1 plan).
 //   * owner: one workgroup per contiguous cluster of K nodes runs every edge
 //     that touches the cluster (edges joining two clusters run in both), adds
 //     only into its own nodes' LDS accumulator (ds_add_f64) and writes each
@@ -509,6 +512,42 @@ __global__ __launch_bounds__(256) void k_edge_atomic(const int2 *__restrict__ e2
     }
 }
 
+// ------------------------------------------------------- flat kernel -- */
+
+// One colour of the flat colouring: one thread per edge, both ends gathered
+// from HBM, both increments added with a plain read-add-write (no other edge
+// of this colour touches either end).
+template <typename T, class Op>
+__global__ __launch_bounds__(256) void k_edge_flat(const int2 *__restrict__ e2n,
+                                                   const int *__restrict__ eids, int n, Arrays<T> a,
+                                                   T gamma)
+{
+    const int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (t >= n) return;
+    const int e = eids[t];
+    const int2 ij = ld(e2n, e);
+    T si[Op::NS], sj[Op::NS], w[3];
+    load_stage<Op>(a, ij.x, gamma, si);
+    load_stage<Op>(a, ij.y, gamma, sj);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) w[d] = ld(a.w[d], e);
+    constexpr int NY = Op::MODE == GEN ? 2 * Op::NOUT : Op::NOUT;
+    double y[NY];
+    double wo[3] = {0.0, 0.0, 0.0};
+    Op::edge(si, sj, w, gamma, y, y + (NY - Op::NOUT), wo);
+#pragma unroll
+    for (int v = 0; v < Op::NOUT; ++v) {
+        const double yi = y[v];
+        const double yj = Op::MODE == ANTI ? -yi : Op::MODE == SAME ? yi : y[Op::NOUT + v];
+        st(a.y[v], ij.x, ld(a.y[v], ij.x) + yi);
+        st(a.y[v], ij.y, ld(a.y[v], ij.y) + yj);
+    }
+    if (Op::NWOUT) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) st(a.wo[d], e, wo[d]);
+    }
+}
+
 // ------------------------------------------------------- owner kernel -- */
 
 // One workgroup per cluster of K consecutive nodes.  It runs every edge with
@@ -757,6 +796,21 @@ int run_atomic(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t 
 }
 
 template <typename T, class Op>
+int run_flat(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st)
+{
+    if (P.nflat <= 0) return (int)hipErrorInvalidValue;
+    for (int c = 0; c < P.nflat; ++c) {
+        const int64_t off = P.flat_off[c], n = P.flat_off[c + 1] - off;
+        if (n <= 0) continue;
+        hipLaunchKernelGGL((k_edge_flat<T, Op>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                           P.e2n, P.flat_eid + off, (int)n, typed<T>(a), (T)gamma);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+    }
+    return 0;
+}
+
+template <typename T, class Op>
 constexpr size_t owner_dyn_lds(int K)
 {
     return stage_bytes<T, Op>(K) + (size_t)Op::NOUT * owner_acc_rows(K) * sizeof(double);
@@ -783,6 +837,7 @@ int run_edge(int variant, const DevPlan &P, const EdgeArrays &a, double gamma, h
     case V_COLOURED_LDS_ATOMIC: return run_coloured_bs<T, Op, true>(P, a, gamma, st, lo);
     case V_ATOMIC: return run_atomic<T, Op>(P, a, gamma, st, lo);
     case V_OWNER: return run_owner<T, Op>(P, a, gamma, st, lo);
+    case V_FLAT: return run_flat<T, Op>(P, a, gamma, st);
     default: return (int)hipErrorInvalidValue;
     }
 }
@@ -837,7 +892,7 @@ size_t owner_lds_bytes(int op, bool fp32, int K)
 
 size_t edge_lds_bytes(int op, bool fp32, int variant, int umax, int K)
 {
-    if (variant == V_ATOMIC) return 0;
+    if (variant == V_ATOMIC || variant == V_FLAT) return 0;
     if (variant == V_OWNER) return owner_lds_bytes(op, fp32, K);
     const int rows = umax;
     if (op == OP_ADJOINT) return lds_bytes<double, OpAdjoint>(rows);

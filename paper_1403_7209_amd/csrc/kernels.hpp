@@ -12,7 +12,7 @@ namespace gpu {
 enum EdgeOpKind { OP_FLUX = 0, OP_ADJOINT = 1, OP_SPECRAD = 2 };
 
 // Execution variants of an edge loop (values match opf_variant).
-enum Variant { V_COLOURED = 0, V_ATOMIC = 1, V_OWNER = 2, V_COLOURED_LDS_ATOMIC = 3 };
+enum Variant { V_COLOURED = 0, V_ATOMIC = 1, V_OWNER = 2, V_COLOURED_LDS_ATOMIC = 3, V_FLAT = 4 };
 
 constexpr int kOwnerThreads = 512;
 
@@ -35,6 +35,10 @@ struct DevPlan {
     const int2 *prim = nullptr;    // [ncl]
     const int *sec_off = nullptr;  // [ncl+1]
     const int *sec_eid = nullptr;  // [sec_off[ncl]]
+    // flat colouring: colour c runs edges flat_eid[flat_off[c] .. flat_off[c+1])
+    int nflat = 0;
+    std::vector<int64_t> flat_off;  // host copy [nflat+1]
+    const int *flat_eid = nullptr;  // [E]
 };
 
 // Component pointers of the arrays an edge loop touches (SoA: one pointer per

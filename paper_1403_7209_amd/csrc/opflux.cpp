@@ -170,6 +170,11 @@ int upload_plan(opf_ctx *ctx, PlanRec &pr)
         if (!rc) rc = upload(ctx, pr, sec_off, D.sec_off);
         if (!rc) rc = upload(ctx, pr, P.cl_sec_eid, D.sec_eid);
     }
+    if (P.flat_ok) {
+        D.nflat = P.flat_colours;
+        D.flat_off.assign(P.flat_off.begin(), P.flat_off.end());
+        if (!rc) rc = upload(ctx, pr, P.flat_eid, D.flat_eid);
+    }
     if (!rc) rc = upload(ctx, pr, e2n, D.e2n);
     if (!rc) rc = upload(ctx, pr, block_off, D.block_off);
     if (!rc) rc = upload(ctx, pr, uniq_off, D.uniq_off);
@@ -250,7 +255,7 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
     if (nargs != want_args || !args)
         return ctx->fail(OPF_EINVAL, "expected " + std::to_string(want_args) + " arguments");
     if (ngbl != 1 || !gbls) return ctx->fail(OPF_EINVAL, "expected one global (gamma)");
-    if (variant < OPF_V_COLOURED || variant > OPF_V_COLOURED_LDS_ATOMIC)
+    if (variant < OPF_V_COLOURED || variant > OPF_V_FLAT)
         return ctx->fail(OPF_EINVAL, "unknown variant");
     const opf_map m = args[0].map;
     if (!ctx->map_ok(m)) return ctx->fail(OPF_EINVAL, "argument 0: invalid map");
@@ -314,9 +319,10 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
                                                    : opf::gpu::OP_SPECRAD;
     const bool fp32 = T == OPF_F32;
     if (variant == OPF_V_OWNER && !pr.dev.owner_ok)
-        return ctx->fail(OPF_EINVAL, "the plan has no owner clusters (cluster_size 0, or a "
-                                     "cluster touching more than 256 edge segments)");
-    if (variant != OPF_V_ATOMIC) {
+        return ctx->fail(OPF_EINVAL, "the plan has no owner clusters (cluster_size 0)");
+    if (variant == OPF_V_FLAT && pr.dev.nflat <= 0)
+        return ctx->fail(OPF_EINVAL, "the map needs more than 128 flat colours");
+    if (variant != OPF_V_ATOMIC && variant != OPF_V_FLAT) {
         const size_t lds = opf::gpu::edge_lds_bytes(op, fp32, variant, pr.dev.umax, pr.dev.K);
         if (lds > ctx->max_lds)
             return ctx->fail(OPF_EINVAL, "a workgroup needs " + std::to_string(lds) +
@@ -584,6 +590,8 @@ int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info
         info->owner_edge_visits = P.owner_edge_visits;
         info->max_cluster_segments = P.max_cluster_segments;
         info->owner_ok = P.owner_ok ? 1 : 0;
+        info->flat_colours = P.flat_colours;
+        info->flat_ok = P.flat_ok ? 1 : 0;
     }
     ctx->plans[map] = std::move(pr);
     return OPF_OK;
@@ -634,6 +642,9 @@ int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out)
     out->cluster_range = P.cl_prim.data();
     out->cluster_list_offsets = P.cl_sec_off.data();
     out->cluster_list_edges = P.cl_sec_eid.data();
+    out->nflat_colours = P.flat_ok ? P.flat_colours : 0;
+    out->flat_offsets = P.flat_ok ? P.flat_off.data() : nullptr;
+    out->flat_edges = P.flat_ok ? P.flat_eid.data() : nullptr;
     return OPF_OK;
 }
 

@@ -476,6 +476,41 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
         }
         P.owner_ok = true;
     }
+
+    // flat colouring: one level over the whole edge set, each edge in edge order
+    // takes the lowest colour free at both of its ends (at most 128 colours)
+    {
+        std::vector<uint64_t> used(2 * (size_t)N, 0);
+        std::vector<uint8_t> col(E);
+        int ncol = 0;
+        P.flat_ok = true;
+        for (int64_t e = 0; e < E && P.flat_ok; ++e) {
+            const int64_t a = P.e2n[2 * e], b = P.e2n[2 * e + 1];
+            int c = lowest_free(used[2 * a] | used[2 * b]);
+            if (c < 0) {
+                const int c1 = lowest_free(used[2 * a + 1] | used[2 * b + 1]);
+                c = c1 < 0 ? -1 : 64 + c1;
+            }
+            if (c < 0) {
+                P.flat_ok = false;
+                break;
+            }
+            const uint64_t bit = 1ULL << (c & 63);
+            used[2 * a + (c >> 6)] |= bit;
+            used[2 * b + (c >> 6)] |= bit;
+            col[e] = (uint8_t)c;
+            ncol = std::max(ncol, c + 1);
+        }
+        if (P.flat_ok) {
+            P.flat_colours = ncol;
+            P.flat_off.assign(ncol + 1, 0);
+            for (int64_t e = 0; e < E; ++e) ++P.flat_off[col[e] + 1];
+            for (int c = 0; c < ncol; ++c) P.flat_off[c + 1] += P.flat_off[c];
+            std::vector<int64_t> fill(P.flat_off.begin(), P.flat_off.end() - 1);
+            P.flat_eid.resize(E);
+            for (int64_t e = 0; e < E; ++e) P.flat_eid[fill[col[e]]++] = (int32_t)e;
+        }
+    }
     lap(2);
 
     // (4) colour the partitions greedily: lowest colour unused by any partition
@@ -696,6 +731,27 @@ VerifyResult verify_plan(const Plan &P, const int32_t *e2n_user)
         for (int64_t k = 0; k < E; ++k) {
             const int want = (P.e2n[2 * k] / K == P.e2n[2 * k + 1] / K) ? 1 : 2;
             if (seen[k] != want) return fail(8, k, "edge missing from its clusters' visit lists");
+        }
+    }
+    // (9) flat colouring: every edge in exactly one colour; edges of one colour
+    // share no node
+    if (P.flat_ok) {
+        const int nc = P.flat_colours;
+        if (nc < 1 || nc > 128 || (int64_t)P.flat_off.size() != nc + 1 || P.flat_off[0] != 0 ||
+            P.flat_off[nc] != E || (int64_t)P.flat_eid.size() != E)
+            return fail(9, -1, "flat colour offsets are inconsistent");
+        std::vector<uint8_t> seen(E, 0);
+        std::vector<int32_t> stamp(N, -1);
+        for (int c = 0; c < nc; ++c) {
+            if (P.flat_off[c + 1] <= P.flat_off[c]) return fail(9, c, "empty flat colour");
+            for (int64_t s = P.flat_off[c]; s < P.flat_off[c + 1]; ++s) {
+                const int64_t k = P.flat_eid[s];
+                if (k < 0 || k >= E || seen[k]) return fail(9, k, "edge listed twice or out of range");
+                seen[k] = 1;
+                const int32_t a = P.e2n[2 * k], b = P.e2n[2 * k + 1];
+                if (stamp[a] == c || stamp[b] == c) return fail(9, k, "two edges of one flat colour share a node");
+                stamp[a] = stamp[b] = c;
+            }
         }
     }
     return r;

@@ -66,6 +66,12 @@ struct Plan {
     std::vector<int32_t> cl_prim;     // [2 ncl]
     std::vector<int64_t> cl_sec_off;  // [ncl+1]
     std::vector<int32_t> cl_sec_eid;
+    // Flat colouring (one level over all edges; no partitions): edges
+    // flat_eid[flat_off[c] .. flat_off[c+1]) have colour c and share no node.
+    bool flat_ok = false;  // false when more than 128 colours would be needed
+    int32_t flat_colours = 0;
+    std::vector<int64_t> flat_off;
+    std::vector<int32_t> flat_eid;
     int64_t nclusters() const { return cluster_size ? (N + cluster_size - 1) / cluster_size : 0; }
     int64_t nblocks() const { return (int64_t)block_colour.size(); }
 };
@@ -82,7 +88,7 @@ struct VerifyResult {
     std::string message;
 };
 
-// Bit-exact check of the plan's properties (1..8) against the user map.
+// Bit-exact check of the plan's properties (1..9) against the user map.
 VerifyResult verify_plan(const Plan &plan, const int32_t *e2n_user);
 
 }  // namespace opf

@@ -21,7 +21,7 @@ DEV = "cuda:0"
 TOL64, TOL32 = 1e-12, 1e-5
 
 
-ALL_VARIANTS = (pk.COLOURED, pk.ATOMIC, pk.OWNER, pk.COLOURED_LDS_ATOMIC)
+ALL_VARIANTS = (pk.COLOURED, pk.ATOMIC, pk.OWNER, pk.COLOURED_LDS_ATOMIC, pk.FLAT)
 
 
 def problem(m, q, fp32=False, renumber="rcm", block_size=512, colour_sort=False,
@@ -34,7 +34,8 @@ def problem(m, q, fp32=False, renumber="rcm", block_size=512, colour_sort=False,
 
 
 def variants(p):
-    return [v for v in ALL_VARIANTS if v != pk.OWNER or p.info["owner_ok"]]
+    return [v for v in ALL_VARIANTS
+            if (v != pk.OWNER or p.info["owner_ok"]) and (v != pk.FLAT or p.info["flat_ok"])]
 
 
 def gpu_residual(p, variant):
@@ -44,7 +45,8 @@ def gpu_residual(p, variant):
     return p.nodes_out(res)
 
 
-@pytest.mark.parametrize("variant", ALL_VARIANTS, ids=["coloured", "atomic", "owner", "ldsatomic"])
+@pytest.mark.parametrize("variant", ALL_VARIANTS,
+                         ids=["coloured", "atomic", "owner", "ldsatomic", "flat"])
 @pytest.mark.parametrize("case", flux_hand_cases(), ids=lambda c: c[0])
 def test_two_node_hand_cases(case, variant):
     name, qi, qj, n, F = case

@@ -76,6 +76,19 @@ def check_plan_properties(m, ctx, nodes, edges, mp):
     k4 = (np.concatenate([blk_of_edge, blk_of_edge]) * 256 + np.concatenate([ecol, ecol])) * m.N + both
     assert len(np.unique(k4)) == len(k4)
     assert np.all(ecol < v["block_ncolours"][blk_of_edge])
+    # 9: flat colouring: one colour per edge, no node twice in a colour
+    nf = v["nflat_colours"]
+    assert nf > 0
+    fo, fe = v["flat_offsets"], v["flat_edges"]
+    assert fo[0] == 0 and fo[-1] == m.E and np.all(np.diff(fo) > 0)
+    assert np.array_equal(np.sort(fe), np.arange(m.E))
+    fcol = np.repeat(np.arange(nf, dtype=np.int64), np.diff(fo))
+    ends = e2n[fe].astype(np.int64)
+    k9 = np.concatenate([fcol * m.N + ends[:, 0], fcol * m.N + ends[:, 1]])
+    assert len(np.unique(k9)) == len(k9)
+    # greedy colouring needs at most 2 * (max degree) - 1 colours
+    deg = np.bincount(e2n.ravel(), minlength=m.N)
+    assert nf <= 2 * deg.max() - 1
     # 8: every edge is run by exactly the owner clusters of its endpoints
     K = v["cluster_size"]
     if K:
