@@ -32,6 +32,9 @@ def _load():
         lib.orc_rk_iteration.argtypes = [i64, i64, vp, vp, vp, vp, d, d, vp]
         lib.orc_spectral_radius.argtypes = [i64, i64, vp, vp, vp, d, vp]
         lib.orc_dt.argtypes = [i64, i64, vp, vp, vp, vp, d, d]
+        lib.orc_local_dt.argtypes = [i64, i64, vp, vp, vp, vp, d, d, vp]
+        lib.orc_rk_stage_local.argtypes = [i64, vp, vp, vp, vp, d, vp, vp]
+        lib.orc_rk_iteration_local.argtypes = [i64, i64, vp, vp, vp, vp, d, vp, vp]
         lib.orc_dt.restype = d
         lib.orc_jvp.argtypes = [i64, i64, vp, vp, vp, d, vp, vp, vp]
         lib.orc_edge_jacobian.argtypes = [vp, vp, vp, d, vp, vp]
@@ -115,6 +118,37 @@ def dt(e2n, q, w, vol, gamma=1.4, cfl=0.5):
     if r < 0:
         raise RuntimeError("orc_dt failed")
     return r
+
+
+def local_dt(e2n, q, w, vol, gamma=1.4, cfl=0.5):
+    """Per-node time step cfl * vol_i / sum of lambda_e at i."""
+    e2n, q, w, vol = _c(e2n, np.int32), _c(q), _c(w), _c(vol)
+    out = np.empty(q.shape[1])
+    _check(_load().orc_local_dt(q.shape[1], w.shape[1], _p(e2n), _p(q), _p(w), _p(vol), gamma,
+                                cfl, _p(out)), "orc_local_dt")
+    return out
+
+
+def rk_stage_local(q0, res, vol, dt, alpha):
+    """Returns (q, ss[6]) with a time step per node; res is zeroed in place."""
+    q0, vol, dt = _c(q0), _c(vol), _c(dt)
+    assert res.flags.c_contiguous and res.dtype == np.float64
+    q = np.empty_like(q0)
+    ss = np.empty(6)
+    _check(_load().orc_rk_stage_local(q0.shape[1], _p(q0), _p(res), _p(vol), _p(dt), alpha, _p(q),
+                                      _p(ss)), "orc_rk_stage_local")
+    return q, ss
+
+
+def rk_iteration_local(e2n, q0, w, vol, dt, gamma=1.4):
+    """One 5-stage iteration with per-node time steps dt; returns (q, ss (5, 6))."""
+    e2n = _c(e2n, np.int32)
+    q = _c(q0).copy()
+    w, vol, dt = _c(w), _c(vol), _c(dt)
+    ss = np.empty(30)
+    _check(_load().orc_rk_iteration_local(q.shape[1], w.shape[1], _p(e2n), _p(q), _p(w), _p(vol),
+                                          gamma, _p(dt), _p(ss)), "orc_rk_iteration_local")
+    return q, ss.reshape(5, 6)
 
 
 def jvp(e2n, q, w, dq=None, dw=None, gamma=1.4):

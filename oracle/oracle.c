@@ -169,6 +169,48 @@ int orc_rk_stage(int64_t N, const double *q0, double *res, const double *vol, do
     return 0;
 }
 
+/* Local time stepping: each node advances with its own stable step, the
+ * global step of Sec. 2's explicit scheme taken node by node; the stage
+ * coefficients stay those of the 5-stage scheme. */
+int orc_rk_stage_local(int64_t N, const double *q0, double *res, const double *vol,
+                       const double *dt, double alpha, double *q, double ss[6])
+{
+    if (N <= 0) return ORC_EINVAL;
+    for (int v = 0; v < 6; ++v) {
+        ksum k = {0.0, 0.0};
+        for (int64_t i = 0; i < N; ++i) {
+            double r = res[(int64_t)v * N + i];
+            ksum_add(&k, r * r);
+            q[(int64_t)v * N + i] = q0[(int64_t)v * N + i] - alpha * dt[i] * r / vol[i];
+            res[(int64_t)v * N + i] = 0.0;
+        }
+        ss[v] = k.s + k.c;
+    }
+    return 0;
+}
+
+int orc_rk_iteration_local(int64_t N, int64_t E, const int32_t *e2n, double *q0, const double *w,
+                           const double *vol, double gamma, const double *dt, double ss[30])
+{
+    double *res = calloc((size_t)N * 6, sizeof(double));
+    double *q = malloc((size_t)N * 6 * sizeof(double));
+    if (!res || !q) {
+        free(res);
+        free(q);
+        return ORC_ENOMEM;
+    }
+    memcpy(q, q0, (size_t)N * 6 * sizeof(double));
+    int rc = 0;
+    for (int k = 0; k < 5 && !rc; ++k) {
+        rc = orc_residual(N, E, e2n, q, w, gamma, res, NULL);
+        if (!rc) rc = orc_rk_stage_local(N, q0, res, vol, dt, RK_ALPHA[k], q, ss + 6 * k);
+    }
+    if (!rc) memcpy(q0, q, (size_t)N * 6 * sizeof(double));
+    free(res);
+    free(q);
+    return rc;
+}
+
 int orc_rk_iteration(int64_t N, int64_t E, const int32_t *e2n, double *q0, const double *w,
                      const double *vol, double gamma, double dt, double ss[30])
 {
@@ -213,6 +255,18 @@ int orc_spectral_radius(int64_t N, int64_t E, const int32_t *e2n, const double *
         lam_sum[j] += lam;
     }
     return 0;
+}
+
+int orc_local_dt(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+                 const double *vol, double gamma, double cfl, double *dt)
+{
+    double *ls = calloc((size_t)N, sizeof(double));
+    if (!ls) return ORC_ENOMEM;
+    int rc = orc_spectral_radius(N, E, e2n, q, w, gamma, ls);
+    if (!rc)
+        for (int64_t i = 0; i < N; ++i) dt[i] = cfl * vol[i] / ls[i];
+    free(ls);
+    return rc;
 }
 
 double orc_dt(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,

@@ -39,6 +39,18 @@ int orc_rk_iteration(int64_t N, int64_t E, const int32_t *e2n, double *q0, const
 int orc_spectral_radius(int64_t N, int64_t E, const int32_t *e2n, const double *q,
                         const double *w, double gamma, double *lam_sum);
 
+/* dt[N] = cfl * vol_i / sum_{e at i} lambda_e: the local time step of each node. */
+int orc_local_dt(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+                 const double *vol, double gamma, double cfl, double *dt);
+
+/* As orc_rk_stage with a time step per node: q = q0 - alpha*dt_i*res/vol. */
+int orc_rk_stage_local(int64_t N, const double *q0, double *res, const double *vol,
+                       const double *dt, double alpha, double *q, double ss[6]);
+
+/* One 5-stage iteration in place on q0 with the local time steps dt[N]. */
+int orc_rk_iteration_local(int64_t N, int64_t E, const int32_t *e2n, double *q0, const double *w,
+                           const double *vol, double gamma, const double *dt, double ss[30]);
+
 /* cfl * min_i vol_i / sum_{e at i} lambda_e; negative on error. */
 double orc_dt(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
               const double *vol, double gamma, double cfl);

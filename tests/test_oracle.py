@@ -236,6 +236,63 @@ def test_dt_closed_form_at_rest(mesh_j):
     np.testing.assert_allclose(ls, [2.5, 2.5], rtol=1e-15)
 
 
+def test_local_dt_closed_form_at_rest(mesh_j):
+    """At rest lambda_e = c |n_e|, so each node's step is cfl vol_i / (c sum |n_e|);
+    the global step is their minimum."""
+    m = mesh_j
+    rho, p = 0.8, 1.3
+    q = np.repeat(cons(rho, [0, 0, 0], p, -0.2)[:, None], m.N, axis=1)
+    c = math.sqrt(GAMMA * p / rho)
+    nn = np.linalg.norm(m.w, axis=0)
+    ssum = np.zeros(m.N)
+    np.add.at(ssum, m.e2n[:, 0], nn)
+    np.add.at(ssum, m.e2n[:, 1], nn)
+    dtl = oracle.local_dt(m.e2n, q, m.w, m.vol, cfl=0.7)
+    np.testing.assert_allclose(dtl, 0.7 * m.vol / (c * ssum), rtol=1e-13)
+    assert dtl.min() == pytest.approx(oracle.dt(m.e2n, q, m.w, m.vol, cfl=0.7), rel=1e-15)
+
+
+def test_local_stage_reduces_to_global_stage():
+    rng = np.random.default_rng(6)
+    N = 3000
+    q0 = rng.normal(size=(6, N))
+    res = rng.normal(size=(6, N))
+    vol = rng.uniform(0.5, 2.0, N)
+    r1, r2 = res.copy(), res.copy()
+    qg, ssg = oracle.rk_stage(q0, r1, vol, 0.375 * 0.02)
+    ql, ssl = oracle.rk_stage_local(q0, r2, vol, np.full(N, 0.02), 0.375)
+    assert np.array_equal(qg, ql) and np.array_equal(ssg, ssl) and np.all(r2 == 0.0)
+
+
+def test_local_time_stepping_amplification_polynomial():
+    """With a step per node the scalar component of the linear problem of
+    test_rk_amplification_polynomial advances by P(D M) with D = diag(dt_i /
+    vol_i): the same polynomial, now of a non-symmetric matrix, so any slip in
+    which node's step scales which residual shows."""
+    m = meshgen.build_mesh(4, 0, 0.0)
+    base = cons(1.0, [0.3, 0.1, -0.2], 1.0, 0.0)
+    rng = np.random.default_rng(12)
+    q = np.repeat(base[:, None], m.N, axis=1)
+    q[5] = rng.uniform(0, 1, m.N)
+    M = np.zeros((m.N, m.N))
+    for k in range(m.N):
+        qk = np.repeat(base[:, None], m.N, axis=1)
+        qk[5, k] = 1.0
+        M[:, k] = oracle.residual(m.e2n, qk, m.w)[5]
+    dt0 = oracle.dt(m.e2n, q, m.w, m.vol)
+    dtl = dt0 * rng.uniform(0.3, 1.0, m.N)
+    X = (dtl / m.vol)[:, None] * M
+    c = [1.0, 1.0, 1.0 / 2.0, 3.0 / 16.0, 1.0 / 32.0, 1.0 / 128.0]
+    Pq = np.zeros(m.N)
+    Xp = q[5].copy()
+    for j in range(6):
+        Pq += (-1) ** j * c[j] * Xp
+        Xp = X @ Xp
+    qn, _ = oracle.rk_iteration_local(m.e2n, q, m.w, m.vol, dtl)
+    assert np.abs(qn[5] - Pq).max() <= 1e-14
+    assert np.abs(qn[:5] - base[:5, None]).max() <= 1e-15
+
+
 def test_edge_jacobian_vs_central_differences():
     rng = np.random.default_rng(9)
     for _ in range(30):
