@@ -71,7 +71,8 @@ typedef enum {
     OPF_K_EDGE_FLUX_ADJ = 1, /* reverse (adjoint) of the edge flux                */
     OPF_K_RK_STAGE = 2,      /* direct explicit stage update + sum-of-squares     */
     OPF_K_EDGE_SPECRAD = 3,  /* OP_INC of the edge spectral radius into nodes     */
-    OPF_K_DT_MIN = 4         /* direct: global min over nodes of cfl*vol/lambda   */
+    OPF_K_DT_MIN = 4,        /* direct: global min over nodes of cfl*vol/lambda   */
+    OPF_K_LOCAL_DT = 5       /* direct: per-node step cfl*vol/lambda              */
 } opf_kernel;
 
 /* How an indirect (edge) loop resolves its increments. */
@@ -304,7 +305,13 @@ typedef struct {
  *   sum_i res_i^2 per component to ss, and zeroes res.  With res READ instead
  *   of RW, res is left untouched (for a following edge loop that WRITEs it).
  *   The sum is deterministic: fixed partition, fixed order.  q must not alias
- *   q0 or res.
+ *   q0 or res.  Local time stepping: a fifth argument (dt,-1,ID,1,F64,READ)
+ *   gives each node its own step; the first global is then the stage
+ *   coefficient alpha and q = q0 - alpha * dt_i * res / vol.
+ *  LOCAL_DT over nodes (direct): (vol,-1,ID,1,F64,READ) (lam,-1,ID,1,F64,READ)
+ *     (dt,-1,ID,1,F64,WRITE) gbl (cfl, 1, F64, READ, host)
+ *   dt_i = cfl * vol_i / lam_i with lam the EDGE_SPECRAD sum; dt must not
+ *   alias vol or lam.
  *  DT_MIN over nodes (direct): (vol,-1,ID,1,F64,READ) (lam,-1,ID,1,F64,READ)
  *     gbl (cfl, 1, F64, READ, host) gbl (dt, 1, F64, MIN, device)
  *   dt = min(dt, cfl * min_i vol_i / lam_i).
@@ -327,6 +334,11 @@ int opf_edge_specrad(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_da
                      opf_dat lam, double gamma, int variant, void *stream);
 int opf_rk_stage(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol, opf_dat q,
                  double alpha_dt, double *ss_dev, int res_access, void *stream);
+int opf_rk_stage_local(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol,
+                       opf_dat dt, opf_dat q, double alpha, double *ss_dev, int res_access,
+                       void *stream);
+int opf_local_dt(opf_ctx *ctx, opf_set nodes, opf_dat vol, opf_dat lam, double cfl, opf_dat dt,
+                 void *stream);
 int opf_dt_min(opf_ctx *ctx, opf_set nodes, opf_dat vol, opf_dat lam, double cfl,
                double *dt_dev, void *stream);
 

@@ -45,7 +45,8 @@ RK_ALPHA = (1.0 / 4.0, 1.0 / 6.0, 3.0 / 8.0, 1.0 / 2.0, 1.0)
 SYMBOLS = ("opf_init", "opf_finalize", "opf_last_error", "opf_set_allocator", "opf_decl_set",
            "opf_decl_map", "opf_plan", "opf_get_perm", "opf_plan_view_get", "opf_plan_verify",
            "opf_decl_dat", "opf_par_loop", "opf_edge_flux", "opf_edge_flux_adjoint",
-           "opf_edge_specrad", "opf_rk_stage", "opf_dt_min", "opf_sync", "opf_check_finite")
+           "opf_edge_specrad", "opf_rk_stage", "opf_rk_stage_local", "opf_local_dt", "opf_dt_min",
+           "opf_sync", "opf_check_finite")
 
 
 class OpfError(RuntimeError):
@@ -144,6 +145,8 @@ def load():
     lib.opf_edge_specrad.argtypes = [vp, i32, i32, i32, i32, i32, d, ctypes.c_int, vp]
     lib.opf_rk_stage.argtypes = [vp, i32, i32, i32, i32, i32, d, vp, ctypes.c_int, vp]
     lib.opf_dt_min.argtypes = [vp, i32, i32, i32, d, vp, vp]
+    lib.opf_rk_stage_local.argtypes = [vp, i32, i32, i32, i32, i32, i32, d, vp, ctypes.c_int, vp]
+    lib.opf_local_dt.argtypes = [vp, i32, i32, i32, d, i32, vp]
     lib.opf_sync.argtypes = [vp, vp]
     lib.opf_check_finite.argtypes = [vp, vp, ctypes.c_int, vp]
     runtimes = _hip_runtimes()
@@ -343,6 +346,18 @@ class Context:
                                           ctypes.c_void_p(ss.data_ptr()), res_access,
                                           _stream_ptr(stream, self.device)), "opf_rk_stage")
 
+    def rk_stage_local(self, nodes, q0, res, vol, dt, q, alpha, ss, res_access=RW, stream=None):
+        """As rk_stage with a time step per node (dat dt): q = q0 - alpha dt_i res / vol."""
+        self._check(self.lib.opf_rk_stage_local(self._ctx, nodes, q0, res, vol, dt, q, float(alpha),
+                                                ctypes.c_void_p(ss.data_ptr()), res_access,
+                                                _stream_ptr(stream, self.device)),
+                    "opf_rk_stage_local")
+
+    def local_dt(self, nodes, vol, lam, cfl, dt, stream=None):
+        """dt_i = cfl vol_i / lam_i (dats on the node set)."""
+        self._check(self.lib.opf_local_dt(self._ctx, nodes, vol, lam, float(cfl), dt,
+                                          _stream_ptr(stream, self.device)), "opf_local_dt")
+
     def dt_min(self, nodes, vol, lam, cfl, dt, stream=None):
         self._check(self.lib.opf_dt_min(self._ctx, nodes, vol, lam, float(cfl),
                                         ctypes.c_void_p(dt.data_ptr()),
@@ -449,6 +464,32 @@ class FluxProblem:
                                ra, stream)
             self.ctx.rk_stage(self.nodes, qa, self.res_d, self.vol, qb, RK_ALPHA[k] * dt,
                               self.ss[k], rk, stream)
+        self.qa, self.qb = self.qb, self.qa
+
+    def compute_local_dt(self, cfl=0.5, variant=COLOURED, stream=None):
+        """Per-node time steps cfl * vol_i / sum_e lambda_e of the current state,
+        left in self.dtl (internal numbering)."""
+        if not hasattr(self, "dtl"):
+            self.dtl = torch.empty(self.N, dtype=torch.float64, device=self.qa.device)
+            self.dtl_d = self.ctx.decl_dat(self.nodes, self.dtl, "dt_local")
+        self.lam.zero_()
+        self.ctx.edge_specrad(self.edges, self.e2n, self.dat(self.qa, "q"), self.w, self.lam_d,
+                              self.gamma, variant, stream)
+        self.ctx.local_dt(self.nodes, self.vol, self.lam_d, cfl, self.dtl_d, stream)
+        return self.dtl
+
+    def rk_iteration_local(self, variant=COLOURED, stream=None):
+        """One 5-stage iteration with the per-node steps of the last
+        compute_local_dt; otherwise as rk_iteration."""
+        qa, qb = self.dat(self.qa, "qa"), self.dat(self.qb, "qb")
+        ra, rk = (WRITE, READ) if variant == OWNER else (INC, RW)
+        self.ss.zero_()
+        for k in range(5):
+            src = qa if k == 0 else qb
+            self.ctx.edge_flux(self.edges, self.e2n, src, self.w, self.res_d, self.gamma, variant,
+                               ra, stream)
+            self.ctx.rk_stage_local(self.nodes, qa, self.res_d, self.vol, self.dtl_d, qb,
+                                    RK_ALPHA[k], self.ss[k], rk, stream)
         self.qa, self.qb = self.qb, self.qa
 
     def rms(self):

@@ -672,6 +672,7 @@ struct RkPtrs {
     double *res[6];
     const double *vol;
     T *q[6];
+    const double *dt;  // per-node steps (local time stepping) or null
 };
 
 template <typename T>
@@ -682,15 +683,25 @@ __global__ __launch_bounds__(kRkThreads) void k_rk_stage(int N, RkPtrs<T> a, dou
     const int stride = (int)gridDim.x * kRkThreads;
     for (int i = (int)blockIdx.x * kRkThreads + (int)threadIdx.x; i < N; i += stride) {
         const double vi = a.vol[i];
+        const double adt = a.dt ? alpha_dt * a.dt[i] : alpha_dt;
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
             const double r = a.res[v][i];
             acc[v] += r * r;
-            a.q[v][i] = (T)((double)a.q0[v][i] - alpha_dt * r / vi);
+            a.q[v][i] = (T)((double)a.q0[v][i] - adt * r / vi);
             if (!keep_res) a.res[v][i] = 0.0;
         }
     }
     block_sum<6>(acc, partial + 6 * blockIdx.x);
+}
+
+__global__ __launch_bounds__(kRkThreads) void k_local_dt(int N, const double *__restrict__ vol,
+                                                         const double *__restrict__ lam, double cfl,
+                                                         double *__restrict__ dt)
+{
+    const int stride = (int)gridDim.x * kRkThreads;
+    for (int i = (int)blockIdx.x * kRkThreads + (int)threadIdx.x; i < N; i += stride)
+        dt[i] = cfl * vol[i] / lam[i];
 }
 
 __global__ __launch_bounds__(256) void k_sum_partials(int nparts, const double *partial,
@@ -939,6 +950,7 @@ static int run_rk(int N, const NodeArrays &a, double alpha_dt, double *ss, doubl
         p.q[v] = static_cast<T *>(a.q[v]);
     }
     p.vol = a.vol;
+    p.dt = a.dt;
     const int grid = std::min(kRkBlocks, std::max(1, (N + kRkThreads - 1) / kRkThreads));
     hipLaunchKernelGGL((k_rk_stage<T>), dim3(grid), dim3(kRkThreads), 0, st, N, p, alpha_dt,
                        partial, keep_res ? 1 : 0);
@@ -959,6 +971,14 @@ int launch_dt_min(int N, const double *vol, const double *lam, double cfl, doubl
     const int grid = std::min(kRkBlocks, std::max(1, (N + kRkThreads - 1) / kRkThreads));
     hipLaunchKernelGGL(k_dt_min, dim3(grid), dim3(kRkThreads), 0, st, N, vol, lam, partial);
     hipLaunchKernelGGL(k_min_partials, dim3(1), dim3(256), 0, st, grid, partial, cfl, dt);
+    return (int)hipGetLastError();
+}
+
+int launch_local_dt(int N, const double *vol, const double *lam, double cfl, double *dt,
+                    hipStream_t st)
+{
+    const int grid = std::min(kRkBlocks, std::max(1, (N + kRkThreads - 1) / kRkThreads));
+    hipLaunchKernelGGL(k_local_dt, dim3(grid), dim3(kRkThreads), 0, st, N, vol, lam, cfl, dt);
     return (int)hipGetLastError();
 }
 

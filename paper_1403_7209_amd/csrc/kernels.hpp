@@ -64,10 +64,12 @@ struct NodeArrays {
     double *res[6] = {};
     const double *vol = nullptr;
     void *q[6] = {};
+    const double *dt = nullptr;  // per-node time steps, or null for one global step
 };
 
-// q = q0 - alpha_dt * res / vol, ss[v] += sum res^2 (two passes, deterministic),
-// res = 0 unless keep_res.  `partial` holds kRkBlocks * 6 doubles.
+// q = q0 - alpha_dt * res / vol (alpha_dt * dt_i with per-node steps),
+// ss[v] += sum res^2 (two passes, deterministic), res = 0 unless keep_res.
+// `partial` holds kRkBlocks * 6 doubles.
 constexpr int kRkThreads = 256;
 constexpr int kRkBlocks = 2048;
 int launch_rk_stage(bool fp32, int N, const NodeArrays &a, double alpha_dt, double *ss,
@@ -76,6 +78,10 @@ int launch_rk_stage(bool fp32, int N, const NodeArrays &a, double alpha_dt, doub
 // dt = min(dt, cfl * min_i vol_i / lam_i); `partial` holds kRkBlocks doubles.
 int launch_dt_min(int N, const double *vol, const double *lam, double cfl, double *dt,
                   double *partial, hipStream_t stream);
+
+// dt[i] = cfl * vol[i] / lam[i].
+int launch_local_dt(int N, const double *vol, const double *lam, double cfl, double *dt,
+                    hipStream_t stream);
 
 // LDS bytes (dynamic and static) of one workgroup of an edge loop.
 size_t edge_lds_bytes(int op, bool fp32, int variant, int umax, int K);

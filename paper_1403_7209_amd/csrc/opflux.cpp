@@ -361,16 +361,18 @@ int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *a
 {
     int rc = OPF_OK;
     if (kernel == OPF_K_RK_STAGE) {
-        if (nargs != 4 || !args) return ctx->fail(OPF_EINVAL, "expected 4 arguments");
+        if ((nargs != 4 && nargs != 5) || !args)
+            return ctx->fail(OPF_EINVAL, "expected 4 arguments (5 with local time steps)");
         if (ngbl != 2 || !gbls) return ctx->fail(OPF_EINVAL, "expected 2 globals");
         if (!ctx->dat_ok(args[0].dat)) return ctx->fail(OPF_EINVAL, "argument 0: invalid dat");
         const int T = ctx->dats[args[0].dat].type;
         const bool keep_res = args[1].access == OPF_READ;
-        const Want w[4] = {{s, -1, OPF_ID, 6, T, OPF_READ},
+        const Want w[5] = {{s, -1, OPF_ID, 6, T, OPF_READ},
                            {s, -1, OPF_ID, 6, OPF_F64, keep_res ? OPF_READ : OPF_RW},
                            {s, -1, OPF_ID, 1, OPF_F64, OPF_READ},
-                           {s, -1, OPF_ID, 6, T, OPF_WRITE}};
-        for (int k = 0; k < 4 && !rc; ++k) rc = check_arg(ctx, args[k], w[k], k);
+                           {s, -1, OPF_ID, 6, T, OPF_WRITE},
+                           {s, -1, OPF_ID, 1, OPF_F64, OPF_READ}};
+        for (int k = 0; k < nargs && !rc; ++k) rc = check_arg(ctx, args[k], w[k], k);
         if (!rc) rc = check_gbl(ctx, gbls[0], 1, OPF_READ, 0, 0);
         if (!rc) rc = check_gbl(ctx, gbls[1], 6, OPF_INC, 1, 1);
         if (rc) return rc;
@@ -387,11 +389,33 @@ int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *a
             na.q[c] = (void *)comp(q, c);
         }
         na.vol = static_cast<const double *>(vol.ptr);
+        if (nargs == 5) na.dt = static_cast<const double *>(ctx->dats[args[4].dat].ptr);
         const double adt = *static_cast<const double *>(gbls[0].ptr);
         int e = opf::gpu::launch_rk_stage(T == OPF_F32, (int)ctx->sets[s].size, na, adt,
                                           static_cast<double *>(gbls[1].ptr), ctx->scratch,
                                           keep_res, st);
         if (e) return hip_fail(ctx, (hipError_t)e, "RK stage launch");
+        return OPF_OK;
+    }
+    if (kernel == OPF_K_LOCAL_DT) {
+        if (nargs != 3 || !args) return ctx->fail(OPF_EINVAL, "expected 3 arguments");
+        if (ngbl != 1 || !gbls) return ctx->fail(OPF_EINVAL, "expected 1 global");
+        const Want w[3] = {{s, -1, OPF_ID, 1, OPF_F64, OPF_READ},
+                           {s, -1, OPF_ID, 1, OPF_F64, OPF_READ},
+                           {s, -1, OPF_ID, 1, OPF_F64, OPF_WRITE}};
+        for (int k = 0; k < 3 && !rc; ++k) rc = check_arg(ctx, args[k], w[k], k);
+        if (!rc) rc = check_gbl(ctx, gbls[0], 1, OPF_READ, 0, 0);
+        if (rc) return rc;
+        if (args[2].dat == args[0].dat || args[2].dat == args[1].dat)
+            return ctx->fail(OPF_EINVAL, "dt must not alias vol or lam");
+        rc = device_ready(ctx);
+        if (rc) return rc;
+        const double cfl = *static_cast<const double *>(gbls[0].ptr);
+        int e = opf::gpu::launch_local_dt((int)ctx->sets[s].size,
+                                          static_cast<const double *>(ctx->dats[args[0].dat].ptr),
+                                          static_cast<const double *>(ctx->dats[args[1].dat].ptr),
+                                          cfl, static_cast<double *>(ctx->dats[args[2].dat].ptr), st);
+        if (e) return hip_fail(ctx, (hipError_t)e, "local time-step launch");
         return OPF_OK;
     }
     // DT_MIN
@@ -696,7 +720,8 @@ int opf_par_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *
     case OPF_K_EDGE_FLUX_ADJ:
     case OPF_K_EDGE_SPECRAD: return edge_loop(ctx, kernel, s, nargs, args, ngbl, gbls, variant, st);
     case OPF_K_RK_STAGE:
-    case OPF_K_DT_MIN: return direct_loop(ctx, kernel, s, nargs, args, ngbl, gbls, st);
+    case OPF_K_DT_MIN:
+    case OPF_K_LOCAL_DT: return direct_loop(ctx, kernel, s, nargs, args, ngbl, gbls, st);
     default: return ctx->fail(OPF_EINVAL, "unknown kernel");
     }
 }
@@ -759,6 +784,33 @@ int opf_rk_stage(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat v
                           {q, -1, OPF_ID, 6, T, OPF_WRITE}};
     const opf_gbl g[2] = {{&alpha_dt, 1, OPF_F64, OPF_READ, 0}, {ss_dev, 6, OPF_F64, OPF_INC, 1}};
     return opf_par_loop(ctx, OPF_K_RK_STAGE, nodes, 4, a, 2, g, OPF_V_COLOURED, stream);
+}
+
+int opf_rk_stage_local(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol,
+                       opf_dat dt, opf_dat q, double alpha, double *ss_dev, int res_access,
+                       void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    if (!ctx->dat_ok(q0)) return ctx->fail(OPF_EINVAL, "invalid dat handle");
+    const int T = ctx->dats[q0].type;
+    const opf_arg a[5] = {{q0, -1, OPF_ID, 6, T, OPF_READ},
+                          {res, -1, OPF_ID, 6, OPF_F64, res_access},
+                          {vol, -1, OPF_ID, 1, OPF_F64, OPF_READ},
+                          {q, -1, OPF_ID, 6, T, OPF_WRITE},
+                          {dt, -1, OPF_ID, 1, OPF_F64, OPF_READ}};
+    const opf_gbl g[2] = {{&alpha, 1, OPF_F64, OPF_READ, 0}, {ss_dev, 6, OPF_F64, OPF_INC, 1}};
+    return opf_par_loop(ctx, OPF_K_RK_STAGE, nodes, 5, a, 2, g, OPF_V_COLOURED, stream);
+}
+
+int opf_local_dt(opf_ctx *ctx, opf_set nodes, opf_dat vol, opf_dat lam, double cfl, opf_dat dt,
+                 void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    const opf_arg a[3] = {{vol, -1, OPF_ID, 1, OPF_F64, OPF_READ},
+                          {lam, -1, OPF_ID, 1, OPF_F64, OPF_READ},
+                          {dt, -1, OPF_ID, 1, OPF_F64, OPF_WRITE}};
+    const opf_gbl g[1] = {{&cfl, 1, OPF_F64, OPF_READ, 0}};
+    return opf_par_loop(ctx, OPF_K_LOCAL_DT, nodes, 3, a, 1, g, OPF_V_COLOURED, stream);
 }
 
 int opf_dt_min(opf_ctx *ctx, opf_set nodes, opf_dat vol, opf_dat lam, double cfl, double *dt_dev,

@@ -49,7 +49,8 @@ def test_fp64_residual_full(prob_e, mesh_e):
     m, q = mesh_e
     print("[E: oracle residual]", flush=True)
     ref = oracle.residual(m.e2n, q, m.w)
-    for variant, acc in ((pk.OWNER, pk.WRITE), (pk.OWNER, pk.INC), (pk.COLOURED, pk.INC)):
+    for variant, acc in ((pk.OWNER, pk.WRITE), (pk.OWNER, pk.INC), (pk.COLOURED, pk.INC),
+                         (pk.FLAT, pk.INC)):
         res = torch.full((6, m.N), 0.0 if acc == pk.INC else 7.0, dtype=torch.float64, device=DEV)
         p64.residual(p64.qa, res, variant, acc)
         p64.ctx.sync()
@@ -82,6 +83,16 @@ def test_time_step_and_rk_iteration_full(prob_e, mesh_e):
     assert report("E state after one iteration", normwise(p64.nodes_out(p64.qa), q1), 1e-12)
     assert report("E stage rms", normwise(p64.rms(), np.sqrt(ss / m.N)), 1e-12)
     p64.qa.copy_(qa0)
+
+
+def test_local_time_steps_full(prob_e, mesh_e):
+    p64, _ = prob_e
+    m, q = mesh_e
+    ref = oracle.local_dt(m.e2n, q, m.w, m.vol, cfl=0.5)
+    dtl = p64.compute_local_dt(0.5, pk.OWNER)
+    p64.ctx.sync()
+    assert report("E local dt", normwise(p64.nodes_out(dtl[None]), ref[None]), 1e-12)
+    assert float(dtl.min()) == pytest.approx(oracle.dt(m.e2n, q, m.w, m.vol), rel=1e-12)
 
 
 def test_adjoint_sampled_full(prob_e, mesh_e):

@@ -168,6 +168,27 @@ def test_rk_iteration(small):
         assert report(f"q v{variant}", normwise(p.nodes_out(p.qa), q_ref), TOL64)
 
 
+def test_local_time_steps(small):
+    """Per-node steps (spectral-radius loop + LOCAL_DT) and one 5-stage
+    iteration with them, every variant, against the oracle."""
+    name, m, q, _ = small
+    print(f"[local time steps {name}]", flush=True)
+    dtl_ref = oracle.local_dt(m.e2n, q, m.w, m.vol, cfl=0.5)
+    q_ref, ss_ref = oracle.rk_iteration_local(m.e2n, q, m.w, m.vol, dtl_ref)
+    p = problem(m, q)
+    for variant in variants(p):
+        p = problem(m, q)
+        dtl = p.compute_local_dt(0.5, variant)
+        p.ctx.sync()
+        assert report(f"local dt v{variant}", normwise(p.nodes_out(dtl[None]), dtl_ref[None]),
+                      TOL64)
+        p.rk_iteration_local(variant)
+        p.ctx.sync()
+        assert report(f"local-step rms v{variant}", normwise(p.rms(), np.sqrt(ss_ref / m.N)),
+                      TOL64)
+        assert report(f"local-step q v{variant}", normwise(p.nodes_out(p.qa), q_ref), TOL64)
+
+
 def test_fp32_storage_stage(small):
     name, m, q, _ = small
     q32 = q.astype(np.float32).astype(np.float64)

@@ -293,6 +293,23 @@ def test_loop_argument_checks_without_device():
     assert flux(w, variant=pk.COLOURED) == pk.EACCESS
     assert flux(w, variant=pk.OWNER) == pk.EDEVICE
     assert "host-only" in lib.opf_last_error(ctx._ctx).decode()
+    assert flux(w, variant=pk.FLAT) == pk.EACCESS
+    assert flux(good, variant=pk.FLAT) == pk.EDEVICE
+    assert flux(good, variant=5) == pk.EINVAL
+    # local time steps: signatures of LOCAL_DT and of the stage with a step per node
+    vol, lam, dtl = dat(nodes, 1, pk.F64, 3), dat(nodes, 1, pk.F64, 3), dat(nodes, 1, pk.F64, 3)
+    edat = dat(edges, 1, pk.F64, 2)
+    assert lib.opf_local_dt(ctx._ctx, nodes, vol, lam, 0.5, dtl, None) == pk.EDEVICE
+    assert lib.opf_local_dt(ctx._ctx, nodes, vol, lam, 0.5, lam, None) == pk.EINVAL  # alias
+    assert lib.opf_local_dt(ctx._ctx, nodes, vol, lam, 0.5, edat, None) == pk.EINVAL  # wrong set
+    q0, q1 = dat(nodes, 6, pk.F64, 3), dat(nodes, 6, pk.F64, 3)
+    assert lib.opf_rk_stage_local(ctx._ctx, nodes, q0, res, vol, dtl, q1, 0.25, None, pk.RW,
+                                  None) == pk.EINVAL  # ss must be device memory
+    ss = (ctypes.c_double * 6)()
+    assert lib.opf_rk_stage_local(ctx._ctx, nodes, q0, res, vol, dtl, q1, 0.25,
+                                  ctypes.addressof(ss), pk.RW, None) in (pk.EDEVICE, pk.EINVAL)
+    assert lib.opf_rk_stage_local(ctx._ctx, nodes, q0, res, vol, q0, q1, 0.25,
+                                  ctypes.addressof(ss), pk.RW, None) == pk.ESIZE  # dt of dim 6
     # a stale plan is refused
     ctx.decl_map(edges, nodes, 2, np.array([[0, 2], [1, 2]]), 0, "e2n")
     assert flux(good) == pk.ESTATE
