@@ -97,6 +97,27 @@ class Mesh:
         return out
 
 
+def edge_vectors(mesh):
+    """(3, E) edge vectors x_j - x_i from the first to the second endpoint, taken
+    across the periodic boundary where shorter (the unit box; jitter stays below
+    a quarter of the spacing, so every edge is shorter than half the box)."""
+    d = mesh.xyz[:, mesh.e2n[:, 1]] - mesh.xyz[:, mesh.e2n[:, 0]]
+    return d - np.round(d)
+
+
+def smooth_state(mesh, amp=0.1, gamma=GAMMA):
+    """A smooth periodic state: density 1 + amp sin(2 pi x) (x the first
+    coordinate), uniform velocity (0.5, 0.2, -0.1), pressure 1, scalar 0.3."""
+    rho = 1.0 + amp * np.sin(2 * np.pi * mesh.xyz[0])
+    u = np.array([0.5, 0.2, -0.1])
+    q = np.empty((6, mesh.N))
+    q[0] = rho
+    q[1:4] = rho[None, :] * u[:, None]
+    q[4] = 1.0 / (gamma - 1.0) + 0.5 * rho * (u @ u)
+    q[5] = 0.3 * rho
+    return q
+
+
 def sizes(n, split=0):
     lib = _load()
     p = _Params(n, split, 1, 0, 0.0, 0)

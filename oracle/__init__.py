@@ -36,6 +36,8 @@ def _load():
         lib.orc_rk_stage_local.argtypes = [i64, vp, vp, vp, vp, d, vp, vp]
         lib.orc_rk_iteration_local.argtypes = [i64, i64, vp, vp, vp, vp, d, vp, vp]
         lib.orc_dt.restype = d
+        lib.orc_gradient.argtypes = [i64, i64, vp, vp, vp, vp]
+        lib.orc_residual2.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, d, vp]
         lib.orc_jvp.argtypes = [i64, i64, vp, vp, vp, d, vp, vp, vp]
         lib.orc_edge_jacobian.argtypes = [vp, vp, vp, d, vp, vp]
         lib.orc_adjoint.argtypes = [i64, i64, vp, vp, vp, d, vp, vp, vp]
@@ -149,6 +151,24 @@ def rk_iteration_local(e2n, q0, w, vol, dt, gamma=1.4):
     _check(_load().orc_rk_iteration_local(q.shape[1], w.shape[1], _p(e2n), _p(q), _p(w), _p(vol),
                                           gamma, _p(dt), _p(ss)), "orc_rk_iteration_local")
     return q, ss.reshape(5, 6)
+
+
+def gradient(e2n, q, w):
+    """Green-Gauss sums G (18, N), component (v, d) in row 3v + d; gradient = G / vol."""
+    e2n, q, w = _c(e2n, np.int32), _c(q), _c(w)
+    G = np.zeros((18, q.shape[1]))
+    _check(_load().orc_gradient(q.shape[1], w.shape[1], _p(e2n), _p(q), _p(w), _p(G)),
+           "orc_gradient")
+    return G
+
+
+def residual2(e2n, q, G, vol, w, dx, gamma=1.4):
+    """Second-order residual from Green-Gauss sums G (18, N) and edge vectors dx (3, E)."""
+    e2n, q, G, vol, w, dx = (_c(e2n, np.int32), _c(q), _c(G), _c(vol), _c(w), _c(dx))
+    res = np.zeros((6, q.shape[1]))
+    _check(_load().orc_residual2(q.shape[1], w.shape[1], _p(e2n), _p(q), _p(G), _p(vol), _p(w),
+                                 _p(dx), gamma, _p(res)), "orc_residual2")
+    return res
 
 
 def jvp(e2n, q, w, dq=None, dw=None, gamma=1.4):

@@ -137,6 +137,62 @@ int orc_residual(int64_t N, int64_t E, const int32_t *e2n, const double *q, cons
     return 0;
 }
 
+/* Gradient and second-order flux.  The paper names the loops (a gradient
+ * accumulation over edges and the dominant viscous edge flux, Sec. 4's loop
+ * tables) but not their numerics.  Readings: the gradient is the Green-Gauss
+ * sum over each median-dual cell with the face value taken as the mean of the
+ * two end states; the second-order flux applies the first-order edge flux to
+ * states reconstructed linearly, without a limiter, to the edge midpoint. */
+int orc_gradient(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+                 double *G)
+{
+    if (N <= 0 || E < 0) return ORC_EINVAL;
+    if (check_map(N, E, e2n)) return ORC_ERANGE;
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t i = e2n[2 * e], j = e2n[2 * e + 1];
+        for (int v = 0; v < 6; ++v) {
+            double face = 0.5 * (q[(int64_t)v * N + i] + q[(int64_t)v * N + j]);
+            for (int d = 0; d < 3; ++d) {
+                double g = face * w[(int64_t)d * E + e];
+                G[(int64_t)(3 * v + d) * N + i] += g;
+                G[(int64_t)(3 * v + d) * N + j] -= g;
+            }
+        }
+    }
+    return 0;
+}
+
+int orc_residual2(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *G,
+                  const double *vol, const double *w, const double *dx, double gamma,
+                  double *res)
+{
+    if (N <= 0 || E < 0) return ORC_EINVAL;
+    if (check_map(N, E, e2n)) return ORC_ERANGE;
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t i = e2n[2 * e], j = e2n[2 * e + 1];
+        double qL[6], qR[6], n[3], d[3], F[6];
+        for (int k = 0; k < 3; ++k) {
+            n[k] = w[(int64_t)k * E + e];
+            d[k] = dx[(int64_t)k * E + e];
+        }
+        for (int v = 0; v < 6; ++v) {
+            double si = 0.0, sj = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                si += G[(int64_t)(3 * v + k) * N + i] / vol[i] * d[k];
+                sj += G[(int64_t)(3 * v + k) * N + j] / vol[j] * d[k];
+            }
+            qL[v] = q[(int64_t)v * N + i] + 0.5 * si;
+            qR[v] = q[(int64_t)v * N + j] - 0.5 * sj;
+        }
+        orc_flux(qL, qR, n, gamma, F);
+        for (int v = 0; v < 6; ++v) {
+            res[(int64_t)v * N + i] += F[v];
+            res[(int64_t)v * N + j] -= F[v];
+        }
+    }
+    return 0;
+}
+
 /* Neumaier's compensated summation. */
 typedef struct {
     double s, c;

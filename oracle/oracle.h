@@ -55,6 +55,19 @@ int orc_rk_iteration_local(int64_t N, int64_t E, const int32_t *e2n, double *q0,
 double orc_dt(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
               const double *vol, double gamma, double cfl);
 
+/* Green-Gauss sums over the median-dual cells: for each edge, +1/2 (q_i + q_j)
+ * n_e is added to node i and subtracted from node j.  G holds 18 components
+ * per node, (v, d) at G[(3v + d) N + k]; the nodal gradient is G / vol. */
+int orc_gradient(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
+                 double *G);
+
+/* Second-order residual: the edge flux of the reconstructed states
+ * q_L = q_i + 1/2 (G_i / vol_i) . d_e and q_R = q_j - 1/2 (G_j / vol_j) . d_e,
+ * d_e = x_j - x_i (dx[3E]); res[6N] += F(q_L, q_R, n_e) at i, -= at j. */
+int orc_residual2(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *G,
+                  const double *vol, const double *w, const double *dx, double gamma,
+                  double *res);
+
 /* jv[6N] = J (dq, dw): the residual's directional derivative (dual numbers). */
 int orc_jvp(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
             double gamma, const double *dq, const double *dw, double *jv);

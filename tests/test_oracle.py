@@ -38,6 +38,13 @@ def euler_flux_from_primitives(rho, u, p, phi, n):
                      rho * phi * un])
 
 
+def physical_flux(q, n):
+    rho = q[0]
+    u = q[1:4] / rho
+    p = (GAMMA - 1.0) * (q[4] - 0.5 * rho * float(u @ u))
+    return euler_flux_from_primitives(rho, u, p, q[5] / rho, n)
+
+
 def cons(rho, u, p, phi):
     u = np.asarray(u, float)
     return np.array([rho, rho * u[0], rho * u[1], rho * u[2],
@@ -291,6 +298,91 @@ def test_local_time_stepping_amplification_polynomial():
     qn, _ = oracle.rk_iteration_local(m.e2n, q, m.w, m.vol, dtl)
     assert np.abs(qn[5] - Pq).max() <= 1e-14
     assert np.abs(qn[:5] - base[:5, None]).max() <= 1e-15
+
+
+def test_gradient_closure_and_linear_exactness(mesh_j):
+    """A constant field has zero Green-Gauss sums (closed dual cells); a linear
+    field a.x + b gets G_i / vol_i = a exactly at every node none of whose edges
+    crosses the periodic boundary (from sum_e n_e (x) d_e = 2 vol I)."""
+    m = mesh_j
+    q = np.repeat(cons(1.1, [0.2, -0.3, 0.1], 0.8, 0.4)[:, None], m.N, axis=1)
+    assert np.abs(oracle.gradient(m.e2n, q, m.w)).max() <= 1e-14 * np.abs(q).max()
+    rng = np.random.default_rng(21)
+    a = rng.normal(size=(6, 3))
+    b = rng.normal(size=6)
+    ql = a @ m.xyz + b[:, None]
+    G = oracle.gradient(m.e2n, ql, m.w)
+    d = m.xyz[:, m.e2n[:, 1]] - m.xyz[:, m.e2n[:, 0]]
+    wraps = (np.abs(d) > 0.5).any(axis=0)
+    bad = np.zeros(m.N, bool)
+    bad[m.e2n[wraps].ravel()] = True
+    inner = ~bad
+    assert inner.sum() > m.N // 4
+    for v in range(6):
+        for k in range(3):
+            got = G[3 * v + k, inner] / m.vol[inner]
+            assert np.abs(got - a[v, k]).max() <= 1e-11 * np.abs(a).max()
+
+
+def smooth_divergence(m, amp=0.1):
+    """div F(q) at the nodes for meshgen.smooth_state: rho(x) varies, velocity
+    and pressure are uniform, so each flux component is a multiple of rho'(x)."""
+    u = np.array([0.5, 0.2, -0.1])
+    drho = amp * 2 * np.pi * np.cos(2 * np.pi * m.xyz[0])
+    div = np.zeros((6, m.N))
+    div[0] = u[0] * drho                         # (rho u)_x
+    div[1:4] = u[:, None] * u[0] * drho[None]    # (rho u_k u)_x, p uniform
+    div[4] = 0.5 * (u @ u) * u[0] * drho         # ((rho E + p) u)_x
+    div[5] = 0.3 * u[0] * drho                   # (rho phi u)_x
+    return div, drho
+
+
+def test_gradient_and_second_order_flux_convergence():
+    """On the regular lattice (h = 1/8, 1/16, 1/32) with a smooth periodic
+    state: the Green-Gauss gradient converges at second order, the first-order
+    residual / vol approaches div F at first order (the dissipation is O(h)),
+    and the reconstructed residual at second order or better."""
+    e1, e2, eg = [], [], []
+    for n in (8, 16, 32):
+        m = meshgen.build_mesh(n, 0, 0.0)
+        q = meshgen.smooth_state(m)
+        G = oracle.gradient(m.e2n, q, m.w)
+        div, drho = smooth_divergence(m)
+        r1 = oracle.residual(m.e2n, q, m.w)
+        r2 = oracle.residual2(m.e2n, q, G, m.vol, m.w, meshgen.edge_vectors(m))
+        e1.append(np.abs(r1 / m.vol - div).max())
+        e2.append(np.abs(r2 / m.vol - div).max())
+        eg.append(np.abs(G[0] / m.vol - drho).max())
+    for k in range(2):
+        assert 1.7 < e1[k] / e1[k + 1] < 2.3
+        assert e2[k] / e2[k + 1] > 3.5
+        assert 3.5 < eg[k] / eg[k + 1] < 4.5
+    assert e2[-1] < 0.05 * e1[-1]
+
+
+def test_second_order_residual_special_cases(mesh_j):
+    m = mesh_j
+    q = meshgen.state(m.N, m.perm)
+    dx = meshgen.edge_vectors(m)
+    # zero gradients: exactly the first-order residual
+    r2 = oracle.residual2(m.e2n, q, np.zeros((18, m.N)), m.vol, m.w, dx)
+    assert np.array_equal(r2, oracle.residual(m.e2n, q, m.w))
+    # conservation with gradients
+    G = oracle.gradient(m.e2n, q, m.w)
+    r2 = oracle.residual2(m.e2n, q, G, m.vol, m.w, dx)
+    assert np.abs(r2.sum(axis=1)).max() <= 1e-12 * np.abs(r2).max()
+    # a linear profile along one edge with its exact gradient at both ends
+    # reconstructs the midpoint state on both sides: no dissipation, the flux is
+    # the physical flux of the midpoint state
+    _, qi, qj, n, _ = flux_hand_cases()[0]
+    d = np.array([0.3, -0.2, 0.5])
+    g = np.outer(qj - qi, d) / (d @ d)          # any gradient with g.d = qj - qi
+    vol = np.array([2.0, 3.0])
+    Gs = np.concatenate([(g * vol[0]).reshape(18, 1), (g * vol[1]).reshape(18, 1)], 1)
+    r = oracle.residual2(np.array([[0, 1]], np.int32), np.stack([qi, qj], 1), Gs, vol,
+                         n.reshape(3, 1), d.reshape(3, 1))
+    qm = 0.5 * (qi + qj)
+    np.testing.assert_allclose(r[:, 0], physical_flux(qm, n), rtol=1e-13, atol=1e-14)
 
 
 def test_edge_jacobian_vs_central_differences():
