@@ -88,8 +88,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--variant", choices=["owner", "coloured", "atomic", "coloured-lds-atomic"],
-                    default="owner")
+    ap.add_argument("--variant", default="owner",
+                    choices=["owner", "coloured", "atomic", "coloured-lds-atomic", "flat"])
     ap.add_argument("--cluster-size", type=int, default=512)
     ap.add_argument("--no-lane-groups", action="store_true")
     ap.add_argument("--renumber", choices=["rcm", "morton", "none"], default="morton")
