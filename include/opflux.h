@@ -72,7 +72,9 @@ typedef enum {
     OPF_K_RK_STAGE = 2,      /* direct explicit stage update + sum-of-squares     */
     OPF_K_EDGE_SPECRAD = 3,  /* OP_INC of the edge spectral radius into nodes     */
     OPF_K_DT_MIN = 4,        /* direct: global min over nodes of cfl*vol/lambda   */
-    OPF_K_LOCAL_DT = 5       /* direct: per-node step cfl*vol/lambda              */
+    OPF_K_LOCAL_DT = 5,      /* direct: per-node step cfl*vol/lambda              */
+    OPF_K_EDGE_GRAD = 6,     /* Green-Gauss sums of the state, OP_INC of 18/node  */
+    OPF_K_EDGE_FLUX2 = 7     /* second-order (reconstructed) edge flux, OP_INC    */
 } opf_kernel;
 
 /* How an indirect (edge) loop resolves its increments. */
@@ -297,6 +299,20 @@ typedef struct {
  *     gbl (gamma, 1, F64, READ, host)
  *  EDGE_SPECRAD over edges: (q,0,e2n,6,T,READ) (q,1,e2n,6,T,READ)
  *     (n,-1,ID,3,T,READ) (lam,0,e2n,1,F64,INC) (lam,1,e2n,1,F64,INC) gbl gamma
+ *  EDGE_GRAD over edges (FP64, no globals): (q,0,e2n,6,READ) (q,1,e2n,6,READ)
+ *     (n,-1,ID,3,READ) (G,0,e2n,18,INC) (G,1,e2n,18,INC)
+ *   Green-Gauss sums over the median-dual cells (the gradient accumulation
+ *   loop of Sec. 4's loop tables): +1/2 (q_i + q_j) n_e into G_i and the
+ *   negative into G_j; component (v, d) of G is 3v + d; the nodal gradient
+ *   is G / vol.
+ *  EDGE_FLUX2 over edges (FP64): (q,0,e2n,6,READ) (q,1,e2n,6,READ)
+ *     (G,0,e2n,18,READ) (G,1,e2n,18,READ) (vol,0,e2n,1,READ) (vol,1,e2n,1,READ)
+ *     (n,-1,ID,3,READ) (dx,-1,ID,3,READ) (res,0,e2n,6,INC) (res,1,e2n,6,INC)
+ *     gbl (gamma, 1, F64, READ, host)
+ *   the EDGE_FLUX flux of the states reconstructed to the edge midpoint,
+ *   q_L = q_i + 1/2 (G_i/vol_i).dx_e and q_R = q_j - 1/2 (G_j/vol_j).dx_e,
+ *   dx_e = x_j - x_i; WRITE increments with the OWNER variant as above.
+ *  In every edge loop the increment target must not be one of the inputs.
  *  RK_STAGE over nodes (direct):
  *     (q0,-1,ID,6,T,READ) (res,-1,ID,6,F64,RW) (vol,-1,ID,1,F64,READ)
  *     (q,-1,ID,6,T,WRITE)
@@ -332,6 +348,11 @@ int opf_edge_flux_adjoint(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, o
                           int qbar_access, void *stream);
 int opf_edge_specrad(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
                      opf_dat lam, double gamma, int variant, void *stream);
+int opf_edge_gradient(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n, opf_dat G,
+                      int variant, int g_access, void *stream);
+int opf_edge_flux2(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat G, opf_dat vol,
+                   opf_dat n, opf_dat dx, opf_dat res, double gamma, int variant, int res_access,
+                   void *stream);
 int opf_rk_stage(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol, opf_dat q,
                  double alpha_dt, double *ss_dev, int res_access, void *stream);
 int opf_rk_stage_local(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol,

@@ -102,7 +102,7 @@ def edge_vectors(mesh):
     across the periodic boundary where shorter (the unit box; jitter stays below
     a quarter of the spacing, so every edge is shorter than half the box)."""
     d = mesh.xyz[:, mesh.e2n[:, 1]] - mesh.xyz[:, mesh.e2n[:, 0]]
-    return d - np.round(d)
+    return np.ascontiguousarray(d - np.round(d))
 
 
 def smooth_state(mesh, amp=0.1, gamma=GAMMA):

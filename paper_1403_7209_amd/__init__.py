@@ -45,7 +45,8 @@ RK_ALPHA = (1.0 / 4.0, 1.0 / 6.0, 3.0 / 8.0, 1.0 / 2.0, 1.0)
 SYMBOLS = ("opf_init", "opf_finalize", "opf_last_error", "opf_set_allocator", "opf_decl_set",
            "opf_decl_map", "opf_plan", "opf_get_perm", "opf_plan_view_get", "opf_plan_verify",
            "opf_decl_dat", "opf_par_loop", "opf_edge_flux", "opf_edge_flux_adjoint",
-           "opf_edge_specrad", "opf_rk_stage", "opf_rk_stage_local", "opf_local_dt", "opf_dt_min",
+           "opf_edge_specrad", "opf_edge_gradient", "opf_edge_flux2", "opf_rk_stage",
+           "opf_rk_stage_local", "opf_local_dt", "opf_dt_min",
            "opf_sync", "opf_check_finite")
 
 
@@ -143,6 +144,9 @@ def load():
     lib.opf_edge_flux_adjoint.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, d, ctypes.c_int,
                                           ctypes.c_int, vp]
     lib.opf_edge_specrad.argtypes = [vp, i32, i32, i32, i32, i32, d, ctypes.c_int, vp]
+    lib.opf_edge_gradient.argtypes = [vp, i32, i32, i32, i32, i32, ctypes.c_int, ctypes.c_int, vp]
+    lib.opf_edge_flux2.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i32, d, ctypes.c_int,
+                                   ctypes.c_int, vp]
     lib.opf_rk_stage.argtypes = [vp, i32, i32, i32, i32, i32, d, vp, ctypes.c_int, vp]
     lib.opf_dt_min.argtypes = [vp, i32, i32, i32, d, vp, vp]
     lib.opf_rk_stage_local.argtypes = [vp, i32, i32, i32, i32, i32, i32, d, vp, ctypes.c_int, vp]
@@ -339,6 +343,19 @@ class Context:
         self._check(self.lib.opf_edge_specrad(self._ctx, edges, e2n, q, n, lam, gamma, variant,
                                               _stream_ptr(stream, self.device)), "opf_edge_specrad")
 
+    def edge_gradient(self, edges, e2n, q, n, G, variant=COLOURED, g_access=INC, stream=None):
+        """Green-Gauss sums G (18 per node, component 3v + d) += over the edges."""
+        self._check(self.lib.opf_edge_gradient(self._ctx, edges, e2n, q, n, G, variant, g_access,
+                                               _stream_ptr(stream, self.device)),
+                    "opf_edge_gradient")
+
+    def edge_flux2(self, edges, e2n, q, G, vol, n, dx, res, gamma=1.4, variant=COLOURED,
+                   res_access=INC, stream=None):
+        """Second-order residual from the Green-Gauss sums G and edge vectors dx."""
+        self._check(self.lib.opf_edge_flux2(self._ctx, edges, e2n, q, G, vol, n, dx, res, gamma,
+                                            variant, res_access, _stream_ptr(stream, self.device)),
+                    "opf_edge_flux2")
+
     def rk_stage(self, nodes, q0, res, vol, q, alpha_dt, ss, res_access=RW, stream=None):
         """ss: float64 device tensor of 6 values, incremented by sum res^2.
         res_access RW zeroes res after use, READ leaves it."""
@@ -423,7 +440,7 @@ class FluxProblem:
         """Host (d, n) array in user numbering -> device tensor in internal numbering."""
         a = np.asarray(a)
         perm = self.edge_new if edges else self.node_new
-        out = np.empty_like(a)
+        out = np.empty(a.shape, dtype=a.dtype)  # C order whatever the layout of a
         out[:, perm] = a
         return torch.from_numpy(out).to(self.ctx.torch_device)
 
@@ -465,6 +482,22 @@ class FluxProblem:
             self.ctx.rk_stage(self.nodes, qa, self.res_d, self.vol, qb, RK_ALPHA[k] * dt,
                               self.ss[k], rk, stream)
         self.qa, self.qb = self.qb, self.qa
+
+    def set_edge_vectors(self, dx):
+        """Edge vectors x_j - x_i (3, E), user numbering, for the second-order loop."""
+        self.dx_t = self.nodes_in(np.asarray(dx, dtype=np.float64), edges=True)
+        self.dx = self.ctx.decl_dat(self.edges, self.dx_t, "dx")
+
+    def gradient(self, q_t, G_t, variant=COLOURED, g_access=INC, stream=None):
+        """G_t (18, N) float64 (internal numbering) += Green-Gauss sums of q_t."""
+        self.ctx.edge_gradient(self.edges, self.e2n, self.dat(q_t, "q"), self.w,
+                               self.dat(G_t, "G"), variant, g_access, stream)
+
+    def residual2(self, q_t, G_t, res_t, variant=COLOURED, res_access=INC, stream=None):
+        """res_t += second-order residual of q_t from its Green-Gauss sums G_t."""
+        self.ctx.edge_flux2(self.edges, self.e2n, self.dat(q_t, "q"), self.dat(G_t, "G"), self.vol,
+                            self.w, self.dx, self.dat(res_t, "res"), self.gamma, variant,
+                            res_access, stream)
 
     def compute_local_dt(self, cfl=0.5, variant=COLOURED, stream=None):
         """Per-node time steps cfl * vol_i / sum_e lambda_e of the current state,

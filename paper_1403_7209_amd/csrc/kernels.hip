@@ -82,7 +82,7 @@ __device__ __forceinline__ float tabs(float x) { return fabsf(x); }
 // -F to node j.  Staged record: rho, u[0..2], rho E, rho phi, p, c (the
 // momentum is rebuilt as rho u).
 struct OpFlux {
-    static constexpr int NIN = 6, NS = 8, NOUT = 6, NWOUT = 0, MODE = ANTI;
+    static constexpr int NIN = 6, NS = 8, NOUT = 6, NW = 3, NWOUT = 0, MODE = ANTI;
     template <typename T>
     __device__ static __forceinline__ void stage(const T *x, T *s, T gamma)
     {
@@ -120,7 +120,7 @@ struct OpFlux {
 // lambda_e added to both end nodes (local time-step denominator).
 // Staged record: u[0..2], c.
 struct OpSpecrad {
-    static constexpr int NIN = 5, NS = 4, NOUT = 1, NWOUT = 0, MODE = SAME;
+    static constexpr int NIN = 5, NS = 4, NOUT = 1, NW = 3, NWOUT = 0, MODE = SAME;
     template <typename T>
     __device__ static __forceinline__ void stage(const T *x, T *s, T gamma)
     {
@@ -207,7 +207,7 @@ __device__ __forceinline__ void node_reverse(const double *q, const Prim<double>
 // Fbar = rbar_i - rbar_j it returns qbar_i, qbar_j and nbar (direct).
 // Forward intermediates are recomputed, never stored.
 struct OpAdjoint {
-    static constexpr int NIN = 12, NS = 12, NOUT = 6, NWOUT = 3, MODE = GEN;
+    static constexpr int NIN = 12, NS = 12, NOUT = 6, NW = 3, NWOUT = 3, MODE = GEN;
     template <typename T>
     __device__ static __forceinline__ void stage(const T *x, T *s, T)
     {
@@ -252,6 +252,61 @@ struct OpAdjoint {
     }
 };
 
+// Green-Gauss sums: +1/2 (q_i + q_j) n_e into node i (component 3v + d),
+// the negative into node j.  Staged record: the state itself.
+struct OpGrad {
+    static constexpr int NIN = 6, NS = 6, NOUT = 18, NW = 3, NWOUT = 0, MODE = ANTI;
+    template <typename T>
+    __device__ static __forceinline__ void stage(const T *x, T *s, T)
+    {
+#pragma unroll
+        for (int v = 0; v < 6; ++v) s[v] = x[v];
+    }
+    template <typename T>
+    __device__ static __forceinline__ void edge(const T *a, const T *b, const T *n, T,
+                                                double *yi, double *, double *)
+    {
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            const T f = T(0.5) * (a[v] + b[v]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) yi[3 * v + d] = (double)(f * n[d]);
+        }
+    }
+};
+
+// Second-order flux: the OpFlux flux of the states reconstructed linearly to
+// the edge midpoint.  Node inputs: q (6), Green-Gauss sums G (18), vol (1);
+// staged record: q and the gradient G / vol.  Edge inputs: n, then dx = x_j - x_i.
+struct OpFlux2 {
+    static constexpr int NIN = 25, NS = 24, NOUT = 6, NW = 6, NWOUT = 0, MODE = ANTI;
+    template <typename T>
+    __device__ static __forceinline__ void stage(const T *x, T *s, T)
+    {
+        const T iv = trcp(x[24]);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) s[v] = x[v];
+#pragma unroll
+        for (int k = 0; k < 18; ++k) s[6 + k] = x[6 + k] * iv;
+    }
+    template <typename T>
+    __device__ static __forceinline__ void edge(const T *a, const T *b, const T *w, T gamma,
+                                                double *yi, double *, double *)
+    {
+        const T h = T(0.5);
+        T qL[6], qR[6];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            qL[v] = a[v] + h * (a[6 + 3 * v] * w[3] + a[7 + 3 * v] * w[4] + a[8 + 3 * v] * w[5]);
+            qR[v] = b[v] - h * (b[6 + 3 * v] * w[3] + b[7 + 3 * v] * w[4] + b[8 + 3 * v] * w[5]);
+        }
+        T sL[OpFlux::NS], sR[OpFlux::NS];
+        OpFlux::stage(qL, sL, gamma);
+        OpFlux::stage(qR, sR, gamma);
+        OpFlux::edge(sL, sR, w, gamma, yi, nullptr, nullptr);
+    }
+};
+
 template <typename T, class Op>
 struct OwnerTune {
     static constexpr int B = 2, WAVES = 0;
@@ -263,6 +318,14 @@ struct OwnerTune<double, OpFlux> {
 template <>
 struct OwnerTune<double, OpAdjoint> {
     static constexpr int B = OPF_ADJ_BATCH, WAVES = OPF_ADJ_WAVES;
+};
+template <>
+struct OwnerTune<double, OpGrad> {
+    static constexpr int B = 1, WAVES = 0;
+};
+template <>
+struct OwnerTune<double, OpFlux2> {
+    static constexpr int B = 1, WAVES = 0;
 };
 
 // ----------------------------------------------------------- plumbing -- */
@@ -287,9 +350,9 @@ struct OwnerPtrs {
 
 template <typename T>
 struct Arrays {
-    const T *x[12];
-    double *y[6];
-    const T *w[3];
+    const T *x[kMaxNodeIn];
+    double *y[kMaxNodeOut];
+    const T *w[kMaxEdgeIn];
     double *wo[3];
 };
 
@@ -297,9 +360,9 @@ template <typename T>
 Arrays<T> typed(const EdgeArrays &a)
 {
     Arrays<T> r;
-    for (int k = 0; k < 12; ++k) r.x[k] = static_cast<const T *>(a.xin[k]);
-    for (int k = 0; k < 6; ++k) r.y[k] = a.yout[k];
-    for (int k = 0; k < 3; ++k) r.w[k] = static_cast<const T *>(a.w[k]);
+    for (int k = 0; k < kMaxNodeIn; ++k) r.x[k] = static_cast<const T *>(a.xin[k]);
+    for (int k = 0; k < kMaxNodeOut; ++k) r.y[k] = a.yout[k];
+    for (int k = 0; k < kMaxEdgeIn; ++k) r.w[k] = static_cast<const T *>(a.w[k]);
     for (int k = 0; k < 3; ++k) r.wo[k] = a.wout[k];
     return r;
 }
@@ -427,11 +490,11 @@ __global__ __launch_bounds__(NT) void k_edge_coloured(PlanPtrs p, Arrays<T> a, T
             li[t] = (int)(l & 0xffffu);
             lj[t] = (int)(l >> 16);
             col[t] = p.ecol[e0 + e];
-            T si[Op::NS], sj[Op::NS], n[3];
+            T si[Op::NS], sj[Op::NS], n[Op::NW];
             lds_get<T, Op::NS>(ss, umax, li[t], si);
             lds_get<T, Op::NS>(ss, umax, lj[t], sj);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) n[d] = ld(a.w[d], e0 + e);
+            for (int d = 0; d < Op::NW; ++d) n[d] = ld(a.w[d], e0 + e);
             double wo[3] = {0.0, 0.0, 0.0};
             Op::edge(si, sj, n, gamma, y[t], y[t] + (NY - Op::NOUT), wo);
             if (Op::NWOUT) {
@@ -490,11 +553,11 @@ __global__ __launch_bounds__(256) void k_edge_atomic(const int2 *__restrict__ e2
     const int e = blk * 256 + (int)threadIdx.x;
     if (e >= E) return;
     const int2 ij = e2n[e];
-    T si[Op::NS], sj[Op::NS], n[3];
+    T si[Op::NS], sj[Op::NS], n[Op::NW];
     load_stage<Op>(a, ij.x, gamma, si);
     load_stage<Op>(a, ij.y, gamma, sj);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) n[d] = ld(a.w[d], e);
+    for (int d = 0; d < Op::NW; ++d) n[d] = ld(a.w[d], e);
     constexpr int NY = Op::MODE == GEN ? 2 * Op::NOUT : Op::NOUT;
     double y[NY];
     double wo[3] = {0.0, 0.0, 0.0};
@@ -526,11 +589,11 @@ __global__ __launch_bounds__(256) void k_edge_flat(const int2 *__restrict__ e2n,
     if (t >= n) return;
     const int e = eids[t];
     const int2 ij = ld(e2n, e);
-    T si[Op::NS], sj[Op::NS], w[3];
+    T si[Op::NS], sj[Op::NS], w[Op::NW];
     load_stage<Op>(a, ij.x, gamma, si);
     load_stage<Op>(a, ij.y, gamma, sj);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) w[d] = ld(a.w[d], e);
+    for (int d = 0; d < Op::NW; ++d) w[d] = ld(a.w[d], e);
     constexpr int NY = Op::MODE == GEN ? 2 * Op::NOUT : Op::NOUT;
     double y[NY];
     double wo[3] = {0.0, 0.0, 0.0};
@@ -596,13 +659,13 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
                 eid[b] = ld(p.sec_eid, sb + (k - pr.y));
         }
         int2 ij[B];
-        T w[B][3];
+        T w[B][Op::NW];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             if (eid[b] >= 0) {
                 ij[b] = ld(p.e2n, eid[b]);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) w[b][d] = ld(a.w[d], eid[b]);
+                for (int d = 0; d < Op::NW; ++d) w[b][d] = ld(a.w[d], eid[b]);
             }
         }
 #pragma unroll
@@ -895,6 +958,8 @@ int raise_all(size_t bytes)
 size_t owner_lds_bytes(int op, bool fp32, int K)
 {
     if (op == OP_ADJOINT) return owner_dyn_lds<double, OpAdjoint>(K);
+    if (op == OP_GRAD) return owner_dyn_lds<double, OpGrad>(K);
+    if (op == OP_FLUX2) return owner_dyn_lds<double, OpFlux2>(K);
     if (op == OP_SPECRAD) return fp32 ? owner_dyn_lds<float, OpSpecrad>(K) : owner_dyn_lds<double, OpSpecrad>(K);
     return fp32 ? owner_dyn_lds<float, OpFlux>(K) : owner_dyn_lds<double, OpFlux>(K);
 }
@@ -907,6 +972,8 @@ size_t edge_lds_bytes(int op, bool fp32, int variant, int umax, int K)
     if (variant == V_OWNER) return owner_lds_bytes(op, fp32, K);
     const int rows = umax;
     if (op == OP_ADJOINT) return lds_bytes<double, OpAdjoint>(rows);
+    if (op == OP_GRAD) return lds_bytes<double, OpGrad>(rows);
+    if (op == OP_FLUX2) return lds_bytes<double, OpFlux2>(rows);
     if (op == OP_SPECRAD)
         return fp32 ? lds_bytes<float, OpSpecrad>(rows) : lds_bytes<double, OpSpecrad>(rows);
     return fp32 ? lds_bytes<float, OpFlux>(rows) : lds_bytes<double, OpFlux>(rows);
@@ -919,6 +986,8 @@ int set_lds_limit(size_t bytes)
     if (!rc) rc = raise_all<double, OpSpecrad>(bytes);
     if (!rc) rc = raise_all<float, OpSpecrad>(bytes);
     if (!rc) rc = raise_all<double, OpAdjoint>(bytes);
+    if (!rc) rc = raise_all<double, OpGrad>(bytes);
+    if (!rc) rc = raise_all<double, OpFlux2>(bytes);
     return rc;
 }
 
@@ -935,6 +1004,12 @@ int launch_edge(int op, bool fp32, int variant, const DevPlan &P, const EdgeArra
     case OP_ADJOINT:
         if (fp32) return (int)hipErrorInvalidValue;
         return run_edge<double, OpAdjoint>(variant, P, a, gamma, st, lo);
+    case OP_GRAD:
+        if (fp32) return (int)hipErrorInvalidValue;
+        return run_edge<double, OpGrad>(variant, P, a, gamma, st, lo);
+    case OP_FLUX2:
+        if (fp32) return (int)hipErrorInvalidValue;
+        return run_edge<double, OpFlux2>(variant, P, a, gamma, st, lo);
     default: return (int)hipErrorInvalidValue;
     }
 }

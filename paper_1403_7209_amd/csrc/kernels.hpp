@@ -9,7 +9,11 @@
 namespace opf {
 namespace gpu {
 
-enum EdgeOpKind { OP_FLUX = 0, OP_ADJOINT = 1, OP_SPECRAD = 2 };
+enum EdgeOpKind { OP_FLUX = 0, OP_ADJOINT = 1, OP_SPECRAD = 2, OP_GRAD = 3, OP_FLUX2 = 4 };
+
+constexpr int kMaxNodeIn = 25;   // node inputs of one edge loop (q, G, vol)
+constexpr int kMaxNodeOut = 18;  // node increments (Green-Gauss sums)
+constexpr int kMaxEdgeIn = 6;    // direct edge inputs (n, dx)
 
 // Execution variants of an edge loop (values match opf_variant).
 enum Variant { V_COLOURED = 0, V_ATOMIC = 1, V_OWNER = 2, V_COLOURED_LDS_ATOMIC = 3, V_FLAT = 4 };
@@ -44,10 +48,10 @@ struct DevPlan {
 // Component pointers of the arrays an edge loop touches (SoA: one pointer per
 // component, each already offset by component * ld).
 struct EdgeArrays {
-    const void *xin[12] = {};  // node inputs (q, then rbar for the adjoint)
-    double *yout[6] = {};      // node increments (res, qbar or lambda)
-    const void *w[3] = {};     // edge weights
-    double *wout[3] = {};      // direct edge outputs (nbar)
+    const void *xin[kMaxNodeIn] = {};  // node inputs (q; then rbar, or G and vol)
+    double *yout[kMaxNodeOut] = {};    // node increments (res, qbar, lambda or G)
+    const void *w[kMaxEdgeIn] = {};    // edge inputs (weights n; then dx)
+    double *wout[3] = {};              // direct edge outputs (nbar)
 };
 
 struct LaunchOpts {

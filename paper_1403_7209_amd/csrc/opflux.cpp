@@ -251,10 +251,14 @@ int device_ready(opf_ctx *ctx)
 int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args, int ngbl,
               const opf_gbl *gbls, int variant, hipStream_t st)
 {
-    const int want_args = kernel == OPF_K_EDGE_FLUX_ADJ ? 8 : 5;
+    const bool adj = kernel == OPF_K_EDGE_FLUX_ADJ, grad = kernel == OPF_K_EDGE_GRAD,
+               flux2 = kernel == OPF_K_EDGE_FLUX2;
+    const int want_args = adj ? 8 : flux2 ? 10 : 5;
     if (nargs != want_args || !args)
         return ctx->fail(OPF_EINVAL, "expected " + std::to_string(want_args) + " arguments");
-    if (ngbl != 1 || !gbls) return ctx->fail(OPF_EINVAL, "expected one global (gamma)");
+    const int want_gbl = grad ? 0 : 1;
+    if (ngbl != want_gbl || (want_gbl && !gbls))
+        return ctx->fail(OPF_EINVAL, grad ? "expected no globals" : "expected one global (gamma)");
     if (variant < OPF_V_COLOURED || variant > OPF_V_FLAT)
         return ctx->fail(OPF_EINVAL, "unknown variant");
     const opf_map m = args[0].map;
@@ -265,26 +269,39 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
     if (!ctx->dat_ok(args[0].dat)) return ctx->fail(OPF_EINVAL, "argument 0: invalid dat");
     const int T = ctx->dats[args[0].dat].type;
     if (T != OPF_F64 && T != OPF_F32) return ctx->fail(OPF_ETYPE, "argument 0: unknown type");
-    if (kernel == OPF_K_EDGE_FLUX_ADJ && T != OPF_F64)
-        return ctx->fail(OPF_ETYPE, "the adjoint loop is FP64 only");
+    if ((adj || grad || flux2) && T != OPF_F64)
+        return ctx->fail(OPF_ETYPE, "the adjoint, gradient and second-order loops are FP64 only");
     const opf_set nodes = mr.to;
     int rc = OPF_OK;
-    const int yd = kernel == OPF_K_EDGE_SPECRAD ? 1 : 6;
-    std::vector<Want> w = {{nodes, 0, m, 6, T, OPF_READ}, {nodes, 1, m, 6, T, OPF_READ},
-                           {s, -1, OPF_ID, 3, T, OPF_READ}};
-    if (kernel == OPF_K_EDGE_FLUX_ADJ) {
+    // expected signature; `yslot` is the first of the two node-increment arguments
+    std::vector<Want> w = {{nodes, 0, m, 6, T, OPF_READ}, {nodes, 1, m, 6, T, OPF_READ}};
+    int yslot = 3;
+    if (adj) {
+        w.push_back({s, -1, OPF_ID, 3, T, OPF_READ});
         w.push_back({nodes, 0, m, 6, OPF_F64, OPF_READ});
         w.push_back({nodes, 1, m, 6, OPF_F64, OPF_READ});
         w.push_back({nodes, 0, m, 6, OPF_F64, OPF_INC});
         w.push_back({nodes, 1, m, 6, OPF_F64, OPF_INC});
         w.push_back({s, -1, OPF_ID, 3, OPF_F64, OPF_WRITE});
+        yslot = 5;
+    } else if (flux2) {
+        w.push_back({nodes, 0, m, 18, OPF_F64, OPF_READ});
+        w.push_back({nodes, 1, m, 18, OPF_F64, OPF_READ});
+        w.push_back({nodes, 0, m, 1, OPF_F64, OPF_READ});
+        w.push_back({nodes, 1, m, 1, OPF_F64, OPF_READ});
+        w.push_back({s, -1, OPF_ID, 3, OPF_F64, OPF_READ});
+        w.push_back({s, -1, OPF_ID, 3, OPF_F64, OPF_READ});
+        w.push_back({nodes, 0, m, 6, OPF_F64, OPF_INC});
+        w.push_back({nodes, 1, m, 6, OPF_F64, OPF_INC});
+        yslot = 8;
     } else {
+        const int yd = kernel == OPF_K_EDGE_SPECRAD ? 1 : grad ? 18 : 6;
+        w.push_back({s, -1, OPF_ID, 3, T, OPF_READ});
         w.push_back({nodes, 0, m, yd, OPF_F64, OPF_INC});
         w.push_back({nodes, 1, m, yd, OPF_F64, OPF_INC});
     }
     // The owner variant writes every node's total exactly once, so it also
     // accepts WRITE on the node increments (res = sum, no prior zeroing).
-    const int yslot = kernel == OPF_K_EDGE_FLUX_ADJ ? 5 : 3;
     bool overwrite = false;
     if (variant == OPF_V_OWNER && args[yslot].access == OPF_WRITE &&
         args[yslot + 1].access == OPF_WRITE) {
@@ -301,11 +318,20 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
                                                std::to_string(b) + " must name the same dat");
     };
     rc = same(0, 1);
-    if (!rc) rc = kernel == OPF_K_EDGE_FLUX_ADJ ? same(3, 4) : same(3, 4);
-    if (!rc && kernel == OPF_K_EDGE_FLUX_ADJ) rc = same(5, 6);
+    if (!rc) rc = same(yslot, yslot + 1);
+    if (!rc && adj) rc = same(3, 4);
+    if (!rc && flux2) rc = same(2, 3);
+    if (!rc && flux2) rc = same(4, 5);
     if (rc) return rc;
-    rc = check_gbl(ctx, gbls[0], 1, OPF_READ, 0, 0);
-    if (rc) return rc;
+    if (want_gbl) {
+        rc = check_gbl(ctx, gbls[0], 1, OPF_READ, 0, 0);
+        if (rc) return rc;
+    }
+    // an increment target must not be one of the loop's inputs
+    for (int k = 0; k < yslot; ++k)
+        if (args[k].dat == args[yslot].dat)
+            return ctx->fail(OPF_EINVAL, "argument " + std::to_string(yslot) +
+                                             " aliases input argument " + std::to_string(k));
     auto it = ctx->plans.find(m);
     if (it == ctx->plans.end()) return ctx->fail(OPF_ESTATE, "no plan for this map: call opf_plan");
     PlanRec &pr = *it->second;
@@ -316,7 +342,9 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
 
     const int op = kernel == OPF_K_EDGE_FLUX       ? opf::gpu::OP_FLUX
                    : kernel == OPF_K_EDGE_FLUX_ADJ ? opf::gpu::OP_ADJOINT
-                                                   : opf::gpu::OP_SPECRAD;
+                   : kernel == OPF_K_EDGE_SPECRAD  ? opf::gpu::OP_SPECRAD
+                   : grad                          ? opf::gpu::OP_GRAD
+                                                   : opf::gpu::OP_FLUX2;
     const bool fp32 = T == OPF_F32;
     if (variant == OPF_V_OWNER && !pr.dev.owner_ok)
         return ctx->fail(OPF_EINVAL, "the plan has no owner clusters (cluster_size 0)");
@@ -335,20 +363,27 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
     }
     opf::gpu::EdgeArrays ea;
     const DatRec &q = ctx->dats[args[0].dat];
-    const DatRec &n = ctx->dats[args[2].dat];
     for (int c = 0; c < 6; ++c) ea.xin[c] = comp(q, c);
-    for (int c = 0; c < 3; ++c) ea.w[c] = comp(n, c);
-    if (kernel == OPF_K_EDGE_FLUX_ADJ) {
-        const DatRec &rb = ctx->dats[args[3].dat], &qb = ctx->dats[args[5].dat];
+    const DatRec &y = ctx->dats[args[yslot].dat];
+    for (int c = 0; c < y.dim; ++c) ea.yout[c] = (double *)comp(y, c);
+    if (adj) {
+        const DatRec &n = ctx->dats[args[2].dat], &rb = ctx->dats[args[3].dat];
         const DatRec &nb = ctx->dats[args[7].dat];
+        for (int c = 0; c < 3; ++c) ea.w[c] = comp(n, c);
         for (int c = 0; c < 6; ++c) ea.xin[6 + c] = comp(rb, c);
-        for (int c = 0; c < 6; ++c) ea.yout[c] = (double *)comp(qb, c);
         for (int c = 0; c < 3; ++c) ea.wout[c] = (double *)comp(nb, c);
+    } else if (flux2) {
+        const DatRec &g = ctx->dats[args[2].dat], &vol = ctx->dats[args[4].dat];
+        const DatRec &n = ctx->dats[args[6].dat], &dx = ctx->dats[args[7].dat];
+        for (int c = 0; c < 18; ++c) ea.xin[6 + c] = comp(g, c);
+        ea.xin[24] = comp(vol, 0);
+        for (int c = 0; c < 3; ++c) ea.w[c] = comp(n, c);
+        for (int c = 0; c < 3; ++c) ea.w[3 + c] = comp(dx, c);
     } else {
-        const DatRec &r = ctx->dats[args[3].dat];
-        for (int c = 0; c < yd; ++c) ea.yout[c] = (double *)comp(r, c);
+        const DatRec &n = ctx->dats[args[2].dat];
+        for (int c = 0; c < 3; ++c) ea.w[c] = comp(n, c);
     }
-    const double gamma = *static_cast<const double *>(gbls[0].ptr);
+    const double gamma = want_gbl ? *static_cast<const double *>(gbls[0].ptr) : 0.0;
     opf::gpu::LaunchOpts lo;
     lo.overwrite = overwrite ? 1 : 0;
     int e = opf::gpu::launch_edge(op, fp32, variant, pr.dev, ea, gamma, st, lo);
@@ -718,7 +753,9 @@ int opf_par_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *
     switch (kernel) {
     case OPF_K_EDGE_FLUX:
     case OPF_K_EDGE_FLUX_ADJ:
-    case OPF_K_EDGE_SPECRAD: return edge_loop(ctx, kernel, s, nargs, args, ngbl, gbls, variant, st);
+    case OPF_K_EDGE_SPECRAD:
+    case OPF_K_EDGE_GRAD:
+    case OPF_K_EDGE_FLUX2: return edge_loop(ctx, kernel, s, nargs, args, ngbl, gbls, variant, st);
     case OPF_K_RK_STAGE:
     case OPF_K_DT_MIN:
     case OPF_K_LOCAL_DT: return direct_loop(ctx, kernel, s, nargs, args, ngbl, gbls, st);
@@ -784,6 +821,37 @@ int opf_rk_stage(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat v
                           {q, -1, OPF_ID, 6, T, OPF_WRITE}};
     const opf_gbl g[2] = {{&alpha_dt, 1, OPF_F64, OPF_READ, 0}, {ss_dev, 6, OPF_F64, OPF_INC, 1}};
     return opf_par_loop(ctx, OPF_K_RK_STAGE, nodes, 4, a, 2, g, OPF_V_COLOURED, stream);
+}
+
+int opf_edge_gradient(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n, opf_dat G,
+                      int variant, int g_access, void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    const opf_arg a[5] = {{q, 0, e2n, 6, OPF_F64, OPF_READ},
+                          {q, 1, e2n, 6, OPF_F64, OPF_READ},
+                          {n, -1, OPF_ID, 3, OPF_F64, OPF_READ},
+                          {G, 0, e2n, 18, OPF_F64, g_access},
+                          {G, 1, e2n, 18, OPF_F64, g_access}};
+    return opf_par_loop(ctx, OPF_K_EDGE_GRAD, edges, 5, a, 0, nullptr, variant, stream);
+}
+
+int opf_edge_flux2(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat G, opf_dat vol,
+                   opf_dat n, opf_dat dx, opf_dat res, double gamma, int variant, int res_access,
+                   void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    const opf_arg a[10] = {{q, 0, e2n, 6, OPF_F64, OPF_READ},
+                           {q, 1, e2n, 6, OPF_F64, OPF_READ},
+                           {G, 0, e2n, 18, OPF_F64, OPF_READ},
+                           {G, 1, e2n, 18, OPF_F64, OPF_READ},
+                           {vol, 0, e2n, 1, OPF_F64, OPF_READ},
+                           {vol, 1, e2n, 1, OPF_F64, OPF_READ},
+                           {n, -1, OPF_ID, 3, OPF_F64, OPF_READ},
+                           {dx, -1, OPF_ID, 3, OPF_F64, OPF_READ},
+                           {res, 0, e2n, 6, OPF_F64, res_access},
+                           {res, 1, e2n, 6, OPF_F64, res_access}};
+    const opf_gbl g[1] = {{&gamma, 1, OPF_F64, OPF_READ, 0}};
+    return opf_par_loop(ctx, OPF_K_EDGE_FLUX2, edges, 10, a, 1, g, variant, stream);
 }
 
 int opf_rk_stage_local(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol,

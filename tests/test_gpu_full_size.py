@@ -95,6 +95,23 @@ def test_local_time_steps_full(prob_e, mesh_e):
     assert float(dtl.min()) == pytest.approx(oracle.dt(m.e2n, q, m.w, m.vol), rel=1e-12)
 
 
+def test_gradient_and_second_order_full(prob_e, mesh_e):
+    p64, _ = prob_e
+    m, q = mesh_e
+    dx = meshgen.edge_vectors(m)
+    print("[E: oracle gradient and second-order residual]", flush=True)
+    G_ref = oracle.gradient(m.e2n, q, m.w)
+    r2_ref = oracle.residual2(m.e2n, q, G_ref, m.vol, m.w, dx)
+    p64.set_edge_vectors(dx)
+    G = torch.empty((18, m.N), dtype=torch.float64, device=DEV)
+    p64.gradient(p64.qa, G, pk.OWNER, pk.WRITE)
+    res = torch.empty((6, m.N), dtype=torch.float64, device=DEV)
+    p64.residual2(p64.qa, G, res, pk.OWNER, pk.WRITE)
+    p64.ctx.sync()
+    assert report("E G", normwise(p64.nodes_out(G), G_ref), 1e-12)
+    assert report("E res2", normwise(p64.nodes_out(res), r2_ref), 1e-12)
+
+
 def test_adjoint_sampled_full(prob_e, mesh_e):
     """qbar at sampled nodes and nbar at sampled edges, each formed one by one
     from the oracle's exact edge Jacobians."""

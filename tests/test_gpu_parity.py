@@ -189,6 +189,34 @@ def test_local_time_steps(small):
         assert report(f"local-step q v{variant}", normwise(p.nodes_out(p.qa), q_ref), TOL64)
 
 
+def test_gradient_and_second_order_flux(small):
+    """Green-Gauss sums and the reconstructed (second-order) residual, every
+    variant, against the oracle; the residual from the GPU's own sums."""
+    name, m, q, _ = small
+    print(f"[gradient + second order {name}]", flush=True)
+    dx = meshgen.edge_vectors(m)
+    G_ref = oracle.gradient(m.e2n, q, m.w)
+    r2_ref = oracle.residual2(m.e2n, q, G_ref, m.vol, m.w, dx)
+    p = problem(m, q)
+    p.set_edge_vectors(dx)
+    for variant in variants(p):
+        G = torch.zeros((18, p.N), dtype=torch.float64, device=DEV)
+        p.gradient(p.qa, G, variant)
+        res = torch.zeros((6, p.N), dtype=torch.float64, device=DEV)
+        p.residual2(p.qa, G, res, variant)
+        p.ctx.sync()
+        assert report(f"G v{variant}", normwise(p.nodes_out(G), G_ref), TOL64)
+        assert report(f"res2 v{variant}", normwise(p.nodes_out(res), r2_ref), TOL64)
+    if p.info["owner_ok"]:
+        G = torch.full((18, p.N), 3e30, dtype=torch.float64, device=DEV)
+        p.gradient(p.qa, G, pk.OWNER, pk.WRITE)
+        res = torch.full((6, p.N), -5e30, dtype=torch.float64, device=DEV)
+        p.residual2(p.qa, G, res, pk.OWNER, pk.WRITE)
+        p.ctx.sync()
+        assert report("G owner WRITE", normwise(p.nodes_out(G), G_ref), TOL64)
+        assert report("res2 owner WRITE", normwise(p.nodes_out(res), r2_ref), TOL64)
+
+
 def test_fp32_storage_stage(small):
     name, m, q, _ = small
     q32 = q.astype(np.float32).astype(np.float64)

@@ -296,6 +296,22 @@ def test_loop_argument_checks_without_device():
     assert flux(w, variant=pk.FLAT) == pk.EACCESS
     assert flux(good, variant=pk.FLAT) == pk.EDEVICE
     assert flux(good, variant=5) == pk.EINVAL
+    # gradient and second-order loops: signatures
+    G = dat(nodes, 18, pk.F64, 3)
+    dx = dat(edges, 3, pk.F64, 2)
+    assert lib.opf_edge_gradient(ctx._ctx, edges, mp, q, n, G, pk.COLOURED, pk.INC, None) == pk.EDEVICE
+    assert lib.opf_edge_gradient(ctx._ctx, edges, mp, q, n, res, pk.COLOURED, pk.INC, None) == pk.ESIZE
+    assert lib.opf_edge_gradient(ctx._ctx, edges, mp, q, n, G, pk.COLOURED, pk.WRITE, None) == pk.EACCESS
+    assert lib.opf_edge_gradient(ctx._ctx, edges, mp, res32, n, G, pk.COLOURED, pk.INC, None) == pk.ETYPE
+    vol1 = dat(nodes, 1, pk.F64, 3)
+    assert lib.opf_edge_flux2(ctx._ctx, edges, mp, q, G, vol1, n, dx, res, 1.4, pk.OWNER, pk.WRITE,
+                              None) == pk.EDEVICE
+    assert lib.opf_edge_flux2(ctx._ctx, edges, mp, q, G, vol1, n, dx, q, 1.4, pk.COLOURED, pk.INC,
+                              None) == pk.EINVAL  # increments into an input
+    assert lib.opf_edge_flux2(ctx._ctx, edges, mp, q, res, vol1, n, dx, res, 1.4, pk.COLOURED,
+                              pk.INC, None) == pk.ESIZE  # G of dimension 6
+    assert lib.opf_edge_flux2(ctx._ctx, edges, mp, q, G, vol1, n, G, res, 1.4, pk.COLOURED, pk.INC,
+                              None) == pk.EINVAL  # node dat where dx goes
     # local time steps: signatures of LOCAL_DT and of the stage with a step per node
     vol, lam, dtl = dat(nodes, 1, pk.F64, 3), dat(nodes, 1, pk.F64, 3), dat(nodes, 1, pk.F64, 3)
     edat = dat(edges, 1, pk.F64, 2)
