@@ -14,6 +14,10 @@ inputs resident in HBM.  The roofline entry is the FP64 edge-flux loop,
 priced in algorithmic bytes (32 B per edge: map 8 + weights 24; 96 B per
 node: state read 48 + residual write 48) against 8 TB/s.
 
+After the timed steps it also times, once per form and outside `value`, the
+Green-Gauss gradient loop, the second-order edge loop and the local time-step
+loop (reported under "forms").
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
@@ -35,6 +39,10 @@ BYTES = {  # algorithmic bytes: (per edge, per node)
     "adjoint": (56, 144),
     "rk64": (0, 152),
     "rk32": (0, 104),
+    # loops outside the step, timed beside it
+    "grad": (32, 192),    # map 8 + n 24; q 48 + G 144 (written)
+    "flux2": (56, 248),   # map 8 + n 24 + dx 24; q 48 + G 144 + vol 8 + res 48
+    "local_dt": (0, 24),  # vol, lam read; dt written
 }
 
 
@@ -207,6 +215,32 @@ def main():
     ctx.sync()
     if not ctx.check_finite(p64.ss) or not ctx.check_finite(p32.ss):
         log("warning: non-finite residual norm")
+
+    # loops beside the step: Green-Gauss gradient, second-order flux, local dt
+    p64.set_edge_vectors(meshgen.edge_vectors(mesh))
+    G = torch.empty((18, N), dtype=torch.float64, device=dev)
+    res2 = torch.empty((6, N), dtype=torch.float64, device=dev)
+    ga = pk.WRITE if variant == pk.OWNER else pk.INC
+    for rec in (False, True):
+        for _ in range(3 if rec else 1):
+            if ga == pk.INC:
+                G.zero_()
+                res2.zero_()
+            a = ev()
+            p64.gradient(p64.qa, G, variant, ga)
+            b = ev()
+            p64.residual2(p64.qa, G, res2, variant, ga)
+            c = ev()
+            p64.compute_local_dt(0.5, variant)
+            d = ev()
+            if rec:
+                timers.setdefault("grad", []).append((a, b))
+                timers.setdefault("flux2", []).append((b, c))
+            p64.ctx.local_dt(p64.nodes, p64.vol, p64.lam_d, 0.5, p64.dtl_d)
+            e = ev()
+            if rec:
+                timers.setdefault("local_dt", []).append((d, e))
+    torch.cuda.synchronize()
 
     per = {}
     for k, lst in timers.items():
