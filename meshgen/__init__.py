@@ -105,6 +105,28 @@ def edge_vectors(mesh):
     return np.ascontiguousarray(d - np.round(d))
 
 
+TET_LOCAL_EDGES = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+
+
+def tet_edges(mesh, tets):
+    """(T, 6) int32 edge ids of each tet's local edges in the order
+    TET_LOCAL_EDGES (connectivity only: a lookup of node pairs in e2n)."""
+    lo = np.minimum(mesh.e2n[:, 0], mesh.e2n[:, 1]).astype(np.int64)
+    hi = np.maximum(mesh.e2n[:, 0], mesh.e2n[:, 1]).astype(np.int64)
+    key = lo * mesh.N + hi
+    order = np.argsort(key)
+    skey = key[order]
+    out = np.empty((tets.shape[0], 6), np.int32)
+    for k, (a, b) in enumerate(TET_LOCAL_EDGES):
+        p, q = tets[:, a].astype(np.int64), tets[:, b].astype(np.int64)
+        want = np.minimum(p, q) * mesh.N + np.maximum(p, q)
+        pos = np.searchsorted(skey, want)
+        if np.any(pos >= len(skey)) or np.any(skey[np.minimum(pos, len(skey) - 1)] != want):
+            raise ValueError("a tet edge is missing from the edge list")
+        out[:, k] = order[pos]
+    return out
+
+
 def smooth_state(mesh, amp=0.1, gamma=GAMMA):
     """A smooth periodic state: density 1 + amp sin(2 pi x) (x the first
     coordinate), uniform velocity (0.5, 0.2, -0.1), pressure 1, scalar 0.3."""

@@ -38,6 +38,8 @@ def _load():
         lib.orc_dt.restype = d
         lib.orc_gradient.argtypes = [i64, i64, vp, vp, vp, vp]
         lib.orc_residual2.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, d, vp]
+        lib.orc_geometry.argtypes = [i64, i64, i64, vp, vp, vp, vp, d, vp, vp]
+        lib.orc_geometry_adjoint.argtypes = [i64, i64, i64, vp, vp, vp, vp, d, vp, vp, vp]
         lib.orc_jvp.argtypes = [i64, i64, vp, vp, vp, d, vp, vp, vp]
         lib.orc_edge_jacobian.argtypes = [vp, vp, vp, d, vp, vp]
         lib.orc_adjoint.argtypes = [i64, i64, vp, vp, vp, d, vp, vp, vp]
@@ -169,6 +171,27 @@ def residual2(e2n, q, G, vol, w, dx, gamma=1.4):
     _check(_load().orc_residual2(q.shape[1], w.shape[1], _p(e2n), _p(q), _p(G), _p(vol), _p(w),
                                  _p(dx), gamma, _p(res)), "orc_residual2")
     return res
+
+
+def geometry(e2n, t2n, t2e, xyz, period=1.0):
+    """Median-dual edge weights (3, E) and node volumes (N,) of the tets."""
+    e2n, t2n, t2e, xyz = _c(e2n, np.int32), _c(t2n, np.int32), _c(t2e, np.int32), _c(xyz)
+    N, E, T = xyz.shape[1], e2n.shape[0], t2n.shape[0]
+    w, vol = np.zeros((3, E)), np.zeros(N)
+    _check(_load().orc_geometry(N, E, T, _p(e2n), _p(t2n), _p(t2e), _p(xyz), period, _p(w),
+                                _p(vol)), "orc_geometry")
+    return w, vol
+
+
+def geometry_adjoint(e2n, t2n, t2e, xyz, wbar, volbar, period=1.0):
+    """xbar (3, N) = (dw/dx)^T wbar + (dvol/dx)^T volbar."""
+    e2n, t2n, t2e, xyz = _c(e2n, np.int32), _c(t2n, np.int32), _c(t2e, np.int32), _c(xyz)
+    wbar, volbar = _c(wbar), _c(volbar)
+    N, E, T = xyz.shape[1], e2n.shape[0], t2n.shape[0]
+    xbar = np.zeros((3, N))
+    _check(_load().orc_geometry_adjoint(N, E, T, _p(e2n), _p(t2n), _p(t2e), _p(xyz), period,
+                                        _p(wbar), _p(volbar), _p(xbar)), "orc_geometry_adjoint")
+    return xbar
 
 
 def jvp(e2n, q, w, dq=None, dw=None, gamma=1.4):

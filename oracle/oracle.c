@@ -193,6 +193,142 @@ int orc_residual2(int64_t N, int64_t E, const int32_t *e2n, const double *q, con
     return 0;
 }
 
+/* Median-dual geometry.  Inside a tet (p, q, r, s), the dual face between the
+ * cells of p and q joins the edge midpoint, the centroids of faces pqr and
+ * pqs and the tet centroid; its area vector (half the cross product of the
+ * quadrilateral's diagonals) is (r + s - p - q) x (s - r) / 24, pointing from
+ * p to q when (p, q, r, s) has the orientation of the tet.  For local edge
+ * (a, b) the completing pair (r, s) is chosen so that (a, b, r, s) is an even
+ * permutation of (0, 1, 2, 3).  Each vertex owns a quarter of the tet. */
+static const int GEO_EDGE[6][4] = {{0, 1, 2, 3}, {0, 2, 3, 1}, {0, 3, 1, 2},
+                                   {1, 2, 0, 3}, {1, 3, 2, 0}, {2, 3, 0, 1}};
+
+static void cross(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* The tet's vertex positions, unwrapped to the images nearest vertex 0. */
+static void tet_positions(int64_t N, const int32_t *t2n, int64_t t, const double *xyz,
+                          double period, double x[4][3])
+{
+    for (int v = 0; v < 4; ++v)
+        for (int d = 0; d < 3; ++d) x[v][d] = xyz[(int64_t)d * N + t2n[4 * t + v]];
+    if (period > 0.0)
+        for (int v = 1; v < 4; ++v)
+            for (int d = 0; d < 3; ++d)
+                x[v][d] -= period * round((x[v][d] - x[0][d]) / period);
+}
+
+/* +1 when global edge g runs from local vertex a to local vertex b, -1 when
+ * it runs the other way, 0 when it is not that edge. */
+static double edge_sign(const int32_t *e2n, const int32_t *t2n, int64_t t, int64_t g, int a, int b)
+{
+    int32_t na = t2n[4 * t + a], nb = t2n[4 * t + b];
+    if (e2n[2 * g] == na && e2n[2 * g + 1] == nb) return 1.0;
+    if (e2n[2 * g] == nb && e2n[2 * g + 1] == na) return -1.0;
+    return 0.0;
+}
+
+static int check_tets(int64_t N, int64_t E, int64_t T, const int32_t *t2n, const int32_t *t2e)
+{
+    for (int64_t k = 0; k < 4 * T; ++k)
+        if (t2n[k] < 0 || t2n[k] >= N) return ORC_ERANGE;
+    for (int64_t k = 0; k < 6 * T; ++k)
+        if (t2e[k] < 0 || t2e[k] >= E) return ORC_ERANGE;
+    return 0;
+}
+
+int orc_geometry(int64_t N, int64_t E, int64_t T, const int32_t *e2n, const int32_t *t2n,
+                 const int32_t *t2e, const double *xyz, double period, double *w, double *vol)
+{
+    if (N <= 0 || E <= 0 || T < 0) return ORC_EINVAL;
+    if (check_map(N, E, e2n) || check_tets(N, E, T, t2n, t2e)) return ORC_ERANGE;
+    for (int64_t t = 0; t < T; ++t) {
+        double x[4][3];
+        tet_positions(N, t2n, t, xyz, period, x);
+        for (int k = 0; k < 6; ++k) {
+            const int *L = GEO_EDGE[k];
+            double a[3], b[3], c[3];
+            for (int d = 0; d < 3; ++d) {
+                a[d] = x[L[2]][d] + x[L[3]][d] - x[L[0]][d] - x[L[1]][d];
+                b[d] = x[L[3]][d] - x[L[2]][d];
+            }
+            cross(a, b, c);
+            int64_t g = t2e[6 * t + k];
+            double sg = edge_sign(e2n, t2n, t, g, L[0], L[1]);
+            if (sg == 0.0) return ORC_EINVAL;
+            for (int d = 0; d < 3; ++d) w[(int64_t)d * E + g] += sg * c[d] / 24.0;
+        }
+        double e1[3], e2[3], e3[3], c[3];
+        for (int d = 0; d < 3; ++d) {
+            e1[d] = x[1][d] - x[0][d];
+            e2[d] = x[2][d] - x[0][d];
+            e3[d] = x[3][d] - x[0][d];
+        }
+        cross(e2, e3, c);
+        double V = (e1[0] * c[0] + e1[1] * c[1] + e1[2] * c[2]) / 6.0;
+        for (int v = 0; v < 4; ++v) vol[t2n[4 * t + v]] += 0.25 * V;
+    }
+    return 0;
+}
+
+int orc_geometry_adjoint(int64_t N, int64_t E, int64_t T, const int32_t *e2n, const int32_t *t2n,
+                         const int32_t *t2e, const double *xyz, double period,
+                         const double *wbar, const double *volbar, double *xbar)
+{
+    if (N <= 0 || E <= 0 || T < 0) return ORC_EINVAL;
+    if (check_map(N, E, e2n) || check_tets(N, E, T, t2n, t2e)) return ORC_ERANGE;
+    for (int64_t t = 0; t < T; ++t) {
+        double x[4][3], xb[4][3] = {{0}};
+        tet_positions(N, t2n, t, xyz, period, x);
+        /* c = a x b / 24: abar = b x cbar / 24, bbar = cbar x a / 24 */
+        for (int k = 0; k < 6; ++k) {
+            const int *L = GEO_EDGE[k];
+            int64_t g = t2e[6 * t + k];
+            double sg = edge_sign(e2n, t2n, t, g, L[0], L[1]);
+            if (sg == 0.0) return ORC_EINVAL;
+            double a[3], b[3], cb[3], ab[3], bb[3];
+            for (int d = 0; d < 3; ++d) {
+                a[d] = x[L[2]][d] + x[L[3]][d] - x[L[0]][d] - x[L[1]][d];
+                b[d] = x[L[3]][d] - x[L[2]][d];
+                cb[d] = sg * wbar[(int64_t)d * E + g] / 24.0;
+            }
+            cross(b, cb, ab);
+            cross(cb, a, bb);
+            for (int d = 0; d < 3; ++d) {
+                xb[L[0]][d] -= ab[d];
+                xb[L[1]][d] -= ab[d];
+                xb[L[2]][d] += ab[d] - bb[d];
+                xb[L[3]][d] += ab[d] + bb[d];
+            }
+        }
+        /* V = e1 . (e2 x e3) / 6, e_k = x_k - x_0 */
+        double Vb = 0.0;
+        for (int v = 0; v < 4; ++v) Vb += 0.25 * volbar[t2n[4 * t + v]];
+        double e1[3], e2[3], e3[3], c1[3], c2[3], c3[3];
+        for (int d = 0; d < 3; ++d) {
+            e1[d] = x[1][d] - x[0][d];
+            e2[d] = x[2][d] - x[0][d];
+            e3[d] = x[3][d] - x[0][d];
+        }
+        cross(e2, e3, c1);
+        cross(e3, e1, c2);
+        cross(e1, e2, c3);
+        for (int d = 0; d < 3; ++d) {
+            xb[1][d] += Vb * c1[d] / 6.0;
+            xb[2][d] += Vb * c2[d] / 6.0;
+            xb[3][d] += Vb * c3[d] / 6.0;
+            xb[0][d] -= Vb * (c1[d] + c2[d] + c3[d]) / 6.0;
+        }
+        for (int v = 0; v < 4; ++v)
+            for (int d = 0; d < 3; ++d) xbar[(int64_t)d * N + t2n[4 * t + v]] += xb[v][d];
+    }
+    return 0;
+}
+
 /* Neumaier's compensated summation. */
 typedef struct {
     double s, c;

@@ -68,6 +68,21 @@ int orc_residual2(int64_t N, int64_t E, const int32_t *e2n, const double *q, con
                   const double *vol, const double *w, const double *dx, double gamma,
                   double *res);
 
+/* Median-dual geometry of a tetrahedral mesh: for every tet (t2n[4t..4t+3],
+ * positively oriented) and each of its six local edges, in the order (0,1),
+ * (0,2), (0,3), (1,2), (1,3), (2,3) with global edge t2e[6t + k], the area
+ * vector of the dual face inside the tet is added to w (3E, oriented from the
+ * edge's first to its second node, e2n), and a quarter of the tet's volume to
+ * vol (N) at each vertex.  xyz is 3N; period > 0 unwraps every vertex to the
+ * image nearest vertex 0 in a periodic box of that side. */
+int orc_geometry(int64_t N, int64_t E, int64_t T, const int32_t *e2n, const int32_t *t2n,
+                 const int32_t *t2e, const double *xyz, double period, double *w, double *vol);
+
+/* Reverse of orc_geometry: xbar (3N) += (dw/dx)^T wbar + (dvol/dx)^T volbar. */
+int orc_geometry_adjoint(int64_t N, int64_t E, int64_t T, const int32_t *e2n, const int32_t *t2n,
+                         const int32_t *t2e, const double *xyz, double period,
+                         const double *wbar, const double *volbar, double *xbar);
+
 /* jv[6N] = J (dq, dw): the residual's directional derivative (dual numbers). */
 int orc_jvp(int64_t N, int64_t E, const int32_t *e2n, const double *q, const double *w,
             double gamma, const double *dq, const double *dw, double *jv);

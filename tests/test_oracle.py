@@ -20,7 +20,7 @@ import pytest
 
 import meshgen
 import oracle
-from tests.golden.load import flux_hand_cases
+from tests.golden.load import flux_hand_cases, unit_tet_dual
 
 GAMMA = 1.4
 
@@ -383,6 +383,88 @@ def test_second_order_residual_special_cases(mesh_j):
                          n.reshape(3, 1), d.reshape(3, 1))
     qm = 0.5 * (qi + qj)
     np.testing.assert_allclose(r[:, 0], physical_flux(qm, n), rtol=1e-13, atol=1e-14)
+
+
+def test_geometry_unit_tet_hand_values():
+    xyz = np.array([[0.0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1]])
+    t2n = np.array([[0, 1, 2, 3]], np.int32)
+    pairs = list(meshgen.TET_LOCAL_EDGES)
+    # the map orients edges 1->0 and 2->3 backwards on purpose: signs follow e2n
+    e2n = np.array([[1, 0], [0, 2], [0, 3], [1, 2], [1, 3], [3, 2]], np.int32)
+    t2e = np.arange(6, dtype=np.int32)[None, :]
+    w, vol = oracle.geometry(e2n, t2n, t2e, xyz, period=0.0)
+    ref = unit_tet_dual()
+    for k, (a, b) in enumerate(pairs):
+        sign = 1.0 if (e2n[k, 0], e2n[k, 1]) == (a, b) else -1.0
+        np.testing.assert_allclose(24 * w[:, k], sign * ref[(a, b)], atol=1e-15)
+    np.testing.assert_allclose(vol, np.full(4, 1.0 / 24.0), rtol=1e-15)
+
+
+def test_geometry_closure_volume_and_linear_exactness(mesh_j):
+    m = mesh_j
+    t2n = m.tets()
+    t2e = meshgen.tet_edges(m, t2n)
+    w, vol = oracle.geometry(m.e2n, t2n, t2e, m.xyz)
+    assert vol.sum() == pytest.approx(1.0, rel=1e-13)
+    assert vol.min() > 0
+    # closed dual cells: the face vectors around every node sum to zero
+    S = np.zeros((3, m.N))
+    for d in range(3):
+        np.add.at(S[d], m.e2n[:, 0], w[d])
+        np.add.at(S[d], m.e2n[:, 1], -w[d])
+    assert np.abs(S).max() <= 1e-15
+    # sum over edges at i of n (x) (x_j - x_i), signed toward i's neighbour, = 2 vol_i I
+    dx = meshgen.edge_vectors(m)
+    M = np.zeros((3, 3, m.N))
+    for a in range(3):
+        for b in range(3):
+            f = w[a] * dx[b]
+            np.add.at(M[a, b], m.e2n[:, 0], f)
+            np.add.at(M[a, b], m.e2n[:, 1], f)
+    eye = np.eye(3)[:, :, None] * (2 * vol)[None, None, :]
+    assert np.abs(M - eye).max() <= 1e-14
+
+
+def test_geometry_adjoint_central_differences():
+    m = meshgen.build_mesh(4, 1, 0.25)
+    t2n = m.tets()
+    t2e = meshgen.tet_edges(m, t2n)
+    rng = np.random.default_rng(31)
+    wbar, volbar = rng.normal(size=(3, m.E)), rng.normal(size=m.N)
+    xbar = oracle.geometry_adjoint(m.e2n, t2n, t2e, m.xyz, wbar, volbar)
+
+    def J(x):
+        w, vol = oracle.geometry(m.e2n, t2n, t2e, x)
+        return float((wbar * w).sum() + (volbar * vol).sum())
+
+    for _ in range(3):
+        dx = rng.normal(size=(3, m.N)) * 1e-3
+        h = 1e-3
+        fd = (J(m.xyz + h * dx) - J(m.xyz - h * dx)) / (2 * h)
+        assert float((xbar * dx).sum()) == pytest.approx(fd, rel=1e-8, abs=1e-14)
+
+
+def test_shape_sensitivity_chain_central_differences():
+    """dJ/dx for J = rbar . R(q, w(x)) at fixed q: the flux adjoint gives
+    wbar = (dR/dw)^T rbar, the geometry adjoint carries it to the nodes."""
+    m = meshgen.build_mesh(4, 1, 0.25)
+    t2n = m.tets()
+    t2e = meshgen.tet_edges(m, t2n)
+    q = meshgen.state(m.N, m.perm)
+    rng = np.random.default_rng(32)
+    rbar = rng.normal(size=(6, m.N))
+    w0, _ = oracle.geometry(m.e2n, t2n, t2e, m.xyz)
+    _, wbar = oracle.adjoint(m.e2n, q, w0, rbar)
+    xbar = oracle.geometry_adjoint(m.e2n, t2n, t2e, m.xyz, wbar, np.zeros(m.N))
+
+    def J(x):
+        w, _ = oracle.geometry(m.e2n, t2n, t2e, x)
+        return float((rbar * oracle.residual(m.e2n, q, w)).sum())
+
+    dx = rng.normal(size=(3, m.N)) * 1e-3
+    h = 1e-3
+    fd = (J(m.xyz + h * dx) - J(m.xyz - h * dx)) / (2 * h)
+    assert float((xbar * dx).sum()) == pytest.approx(fd, rel=1e-6)
 
 
 def test_edge_jacobian_vs_central_differences():
