@@ -43,6 +43,9 @@ typedef int32_t opf_dat;
 
 /* map value of a direct argument (OP2's OP_ID) */
 #define OPF_ID (-1)
+/* idx of an argument that reads or increments every column of its map (the
+ * tet loops: all four vertices, all six edges). */
+#define OPF_ALL (-2)
 
 typedef enum {
     OPF_OK = 0,
@@ -74,7 +77,9 @@ typedef enum {
     OPF_K_DT_MIN = 4,        /* direct: global min over nodes of cfl*vol/lambda   */
     OPF_K_LOCAL_DT = 5,      /* direct: per-node step cfl*vol/lambda              */
     OPF_K_EDGE_GRAD = 6,     /* Green-Gauss sums of the state, OP_INC of 18/node  */
-    OPF_K_EDGE_FLUX2 = 7     /* second-order (reconstructed) edge flux, OP_INC    */
+    OPF_K_EDGE_FLUX2 = 7,    /* second-order (reconstructed) edge flux, OP_INC    */
+    OPF_K_GEOMETRY = 8,      /* tets: median-dual edge weights and node volumes  */
+    OPF_K_GEOMETRY_ADJ = 9   /* tets: reverse of GEOMETRY into node coordinates   */
 } opf_kernel;
 
 /* How an indirect (edge) loop resolves its increments. */
@@ -313,6 +318,24 @@ typedef struct {
  *   q_L = q_i + 1/2 (G_i/vol_i).dx_e and q_R = q_j - 1/2 (G_j/vol_j).dx_e,
  *   dx_e = x_j - x_i; WRITE increments with the OWNER variant as above.
  *  In every edge loop the increment target must not be one of the inputs.
+ *  GEOMETRY over tets (ATOMIC variant only):
+ *     (x, ALL, t2n, 3, F64, READ) (w, ALL, t2e, 3, F64, INC)
+ *     (vol, ALL, t2n, 1, F64, INC) gbl (period, 1, F64, READ, host)
+ *   t2n (tets -> nodes, arity 4) lists positively oriented tets; t2e (tets ->
+ *   edges, arity 6) lists their edges in the local order (0,1) (0,2) (0,3)
+ *   (1,2) (1,3) (2,3).  The edge set must have been planned (its edge->node
+ *   map orients each edge).  Each tet adds the area vectors of its six
+ *   median-dual faces, (x_r + x_s - x_p - x_q) x (x_s - x_r) / 24 for local
+ *   edge (p, q) with (p, q, r, s) an even permutation of the vertices, to w
+ *   (signed from the edge's first to its second node) and a quarter of its
+ *   volume to each vertex.  period > 0: vertices are unwrapped to the image
+ *   nearest vertex 0 in a periodic box of that side.  Summation order is not
+ *   fixed (FP64 atomics).
+ *  GEOMETRY_ADJ over tets (ATOMIC): (x, ALL, t2n, 3, READ)
+ *     (wbar, ALL, t2e, 3, READ) (volbar, ALL, t2n, 1, READ)
+ *     (xbar, ALL, t2n, 3, INC) gbl period
+ *   xbar += (dw/dx)^T wbar + (dvol/dx)^T volbar (shape sensitivities when
+ *   wbar is the nbar output of EDGE_FLUX_ADJ).
  *  RK_STAGE over nodes (direct):
  *     (q0,-1,ID,6,T,READ) (res,-1,ID,6,F64,RW) (vol,-1,ID,1,F64,READ)
  *     (q,-1,ID,6,T,WRITE)
@@ -353,6 +376,10 @@ int opf_edge_gradient(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_d
 int opf_edge_flux2(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat G, opf_dat vol,
                    opf_dat n, opf_dat dx, opf_dat res, double gamma, int variant, int res_access,
                    void *stream);
+int opf_geometry(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x, double period,
+                 opf_dat w, opf_dat vol, void *stream);
+int opf_geometry_adjoint(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x,
+                         double period, opf_dat wbar, opf_dat volbar, opf_dat xbar, void *stream);
 int opf_rk_stage(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol, opf_dat q,
                  double alpha_dt, double *ss_dev, int res_access, void *stream);
 int opf_rk_stage_local(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol,

@@ -30,12 +30,14 @@ STATUS = {0: "OPF_OK", -1: "OPF_EINVAL", -2: "OPF_ERANGE", -3: "OPF_ESIZE", -4: 
           -9: "OPF_ENONFINITE", -10: "OPF_EPLAN"}
 F64, F32 = 0, 1
 READ, WRITE, RW, INC, MIN = 0, 1, 2, 3, 4
-K_EDGE_FLUX, K_EDGE_FLUX_ADJ, K_RK_STAGE, K_EDGE_SPECRAD, K_DT_MIN = 0, 1, 2, 3, 4
+(K_EDGE_FLUX, K_EDGE_FLUX_ADJ, K_RK_STAGE, K_EDGE_SPECRAD, K_DT_MIN, K_LOCAL_DT, K_EDGE_GRAD,
+ K_EDGE_FLUX2, K_GEOMETRY, K_GEOMETRY_ADJ) = range(10)
 COLOURED, ATOMIC, OWNER, COLOURED_LDS_ATOMIC, FLAT = 0, 1, 2, 3, 4
 VARIANTS = {"coloured": COLOURED, "atomic": ATOMIC, "owner": OWNER,
             "coloured-lds-atomic": COLOURED_LDS_ATOMIC, "flat": FLAT}
 RENUMBER = {"none": 0, "rcm": 1, "morton": 2}
 ID = -1
+ALL = -2
 
 # Stage coefficients of the 5-stage scheme (low-storage form
 # q_k = q_0 - alpha_k dt res(q_{k-1}) / vol).
@@ -46,7 +48,8 @@ SYMBOLS = ("opf_init", "opf_finalize", "opf_last_error", "opf_set_allocator", "o
            "opf_decl_map", "opf_plan", "opf_get_perm", "opf_plan_view_get", "opf_plan_verify",
            "opf_decl_dat", "opf_par_loop", "opf_edge_flux", "opf_edge_flux_adjoint",
            "opf_edge_specrad", "opf_edge_gradient", "opf_edge_flux2", "opf_rk_stage",
-           "opf_rk_stage_local", "opf_local_dt", "opf_dt_min",
+           "opf_rk_stage_local", "opf_local_dt", "opf_dt_min", "opf_geometry",
+           "opf_geometry_adjoint",
            "opf_sync", "opf_check_finite")
 
 
@@ -151,6 +154,8 @@ def load():
     lib.opf_dt_min.argtypes = [vp, i32, i32, i32, d, vp, vp]
     lib.opf_rk_stage_local.argtypes = [vp, i32, i32, i32, i32, i32, i32, d, vp, ctypes.c_int, vp]
     lib.opf_local_dt.argtypes = [vp, i32, i32, i32, d, i32, vp]
+    lib.opf_geometry.argtypes = [vp, i32, i32, i32, i32, d, i32, i32, vp]
+    lib.opf_geometry_adjoint.argtypes = [vp, i32, i32, i32, i32, d, i32, i32, i32, vp]
     lib.opf_sync.argtypes = [vp, vp]
     lib.opf_check_finite.argtypes = [vp, vp, ctypes.c_int, vp]
     runtimes = _hip_runtimes()
@@ -356,6 +361,18 @@ class Context:
                                             variant, res_access, _stream_ptr(stream, self.device)),
                     "opf_edge_flux2")
 
+    def geometry(self, tets, t2n, t2e, x, w, vol, period=1.0, stream=None):
+        """w (edge dat, 3) and vol (node dat) += median-dual weights and volumes of the tets."""
+        self._check(self.lib.opf_geometry(self._ctx, tets, t2n, t2e, x, float(period), w, vol,
+                                          _stream_ptr(stream, self.device)), "opf_geometry")
+
+    def geometry_adjoint(self, tets, t2n, t2e, x, wbar, volbar, xbar, period=1.0, stream=None):
+        """xbar (node dat, 3) += (dw/dx)^T wbar + (dvol/dx)^T volbar."""
+        self._check(self.lib.opf_geometry_adjoint(self._ctx, tets, t2n, t2e, x, float(period),
+                                                  wbar, volbar, xbar,
+                                                  _stream_ptr(stream, self.device)),
+                    "opf_geometry_adjoint")
+
     def rk_stage(self, nodes, q0, res, vol, q, alpha_dt, ss, res_access=RW, stream=None):
         """ss: float64 device tensor of 6 values, incremented by sum res^2.
         res_access RW zeroes res after use, READ leaves it."""
@@ -402,12 +419,13 @@ class FluxProblem:
 
     def __init__(self, ctx, e2n, w, vol, q, fp32=False, renumber="rcm", block_size=512,
                  colour_sort=False, coords=None, gamma=1.4, index_base=0, like=None,
-                 cluster_size=512, lane_groups=True):
+                 cluster_size=512, lane_groups=True, tets=None, tet_edges=None):
         self.ctx, self.gamma, self.fp32 = ctx, float(gamma), fp32
         if like is not None:  # same mesh, sets, map and plan; other dats
             if like.ctx is not ctx:
                 raise ValueError("like= must be a problem on the same context")
-            for k in ("N", "E", "nodes", "edges", "e2n", "info", "node_new", "edge_new"):
+            for k in ("N", "E", "nodes", "edges", "e2n", "info", "node_new", "edge_new", "tets",
+                      "t2n", "t2e"):
                 setattr(self, k, getattr(like, k))
         else:
             e2n = np.ascontiguousarray(e2n, dtype=np.int32)
@@ -415,6 +433,14 @@ class FluxProblem:
             self.nodes = ctx.decl_set(self.N, "nodes")
             self.edges = ctx.decl_set(self.E, "edges")
             self.e2n = ctx.decl_map(self.edges, self.nodes, 2, e2n, index_base, "e2n")
+            self.tets = self.t2n = self.t2e = None
+            if tets is not None:  # tet maps must exist before the plan renumbers the sets
+                tets = np.ascontiguousarray(tets, dtype=np.int32)
+                self.tets = ctx.decl_set(tets.shape[0], "tets")
+                self.t2n = ctx.decl_map(self.tets, self.nodes, 4, tets, index_base, "t2n")
+                self.t2e = ctx.decl_map(self.tets, self.edges, 6,
+                                        np.ascontiguousarray(tet_edges, dtype=np.int32),
+                                        index_base, "t2e")
             self.info = ctx.plan(self.e2n, renumber=renumber, block_size=block_size,
                                  colour_sort=colour_sort, coords=coords,
                                  cluster_size=cluster_size, lane_groups=lane_groups)
@@ -482,6 +508,35 @@ class FluxProblem:
             self.ctx.rk_stage(self.nodes, qa, self.res_d, self.vol, qb, RK_ALPHA[k] * dt,
                               self.ss[k], rk, stream)
         self.qa, self.qb = self.qb, self.qa
+
+    def geometry(self, x_t, w_t, vol_t, period=1.0, stream=None):
+        """w_t (3, E) and vol_t (N,) += weights and volumes of the tets at node
+        coordinates x_t (3, N); all internal numbering, FP64."""
+        self.ctx.geometry(self.tets, self.t2n, self.t2e, self.dat(x_t, "x"),
+                          self.dat(w_t, "w", edges=True), self.dat(vol_t[None], "vol_out"),
+                          period, stream)
+
+    def geometry_adjoint(self, x_t, wbar_t, volbar_t, xbar_t, period=1.0, stream=None):
+        self.ctx.geometry_adjoint(self.tets, self.t2n, self.t2e, self.dat(x_t, "x"),
+                                  self.dat(wbar_t, "wbar", edges=True),
+                                  self.dat(volbar_t[None], "volbar"), self.dat(xbar_t, "xbar"),
+                                  period, stream)
+
+    def shape_gradient(self, x_t, rbar_t, period=1.0, variant=COLOURED, stream=None):
+        """d(rbar . R(q, w(x)))/dx at the current state (FP64): the flux adjoint
+        gives the weight sensitivities, the geometry reverse carries them to the
+        node coordinates.  Returns xbar (3, N), internal numbering."""
+        dev = self.ctx.torch_device
+        qbar = torch.zeros((6, self.N), dtype=torch.float64, device=dev)
+        nbar = torch.empty((3, self.E), dtype=torch.float64, device=dev)
+        self.ctx.edge_flux_adjoint(self.edges, self.e2n, self.dat(self.qa, "q"), self.w,
+                                   self.dat(rbar_t, "rbar"), self.dat(qbar, "qbar"),
+                                   self.dat(nbar, "nbar", edges=True), self.gamma, variant, INC,
+                                   stream)
+        xbar = torch.zeros((3, self.N), dtype=torch.float64, device=dev)
+        volbar = torch.zeros(self.N, dtype=torch.float64, device=dev)
+        self.geometry_adjoint(x_t, nbar, volbar, xbar, period, stream)
+        return xbar
 
     def set_edge_vectors(self, dx):
         """Edge vectors x_j - x_i (3, E), user numbering, for the second-order loop."""

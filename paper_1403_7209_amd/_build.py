@@ -31,7 +31,7 @@ def build(verbose=False):
     o = os.path.join(BUILD, "planner.o")
     _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "planner.cpp"), "-o", o], verbose)
     objs.append(o)
-    for src in ("opflux.cpp", "kernels.hip"):
+    for src in ("opflux.cpp", "kernels.hip", "geometry.hip"):
         o = os.path.join(BUILD, src.split(".")[0] + ".o")
         _run([hipcc, *HIP_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)

@@ -83,6 +83,19 @@ int launch_rk_stage(bool fp32, int N, const NodeArrays &a, double alpha_dt, doub
 int launch_dt_min(int N, const double *vol, const double *lam, double cfl, double *dt,
                   double *partial, hipStream_t stream);
 
+// Tet loops (one thread per tet, FP64 atomics).  t2n [4T] and t2e [6T] in
+// internal numbering; e2n orients the edges.  Pointers are SoA components.
+struct TetArrays {
+    const int *t2n = nullptr;
+    const int *t2e = nullptr;
+    const int2 *e2n = nullptr;
+    const double *x[3] = {};
+    double *w[3] = {};      // GEOMETRY: weights (INC); ADJ: wbar (read)
+    double *vol = nullptr;  // GEOMETRY: volumes (INC); ADJ: volbar (read)
+    double *xbar[3] = {};   // ADJ only
+};
+int launch_geometry(bool adjoint, int T, const TetArrays &a, double period, hipStream_t stream);
+
 // dt[i] = cfl * vol[i] / lam[i].
 int launch_local_dt(int N, const double *vol, const double *lam, double cfl, double *dt,
                     hipStream_t stream);

@@ -58,6 +58,12 @@ size_t type_size(int t) { return t == OPF_F32 ? 4 : 8; }
 
 }  // namespace
 
+// Device copy of a map in internal numbering (tet loops), keyed by map.
+struct DevMap {
+    uint64_t version = 0;
+    int32_t *ptr = nullptr;
+};
+
 struct opf_ctx {
     int device = -1;
     std::string err;
@@ -65,6 +71,7 @@ struct opf_ctx {
     std::vector<MapRec> maps;
     std::vector<DatRec> dats;
     std::map<int, std::unique_ptr<PlanRec>> plans;
+    std::map<int, DevMap> dmaps;
     void *(*alloc_fn)(void *, size_t) = nullptr;
     void (*free_fn)(void *, void *) = nullptr;
     void *alloc_user = nullptr;
@@ -391,6 +398,109 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
     return OPF_OK;
 }
 
+// Internal label of every user element of set s (identity if not renumbered).
+const std::vector<int32_t> *set_perm(const opf_ctx *ctx, opf_set s)
+{
+    const SetRec &sr = ctx->sets[s];
+    if (sr.plan_map < 0) return nullptr;
+    auto it = ctx->plans.find(sr.plan_map);
+    if (it == ctx->plans.end()) return nullptr;
+    const MapRec &m = ctx->maps[sr.plan_map];
+    return s == m.to ? &it->second->host.node_new : &it->second->host.edge_new;
+}
+
+// The map's entries in the internal numbering of both sets, on the device
+// (uploaded once per map version).
+int device_map(opf_ctx *ctx, opf_map m, const int32_t *&out)
+{
+    const MapRec &mr = ctx->maps[m];
+    DevMap &dm = ctx->dmaps[m];
+    if (dm.ptr && dm.version == mr.version) {
+        out = dm.ptr;
+        return OPF_OK;
+    }
+    const int64_t nfrom = ctx->sets[mr.from].size;
+    const std::vector<int32_t> *pf = set_perm(ctx, mr.from), *pt = set_perm(ctx, mr.to);
+    std::vector<int32_t> v((size_t)nfrom * mr.dim);
+    for (int64_t r = 0; r < nfrom; ++r) {
+        const int64_t row = pf ? (*pf)[r] : r;
+        for (int k = 0; k < mr.dim; ++k) {
+            const int32_t x = mr.idx[(size_t)r * mr.dim + k];
+            v[(size_t)row * mr.dim + k] = pt ? (*pt)[x] : x;
+        }
+    }
+    ctx->dfree(dm.ptr);
+    dm.ptr = static_cast<int32_t *>(ctx->dalloc(v.size() * sizeof(int32_t)));
+    if (!dm.ptr) return ctx->fail(OPF_ENOMEM, "device allocation of a map failed");
+    hipError_t e = hipMemcpy(dm.ptr, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "map upload");
+    dm.version = mr.version;
+    out = dm.ptr;
+    return OPF_OK;
+}
+
+int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args, int ngbl,
+             const opf_gbl *gbls, int variant, hipStream_t st)
+{
+    const bool adj = kernel == OPF_K_GEOMETRY_ADJ;
+    const int want_args = adj ? 4 : 3;
+    if (nargs != want_args || !args)
+        return ctx->fail(OPF_EINVAL, "expected " + std::to_string(want_args) + " arguments");
+    if (ngbl != 1 || !gbls) return ctx->fail(OPF_EINVAL, "expected one global (period)");
+    if (variant != OPF_V_ATOMIC) return ctx->fail(OPF_EINVAL, "the tet loops run as ATOMIC only");
+    const opf_map t2n = args[0].map, t2e = args[1].map;
+    if (!ctx->map_ok(t2n) || !ctx->map_ok(t2e)) return ctx->fail(OPF_EINVAL, "invalid map");
+    const MapRec &mn = ctx->maps[t2n], &me = ctx->maps[t2e];
+    if (mn.from != s || mn.dim != 4) return ctx->fail(OPF_EINVAL, "t2n must map the loop set, arity 4");
+    if (me.from != s || me.dim != 6) return ctx->fail(OPF_EINVAL, "t2e must map the loop set, arity 6");
+    const opf_set nodes = mn.to, edges = me.to;
+    const int eplan = ctx->sets[edges].plan_map;
+    if (eplan < 0 || ctx->maps[eplan].from != edges || ctx->maps[eplan].to != nodes)
+        return ctx->fail(OPF_ESTATE, "the edge set needs a plan of its edge->node map");
+    std::vector<Want> w = {{nodes, OPF_ALL, t2n, 3, OPF_F64, OPF_READ},
+                           {edges, OPF_ALL, t2e, 3, OPF_F64, adj ? OPF_READ : OPF_INC},
+                           {nodes, OPF_ALL, t2n, 1, OPF_F64, adj ? OPF_READ : OPF_INC}};
+    if (adj) w.push_back({nodes, OPF_ALL, t2n, 3, OPF_F64, OPF_INC});
+    int rc = OPF_OK;
+    for (int k = 0; k < nargs && !rc; ++k) rc = check_arg(ctx, args[k], w[k], k);
+    if (!rc) rc = check_gbl(ctx, gbls[0], 1, OPF_READ, 0, 0);
+    if (rc) return rc;
+    const int out0 = adj ? 3 : 1;
+    for (int k = out0; k < nargs; ++k)
+        for (int j = 0; j < out0; ++j)
+            if (args[k].dat == args[j].dat)
+                return ctx->fail(OPF_EINVAL, "an incremented argument aliases an input");
+    const double period = *static_cast<const double *>(gbls[0].ptr);
+    if (!(period >= 0.0)) return ctx->fail(OPF_EINVAL, "period must be >= 0");
+    auto it = ctx->plans.find(eplan);
+    if (it == ctx->plans.end()) return ctx->fail(OPF_ESTATE, "no plan for the edge map");
+    if (it->second->map_version != ctx->maps[eplan].version)
+        return ctx->fail(OPF_ESTATE, "the edge map's plan is stale");
+    rc = device_ready(ctx);
+    if (rc) return rc;
+    if (!it->second->on_device) return ctx->fail(OPF_ESTATE, "plan is not on the device");
+    opf::gpu::TetArrays ta;
+    rc = device_map(ctx, t2n, ta.t2n);
+    if (!rc) rc = device_map(ctx, t2e, ta.t2e);
+    if (rc) return rc;
+    ta.e2n = it->second->dev.e2n;
+    const DatRec &x = ctx->dats[args[0].dat], &wd = ctx->dats[args[1].dat];
+    const DatRec &vd = ctx->dats[args[2].dat];
+    for (int d = 0; d < 3; ++d) {
+        ta.x[d] = static_cast<const double *>(comp(x, d));
+        ta.w[d] = (double *)comp(wd, d);
+    }
+    ta.vol = (double *)comp(vd, 0);
+    if (adj) {
+        const DatRec &xb = ctx->dats[args[3].dat];
+        for (int d = 0; d < 3; ++d) ta.xbar[d] = (double *)comp(xb, d);
+    }
+    const int64_t T = ctx->sets[s].size;
+    int e = opf::gpu::launch_geometry(adj, (int)T, ta, period, st);
+    if (e) return hip_fail(ctx, (hipError_t)e, "tet loop launch");
+    return OPF_OK;
+}
+
 int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args, int ngbl,
                 const opf_gbl *gbls, hipStream_t st)
 {
@@ -504,6 +614,7 @@ int opf_finalize(opf_ctx *ctx)
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
         for (auto &kv : ctx->plans) free_plan(ctx, *kv.second);
+        for (auto &kv : ctx->dmaps) ctx->dfree(kv.second.ptr);
         ctx->dfree(ctx->scratch);
     }
     delete ctx;
@@ -759,6 +870,8 @@ int opf_par_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *
     case OPF_K_RK_STAGE:
     case OPF_K_DT_MIN:
     case OPF_K_LOCAL_DT: return direct_loop(ctx, kernel, s, nargs, args, ngbl, gbls, st);
+    case OPF_K_GEOMETRY:
+    case OPF_K_GEOMETRY_ADJ: return tet_loop(ctx, kernel, s, nargs, args, ngbl, gbls, variant, st);
     default: return ctx->fail(OPF_EINVAL, "unknown kernel");
     }
 }
@@ -852,6 +965,29 @@ int opf_edge_flux2(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat 
                            {res, 1, e2n, 6, OPF_F64, res_access}};
     const opf_gbl g[1] = {{&gamma, 1, OPF_F64, OPF_READ, 0}};
     return opf_par_loop(ctx, OPF_K_EDGE_FLUX2, edges, 10, a, 1, g, variant, stream);
+}
+
+int opf_geometry(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x, double period,
+                 opf_dat w, opf_dat vol, void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    const opf_arg a[3] = {{x, OPF_ALL, t2n, 3, OPF_F64, OPF_READ},
+                          {w, OPF_ALL, t2e, 3, OPF_F64, OPF_INC},
+                          {vol, OPF_ALL, t2n, 1, OPF_F64, OPF_INC}};
+    const opf_gbl g[1] = {{&period, 1, OPF_F64, OPF_READ, 0}};
+    return opf_par_loop(ctx, OPF_K_GEOMETRY, tets, 3, a, 1, g, OPF_V_ATOMIC, stream);
+}
+
+int opf_geometry_adjoint(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x,
+                         double period, opf_dat wbar, opf_dat volbar, opf_dat xbar, void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    const opf_arg a[4] = {{x, OPF_ALL, t2n, 3, OPF_F64, OPF_READ},
+                          {wbar, OPF_ALL, t2e, 3, OPF_F64, OPF_READ},
+                          {volbar, OPF_ALL, t2n, 1, OPF_F64, OPF_READ},
+                          {xbar, OPF_ALL, t2n, 3, OPF_F64, OPF_INC}};
+    const opf_gbl g[1] = {{&period, 1, OPF_F64, OPF_READ, 0}};
+    return opf_par_loop(ctx, OPF_K_GEOMETRY_ADJ, tets, 4, a, 1, g, OPF_V_ATOMIC, stream);
 }
 
 int opf_rk_stage_local(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol,

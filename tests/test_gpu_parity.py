@@ -217,6 +217,42 @@ def test_gradient_and_second_order_flux(small):
         assert report("res2 owner WRITE", normwise(p.nodes_out(res), r2_ref), TOL64)
 
 
+def test_geometry_and_shape_gradient(small):
+    """Median-dual weights and volumes from the tets, their reverse, and the
+    shape-sensitivity chain through the flux adjoint, against the oracle."""
+    name, m, q, _ = small
+    print(f"[geometry {name}]", flush=True)
+    t2n = m.tets()
+    t2e = meshgen.tet_edges(m, t2n)
+    w_ref, vol_ref = oracle.geometry(m.e2n, t2n, t2e, m.xyz)
+    ctx = pk.Context(DEV)
+    p = pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, renumber="morton", coords=m.xyz,
+                       tets=t2n, tet_edges=t2e)
+    x = p.nodes_in(m.xyz)
+    w = torch.zeros((3, m.E), dtype=torch.float64, device=DEV)
+    vol = torch.zeros(m.N, dtype=torch.float64, device=DEV)
+    p.geometry(x, w, vol)
+    p.ctx.sync()
+    assert report("geometry w", normwise(p.nodes_out(w, edges=True), w_ref), TOL64)
+    assert report("geometry vol", normwise(p.nodes_out(vol[None]), vol_ref[None]), TOL64)
+    rng = np.random.default_rng(41)
+    wbar, volbar = rng.normal(size=(3, m.E)), rng.normal(size=m.N)
+    xb_ref = oracle.geometry_adjoint(m.e2n, t2n, t2e, m.xyz, wbar, volbar)
+    xbar = torch.zeros((3, m.N), dtype=torch.float64, device=DEV)
+    p.geometry_adjoint(x, p.nodes_in(wbar, edges=True), p.nodes_in(volbar[None])[0].contiguous(),
+                       xbar)
+    p.ctx.sync()
+    assert report("geometry xbar", normwise(p.nodes_out(xbar), xb_ref), TOL64)
+    # shape sensitivities of rbar . R(q, w(x))
+    rbar = rng.normal(size=(6, m.N))
+    _, nbar = oracle.adjoint(m.e2n, q, m.w, rbar)
+    xs_ref = oracle.geometry_adjoint(m.e2n, t2n, t2e, m.xyz, nbar, np.zeros(m.N))
+    for variant in variants(p):
+        xs = p.shape_gradient(x, p.nodes_in(rbar), variant=variant)
+        p.ctx.sync()
+        assert report(f"shape gradient v{variant}", normwise(p.nodes_out(xs), xs_ref), TOL64)
+
+
 def test_fp32_storage_stage(small):
     name, m, q, _ = small
     q32 = q.astype(np.float32).astype(np.float64)

@@ -331,6 +331,43 @@ def test_loop_argument_checks_without_device():
     assert flux(good) == pk.ESTATE
 
 
+def test_tet_loop_checks_without_device():
+    m = meshgen.build_mesh(4, 1, 0.25)
+    t2n = m.tets()
+    t2e = meshgen.tet_edges(m, t2n)
+    ctx = pk.Context(None)
+    nodes = ctx.decl_set(m.N, "nodes")
+    edges = ctx.decl_set(m.E, "edges")
+    tets = ctx.decl_set(len(t2n), "tets")
+    mp = ctx.decl_map(edges, nodes, 2, m.e2n, 0, "e2n")
+    tn = ctx.decl_map(tets, nodes, 4, t2n, 0, "t2n")
+    te = ctx.decl_map(tets, edges, 6, t2e, 0, "t2e")
+    lib, out = ctx.lib, ctypes.c_int32()
+
+    def dat(s, dim):
+        assert lib.opf_decl_dat(ctx._ctx, s, dim, pk.F64, None, ctx_size[s], b"d",
+                                ctypes.byref(out)) == 0
+        return out.value
+
+    ctx_size = {nodes: m.N, edges: m.E, tets: len(t2n)}
+    x, w, vol, xb = dat(nodes, 3), dat(edges, 3), dat(nodes, 1), dat(nodes, 3)
+    # before the plan the edges have no orientation map on the device
+    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, vol, None) == pk.ESTATE
+    ctx.plan(mp, block_size=256, cluster_size=256)
+    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, vol, None) == pk.EDEVICE
+    assert lib.opf_geometry(ctx._ctx, tets, te, tn, x, 1.0, w, vol, None) == pk.EINVAL  # swapped
+    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, -1.0, w, vol, None) == pk.EINVAL
+    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, x, None) == pk.ESIZE  # vol dim 3
+    assert lib.opf_geometry_adjoint(ctx._ctx, tets, tn, te, x, 1.0, w, vol, xb, None) == pk.EDEVICE
+    assert lib.opf_geometry_adjoint(ctx._ctx, tets, tn, te, x, 1.0, w, vol, x, None) == pk.EINVAL
+    a = (pk.Arg * 3)(pk.Arg(x, pk.ALL, tn, 3, pk.F64, pk.READ), pk.Arg(w, pk.ALL, te, 3, pk.F64, pk.INC),
+                     pk.Arg(vol, pk.ALL, tn, 1, pk.F64, pk.INC))
+    period = ctypes.c_double(1.0)
+    g = (pk.Gbl * 1)(pk.Gbl(ctypes.addressof(period), 1, pk.F64, pk.READ, 0))
+    assert lib.opf_par_loop(ctx._ctx, pk.K_GEOMETRY, tets, 3, a, 1, g, pk.COLOURED, None) == pk.EINVAL
+    assert lib.opf_par_loop(ctx._ctx, pk.K_GEOMETRY, tets, 3, a, 1, g, pk.ATOMIC, None) == pk.EDEVICE
+
+
 def test_finalize_accepts_null_and_init_rejects_bad_device():
     lib = pk.load()
     assert lib.opf_finalize(None) == 0
