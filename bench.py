@@ -14,9 +14,9 @@ inputs resident in HBM.  The roofline entry is the FP64 edge-flux loop,
 priced in algorithmic bytes (32 B per edge: map 8 + weights 24; 96 B per
 node: state read 48 + residual write 48) against 8 TB/s.
 
-After the timed steps it also times, once per form and outside `value`, the
-Green-Gauss gradient loop, the second-order edge loop and the local time-step
-loop (reported under "forms").
+After the timed steps it also times, outside `value`, the Green-Gauss
+gradient loop, the second-order edge loop, the local time-step loop and the
+tet geometry loop with its reverse (reported under "forms").
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES = {  # algorithmic bytes: (per edge, per node)
+BYTES = {  # algorithmic bytes: (per edge, per node[, per tet])
     "fp64": (32, 96),
     "fp32": (20, 72),
     "adjoint": (56, 144),
@@ -43,6 +43,10 @@ BYTES = {  # algorithmic bytes: (per edge, per node)
     "grad": (32, 192),    # map 8 + n 24; q 48 + G 144 (written)
     "flux2": (56, 248),   # map 8 + n 24 + dx 24; q 48 + G 144 + vol 8 + res 48
     "local_dt": (0, 24),  # vol, lam read; dt written
+    # per tet: t2n 16 + t2e 24; per edge: weights written 24; per node: x 24 + vol written 8
+    "geometry": (24, 32, 40),
+    # per tet: maps 40; per edge: wbar 24; per node: x 24 + volbar 8 + xbar written 24
+    "geometry_adj": (24, 56, 40),
 }
 
 
@@ -134,10 +138,13 @@ def main():
 
     ctx = pk.Context(dev)
     t0 = time.perf_counter()
+    t2n = mesh.tets()
+    t2e = meshgen.tet_edges(mesh, t2n)
     p64 = pk.FluxProblem(ctx, mesh.e2n, mesh.w, mesh.vol, q, renumber=args.renumber,
                          block_size=args.block_size, colour_sort=args.colour_sort,
                          coords=mesh.xyz, cluster_size=args.cluster_size,
-                         lane_groups=not args.no_lane_groups)
+                         lane_groups=not args.no_lane_groups, tets=t2n, tet_edges=t2e)
+    T = len(t2n)
     p32 = pk.FluxProblem(ctx, mesh.e2n, mesh.w, mesh.vol, q, fp32=True, like=p64)
     info = p64.info
     log(f"plan: {info['plan_seconds']:.1f} s, nb={info['nblocks']} nc={info['nblock_colours']} "
@@ -240,13 +247,31 @@ def main():
             e = ev()
             if rec:
                 timers.setdefault("local_dt", []).append((d, e))
+    # the geometry loop over the tets and its reverse
+    x = p64.nodes_in(mesh.xyz)
+    wg = torch.empty((3, E), dtype=torch.float64, device=dev)
+    volg = torch.empty(N, dtype=torch.float64, device=dev)
+    xbar = torch.empty((3, N), dtype=torch.float64, device=dev)
+    for rec in (False, True):
+        for _ in range(3 if rec else 1):
+            wg.zero_()
+            volg.zero_()
+            xbar.zero_()
+            a = ev()
+            p64.geometry(x, wg, volg)
+            b = ev()
+            p64.geometry_adjoint(x, nbar, volg, xbar)
+            c = ev()
+            if rec:
+                timers.setdefault("geometry", []).append((a, b))
+                timers.setdefault("geometry_adj", []).append((b, c))
     torch.cuda.synchronize()
 
     per = {}
     for k, lst in timers.items():
         ms = float(np.mean([a.elapsed_time(b) for a, b in lst]))
-        be, bn = BYTES[k]
-        gbs = (be * E + bn * N) / (ms * 1e-3) / 1e9
+        be, bn, bt = (*BYTES[k], 0)[:3]
+        gbs = (be * E + bn * N + bt * T) / (ms * 1e-3) / 1e9
         per[k] = {"ms": round(ms, 4), "algorithmic_GBs": round(gbs, 1),
                   "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
         if be:
