@@ -62,7 +62,7 @@ class OpfError(RuntimeError):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("renumber", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("colour_sort", ctypes.c_int32), ("cluster_size", ctypes.c_int32),
-                ("lane_groups", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("lane_groups", ctypes.c_int32), ("owner_compact", ctypes.c_int32),
                 ("coords", ctypes.c_void_p)]
 
 
@@ -74,7 +74,8 @@ class PlanInfo(ctypes.Structure):
                 ("bandwidth_after", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("nclusters", ctypes.c_int64),
                 ("owner_edge_visits", ctypes.c_int64), ("max_cluster_segments", ctypes.c_int32),
-                ("owner_ok", ctypes.c_int32), ("flat_colours", ctypes.c_int32),
+                ("owner_ok", ctypes.c_int32), ("owner_compact", ctypes.c_int32),
+                ("flat_colours", ctypes.c_int32),
                 ("flat_ok", ctypes.c_int32)]
 
 
@@ -229,10 +230,11 @@ class Context:
         return out.value
 
     def plan(self, m, renumber="rcm", block_size=512, colour_sort=False, coords=None,
-             cluster_size=512, lane_groups=True):
+             cluster_size=512, lane_groups=True, owner_compact=False):
         c = None if coords is None else np.ascontiguousarray(coords, dtype=np.float64)
         opts = PlanOpts(RENUMBER[renumber], block_size, 1 if colour_sort else 0, cluster_size,
-                        1 if lane_groups else 0, 0, None if c is None else c.ctypes.data)
+                        1 if lane_groups else 0, 1 if owner_compact else 0,
+                        None if c is None else c.ctypes.data)
         info = PlanInfo()
         self._check(self.lib.opf_plan(self._ctx, m, ctypes.byref(opts), ctypes.byref(info)),
                     "opf_plan")
@@ -419,7 +421,8 @@ class FluxProblem:
 
     def __init__(self, ctx, e2n, w, vol, q, fp32=False, renumber="rcm", block_size=512,
                  colour_sort=False, coords=None, gamma=1.4, index_base=0, like=None,
-                 cluster_size=512, lane_groups=True, tets=None, tet_edges=None):
+                 cluster_size=512, lane_groups=True, tets=None, tet_edges=None,
+                 owner_compact=False):
         self.ctx, self.gamma, self.fp32 = ctx, float(gamma), fp32
         if like is not None:  # same mesh, sets, map and plan; other dats
             if like.ctx is not ctx:
@@ -443,7 +446,8 @@ class FluxProblem:
                                         index_base, "t2e")
             self.info = ctx.plan(self.e2n, renumber=renumber, block_size=block_size,
                                  colour_sort=colour_sort, coords=coords,
-                                 cluster_size=cluster_size, lane_groups=lane_groups)
+                                 cluster_size=cluster_size, lane_groups=lane_groups,
+                                 owner_compact=owner_compact)
             self.node_new = ctx.get_perm(self.nodes, self.N)
             self.edge_new = ctx.get_perm(self.edges, self.E)
         dev = ctx.torch_device

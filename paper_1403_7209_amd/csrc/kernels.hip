@@ -346,7 +346,21 @@ struct OwnerPtrs {
     const int2 *prim;     // [ncl] (first edge, count) of the cluster's contiguous range
     const int *sec_off;   // [ncl+1]
     const int *sec_eid;   // the cluster's other edges
+    const uint32_t *pmap; // compact words of the contiguous range (by edge)
+    const int2 *smap;     // (edge, compact word) of the listed edges
+    const int *nb_off;    // [ncl+1] neighbour-cluster tables
+    const int *nb;
 };
+
+// Endpoints of an edge from its compact visit word (see DevPlan): the owned
+// end at v0 + offset, the other end in this cluster or in neighbour slot nb[s].
+__device__ __forceinline__ int2 visit_ends(uint32_t v, int v0, int K, const int *nb)
+{
+    const int go = v0 + (int)(v & 1023u);
+    const int off = (int)(v >> 20);
+    const int gx = (v & 0x800u) ? nb[(v >> 12) & 255u] * K + off : v0 + off;
+    return (v & 0x400u) ? make_int2(gx, go) : make_int2(go, gx);
+}
 
 template <typename T>
 struct Arrays {
@@ -620,7 +634,7 @@ __global__ __launch_bounds__(256) void k_edge_flat(const int2 *__restrict__ e2n,
 // writes its nodes' totals once.
 __host__ __device__ constexpr int owner_acc_rows(int K) { return K; }
 
-template <typename T, class Op, int NT>
+template <typename T, class Op, int NT, bool COMPACT>
 __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>::WAVES : 1)) void k_edge_owner(
     OwnerPtrs p, Arrays<T> a, T gamma, int N, int K, int ncl, int remap, int overwrite)
 {
@@ -636,6 +650,13 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
     const int2 pr = p.prim[c];
     const int sb = p.sec_off[c];
     const int total = pr.y + (p.sec_off[c + 1] - sb);
+    [[maybe_unused]] const int *nbt = nullptr;
+    if constexpr (COMPACT) {
+        __shared__ int s_nb[kCompactMaxNeighbours];
+        const int n0 = p.nb_off[c], nn = p.nb_off[c + 1] - n0;
+        for (int t = threadIdx.x; t < nn; t += NT) s_nb[t] = p.nb[n0 + t];
+        nbt = s_nb;
+    }
     // stage the owned nodes (contiguous ids: coalesced), clear the accumulator
     for (int v = threadIdx.x; v < nown; v += NT) {
         T rec[Op::NS];
@@ -649,24 +670,41 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
     for (int k0 = threadIdx.x; k0 < total; k0 += NT * B) {
         // resolve B edges and issue all their global loads first
         int eid[B];
+        int2 ij[B];
+        [[maybe_unused]] uint32_t wd[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int k = k0 + b * NT;
             eid[b] = -1;
-            if (k < pr.y)
-                eid[b] = pr.x + k;
-            else if (k < total)
-                eid[b] = ld(p.sec_eid, sb + (k - pr.y));
+            if constexpr (COMPACT) {
+                if (k < pr.y) {
+                    eid[b] = pr.x + k;
+                    wd[b] = ld(p.pmap, eid[b]);
+                } else if (k < total) {
+                    const int2 sv = ld(p.smap, sb + (k - pr.y));
+                    eid[b] = sv.x;
+                    wd[b] = (uint32_t)sv.y;
+                }
+            } else {
+                if (k < pr.y)
+                    eid[b] = pr.x + k;
+                else if (k < total)
+                    eid[b] = ld(p.sec_eid, sb + (k - pr.y));
+            }
         }
-        int2 ij[B];
         T w[B][Op::NW];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             if (eid[b] >= 0) {
-                ij[b] = ld(p.e2n, eid[b]);
+                if constexpr (!COMPACT) ij[b] = ld(p.e2n, eid[b]);
 #pragma unroll
                 for (int d = 0; d < Op::NW; ++d) w[b][d] = ld(a.w[d], eid[b]);
             }
+        }
+        if constexpr (COMPACT) {
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (eid[b] >= 0) ij[b] = visit_ends(wd[b], v0, K, nbt);
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -896,9 +934,15 @@ int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t s
 {
     if (!P.owner_ok || P.ncl <= 0) return (int)hipErrorInvalidValue;
     const size_t lds = owner_dyn_lds<T, Op>(P.K);
-    const OwnerPtrs op{P.e2n, P.prim, P.sec_off, P.sec_eid};
-    hipLaunchKernelGGL((k_edge_owner<T, Op, kOwnerThreads>), dim3(P.ncl), dim3(kOwnerThreads), lds,
-                       st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
+    const OwnerPtrs op{P.e2n, P.prim, P.sec_off, P.sec_eid, P.pmap, P.smap, P.nbr_off, P.nbr};
+    if (P.compact && lo.compact)
+        hipLaunchKernelGGL((k_edge_owner<T, Op, kOwnerThreads, true>), dim3(P.ncl),
+                           dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
+                           lo.xcd_remap, lo.overwrite);
+    else
+        hipLaunchKernelGGL((k_edge_owner<T, Op, kOwnerThreads, false>), dim3(P.ncl),
+                           dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
+                           lo.xcd_remap, lo.overwrite);
     return (int)hipGetLastError();
 }
 
@@ -951,17 +995,28 @@ int raise_all(size_t bytes)
     int rc = raise_coloured<T, Op, false>(bytes);
     if (!rc) rc = raise_coloured<T, Op, true>(bytes);
     if (!rc)
-        rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads>), bytes);
+        rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, false>),
+                       bytes);
+    if (!rc)
+        rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, true>),
+                       bytes);
     return rc;
 }
 
-size_t owner_lds_bytes(int op, bool fp32, int K)
+size_t owner_dyn_lds_bytes(int op, bool fp32, int K)
 {
     if (op == OP_ADJOINT) return owner_dyn_lds<double, OpAdjoint>(K);
     if (op == OP_GRAD) return owner_dyn_lds<double, OpGrad>(K);
     if (op == OP_FLUX2) return owner_dyn_lds<double, OpFlux2>(K);
     if (op == OP_SPECRAD) return fp32 ? owner_dyn_lds<float, OpSpecrad>(K) : owner_dyn_lds<double, OpSpecrad>(K);
     return fp32 ? owner_dyn_lds<float, OpFlux>(K) : owner_dyn_lds<double, OpFlux>(K);
+}
+
+// Dynamic LDS of an owner workgroup; the compact form adds a static table of
+// kCompactMaxNeighbours ints, which the limits below include.
+size_t owner_lds_bytes(int op, bool fp32, int K)
+{
+    return owner_dyn_lds_bytes(op, fp32, K) + sizeof(int) * kCompactMaxNeighbours;
 }
 
 }  // namespace

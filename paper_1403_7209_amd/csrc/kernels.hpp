@@ -14,6 +14,8 @@ enum EdgeOpKind { OP_FLUX = 0, OP_ADJOINT = 1, OP_SPECRAD = 2, OP_GRAD = 3, OP_F
 constexpr int kMaxNodeIn = 25;   // node inputs of one edge loop (q, G, vol)
 constexpr int kMaxNodeOut = 18;  // node increments (Green-Gauss sums)
 constexpr int kMaxEdgeIn = 6;    // direct edge inputs (n, dx)
+constexpr int kCompactMaxK = 1024;       // cluster size limit of the compact visit words
+constexpr int kCompactMaxNeighbours = 256;
 
 // Execution variants of an edge loop (values match opf_variant).
 enum Variant { V_COLOURED = 0, V_ATOMIC = 1, V_OWNER = 2, V_COLOURED_LDS_ATOMIC = 3, V_FLAT = 4 };
@@ -39,6 +41,14 @@ struct DevPlan {
     const int2 *prim = nullptr;    // [ncl]
     const int *sec_off = nullptr;  // [ncl+1]
     const int *sec_eid = nullptr;  // [sec_off[ncl]]
+    // Compact visit words (K <= 1024, at most 256 neighbour clusters each):
+    // own offset (10 bits) | own is the second end (1) | other end foreign (1)
+    // | neighbour slot (8) | other end's offset in its cluster (10).
+    bool compact = false;
+    const uint32_t *pmap = nullptr;  // [E] word of each edge for the cluster of its smaller end
+    const int2 *smap = nullptr;      // [sec_off[ncl]] (edge, word) of the listed visits
+    const int *nbr_off = nullptr;    // [ncl+1]
+    const int *nbr = nullptr;        // neighbour clusters of each cluster, by slot
     // flat colouring: colour c runs edges flat_eid[flat_off[c] .. flat_off[c+1])
     int nflat = 0;
     std::vector<int64_t> flat_off;  // host copy [nflat+1]
@@ -57,6 +67,7 @@ struct EdgeArrays {
 struct LaunchOpts {
     int xcd_remap = 1;  // give each XCD a contiguous range of partitions/clusters
     int overwrite = 0;  // owner variant: res = sum instead of res += sum
+    int compact = 1;    // owner variant: compact visit words when the plan has them
 };
 
 // Returns 0 or a hipError_t value.

@@ -25,12 +25,13 @@ ALL_VARIANTS = (pk.COLOURED, pk.ATOMIC, pk.OWNER, pk.COLOURED_LDS_ATOMIC, pk.FLA
 
 
 def problem(m, q, fp32=False, renumber="rcm", block_size=512, colour_sort=False,
-            cluster_size=512, lane_groups=True):
+            cluster_size=512, lane_groups=True, owner_compact=False):
     ctx = pk.Context(DEV)
     coords = m.xyz if renumber == "morton" else None
     return pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, fp32=fp32, renumber=renumber,
                           block_size=block_size, colour_sort=colour_sort, coords=coords,
-                          cluster_size=cluster_size, lane_groups=lane_groups)
+                          cluster_size=cluster_size, lane_groups=lane_groups,
+                          owner_compact=owner_compact)
 
 
 def variants(p):
@@ -76,17 +77,21 @@ def small(request):
     return request.param, m, q, res
 
 
-@pytest.mark.parametrize("renumber,bs,csort,K,lg", [("rcm", 512, False, 512, True),
-                                                    ("rcm", 64, True, 64, True),
-                                                    ("morton", 2048, False, 1024, False),
-                                                    ("morton", 256, False, 0, False),
-                                                    ("none", 256, False, 128, True)])
-def test_residual_small(small, renumber, bs, csort, K, lg):
+@pytest.mark.parametrize("renumber,bs,csort,K,lg,compact", [("rcm", 512, False, 512, True, True),
+                                                            ("rcm", 512, False, 512, True, False),
+                                                            ("rcm", 64, True, 64, True, True),
+                                                            ("morton", 2048, False, 1024, False, True),
+                                                            ("morton", 256, False, 0, False, True),
+                                                            ("none", 256, False, 128, True, True),
+                                                            ("none", 256, False, 64, True, False)])
+def test_residual_small(small, renumber, bs, csort, K, lg, compact):
     name, m, q, ref = small
-    print(f"[residual {name} {renumber} bs={bs} sort={csort} K={K} groups={lg}]", flush=True)
+    print(f"[residual {name} {renumber} bs={bs} sort={csort} K={K} groups={lg} compact={compact}]",
+          flush=True)
     p = problem(m, q, renumber=renumber, block_size=bs, colour_sort=csort, cluster_size=K,
-                lane_groups=lg)
+                lane_groups=lg, owner_compact=compact)
     assert p.info["owner_ok"] == (K > 0)
+    assert p.info["owner_compact"] == (K > 0 and compact)
     for variant in variants(p):
         res = gpu_residual(p, variant)
         assert report(f"variant {variant}", normwise(res, ref), TOL64)
