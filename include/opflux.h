@@ -161,6 +161,11 @@ typedef struct {
                               (when every cluster has <= 256 neighbour clusters
                               and cluster_size <= 1024) instead of the 8-byte
                               edge map: 7 % less traffic, no faster on MI355X  */
+    int32_t bank_spread;   /* 1: place the visits of every 64-lane wavefront of
+                              the OWNER variant so that their LDS words fall in
+                              distinct banks as far as possible, and choose
+                              which end each lane updates first              */
+    int32_t pad;
     const double *coords;  /* host, SoA 3 x to.size; required for MORTON          */
 } opf_plan_opts;
 
@@ -194,7 +199,7 @@ typedef struct {
  * the upload is done).  The plan renumbers both sets: afterwards every dat on
  * them must be in internal numbering.  A set can be renumbered by one plan only.
  * `opts` NULL means RCM, block_size 512, no colour sort, cluster_size 512,
- * lane groups on.
+ * lane groups on, bank spreading on.
  * `info` may be NULL.
  * Errors: OPF_EINVAL (dim != 2, self-loop edge, bad options), OPF_ESTATE (a set
  * already renumbered by another plan), OPF_ENOMEM, OPF_EDEVICE, OPF_EPLAN. */
@@ -236,6 +241,8 @@ typedef struct {
     int64_t nflat_colours;
     const int64_t *flat_offsets;  /* [nflat_colours+1]                          */
     const int32_t *flat_edges;    /* [E]                                        */
+    const uint8_t *owner_swap;    /* [E] 1: the OWNER kernel updates the edge's
+                                     second end first; NULL without bank spreading */
 } opf_plan_view;
 
 int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out);

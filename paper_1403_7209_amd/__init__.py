@@ -63,6 +63,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("renumber", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("colour_sort", ctypes.c_int32), ("cluster_size", ctypes.c_int32),
                 ("lane_groups", ctypes.c_int32), ("owner_compact", ctypes.c_int32),
+                ("bank_spread", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("coords", ctypes.c_void_p)]
 
 
@@ -92,7 +93,7 @@ class PlanView(ctypes.Structure):
                 ("cluster_seg_len", ctypes.c_void_p), ("cluster_range", ctypes.c_void_p),
                 ("cluster_list_offsets", ctypes.c_void_p), ("cluster_list_edges", ctypes.c_void_p),
                 ("nflat_colours", ctypes.c_int64), ("flat_offsets", ctypes.c_void_p),
-                ("flat_edges", ctypes.c_void_p)]
+                ("flat_edges", ctypes.c_void_p), ("owner_swap", ctypes.c_void_p)]
 
 
 class PlanReport(ctypes.Structure):
@@ -230,11 +231,11 @@ class Context:
         return out.value
 
     def plan(self, m, renumber="rcm", block_size=512, colour_sort=False, coords=None,
-             cluster_size=512, lane_groups=True, owner_compact=False):
+             cluster_size=512, lane_groups=True, owner_compact=False, bank_spread=True):
         c = None if coords is None else np.ascontiguousarray(coords, dtype=np.float64)
         opts = PlanOpts(RENUMBER[renumber], block_size, 1 if colour_sort else 0, cluster_size,
                         1 if lane_groups else 0, 1 if owner_compact else 0,
-                        None if c is None else c.ctypes.data)
+                        1 if bank_spread else 0, 0, None if c is None else c.ctypes.data)
         info = PlanInfo()
         self._check(self.lib.opf_plan(self._ctx, m, ctypes.byref(opts), ctypes.byref(info)),
                     "opf_plan")
@@ -287,7 +288,9 @@ class Context:
                     flat_offsets=arr(v.flat_offsets, ctypes.c_int64, v.nflat_colours + 1,
                                      np.int64) if v.nflat_colours else None,
                     flat_edges=arr(v.flat_edges, ctypes.c_int32, E, np.int32)
-                    if v.nflat_colours else None)
+                    if v.nflat_colours else None,
+                    owner_swap=arr(v.owner_swap, ctypes.c_uint8, E, np.uint8)
+                    if v.owner_swap else None)
 
     def plan_verify(self, m):
         rep = PlanReport()
@@ -422,7 +425,7 @@ class FluxProblem:
     def __init__(self, ctx, e2n, w, vol, q, fp32=False, renumber="rcm", block_size=512,
                  colour_sort=False, coords=None, gamma=1.4, index_base=0, like=None,
                  cluster_size=512, lane_groups=True, tets=None, tet_edges=None,
-                 owner_compact=False):
+                 owner_compact=False, bank_spread=True):
         self.ctx, self.gamma, self.fp32 = ctx, float(gamma), fp32
         if like is not None:  # same mesh, sets, map and plan; other dats
             if like.ctx is not ctx:
@@ -447,7 +450,7 @@ class FluxProblem:
             self.info = ctx.plan(self.e2n, renumber=renumber, block_size=block_size,
                                  colour_sort=colour_sort, coords=coords,
                                  cluster_size=cluster_size, lane_groups=lane_groups,
-                                 owner_compact=owner_compact)
+                                 owner_compact=owner_compact, bank_spread=bank_spread)
             self.node_new = ctx.get_perm(self.nodes, self.N)
             self.edge_new = ctx.get_perm(self.edges, self.E)
         dev = ctx.torch_device

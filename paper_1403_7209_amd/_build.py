@@ -15,7 +15,7 @@ ARCH = "gfx950"
 # Packed FP32 instructions are switched off for every HIP translation unit.
 HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", f"-I{INC}"]
-CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall", "-Wextra", f"-I{INC}"]
+CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-pthread", "-Wall", "-Wextra", f"-I{INC}"]
 
 
 def _run(cmd, verbose):
@@ -37,7 +37,7 @@ def build(verbose=False):
         objs.append(o)
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
-          f"-L{os.path.join(ROCM, 'lib')}", "-lamdhip64"], verbose)
+          f"-L{os.path.join(ROCM, 'lib')}", "-lamdhip64", "-pthread"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

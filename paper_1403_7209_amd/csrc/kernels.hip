@@ -709,6 +709,9 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             if (eid[b] < 0) continue;
+            // bit 31 of the second end: update that end first (bank spreading)
+            const bool swp = ij[b].y < 0;
+            ij[b].y &= 0x7fffffff;
             const int li = ij[b].x - v0, lj = ij[b].y - v0;
             const bool oi = (unsigned)li < (unsigned)nown, oj = (unsigned)lj < (unsigned)nown;
             T si[Op::NS], sj[Op::NS];
@@ -723,12 +726,14 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
             double y[NY];
             double wo[3] = {0.0, 0.0, 0.0};
             Op::edge(si, sj, w[b], gamma, y, y + (NY - Op::NOUT), wo);
+            const int la = swp ? lj : li, lb = swp ? li : lj;
+            const bool oa = swp ? oj : oi, ob = swp ? oi : oj;
 #pragma unroll
             for (int v = 0; v < Op::NOUT; ++v) {
                 const double yi = y[v];
                 const double yj = Op::MODE == ANTI ? -yi : Op::MODE == SAME ? yi : y[Op::NOUT + v];
-                if (oi) lds_add(&sy[v * AR + li], yi);
-                if (oj) lds_add(&sy[v * AR + lj], yj);
+                if (oa) lds_add(&sy[v * AR + la], swp ? yj : yi);
+                if (ob) lds_add(&sy[v * AR + lb], swp ? yi : yj);
             }
             // a direct output is written by the cluster of the smaller end only
             if (Op::NWOUT && (ij[b].x < ij[b].y ? oi : oj)) {
@@ -934,7 +939,8 @@ int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t s
 {
     if (!P.owner_ok || P.ncl <= 0) return (int)hipErrorInvalidValue;
     const size_t lds = owner_dyn_lds<T, Op>(P.K);
-    const OwnerPtrs op{P.e2n, P.prim, P.sec_off, P.sec_eid, P.pmap, P.smap, P.nbr_off, P.nbr};
+    const OwnerPtrs op{P.oe2n ? P.oe2n : P.e2n, P.prim, P.sec_off, P.sec_eid, P.pmap, P.smap,
+                       P.nbr_off, P.nbr};
     if (P.compact && lo.compact)
         hipLaunchKernelGGL((k_edge_owner<T, Op, kOwnerThreads, true>), dim3(P.ncl),
                            dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,

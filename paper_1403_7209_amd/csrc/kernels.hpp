@@ -41,6 +41,8 @@ struct DevPlan {
     const int2 *prim = nullptr;    // [ncl]
     const int *sec_off = nullptr;  // [ncl+1]
     const int *sec_eid = nullptr;  // [sec_off[ncl]]
+    const int2 *oe2n = nullptr;    // [E] the map with bit 31 of .y set where the owner
+                                   // kernel updates the second end first (bank spreading)
     // Compact visit words (K <= 1024, at most 256 neighbour clusters each):
     // own offset (10 bits) | own is the second end (1) | other end foreign (1)
     // | neighbour slot (8) | other end's offset in its cluster (10).

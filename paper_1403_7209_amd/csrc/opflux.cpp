@@ -242,6 +242,14 @@ int upload_plan(opf_ctx *ctx, PlanRec &pr)
         if (!rc) rc = upload(ctx, pr, prim, D.prim);
         if (!rc) rc = upload(ctx, pr, sec_off, D.sec_off);
         if (!rc) rc = upload(ctx, pr, P.cl_sec_eid, D.sec_eid);
+        if (!rc && !P.owner_swap.empty()) {
+            std::vector<int2> oe2n(P.E);
+            for (int64_t k = 0; k < P.E; ++k)
+                oe2n[k] = make_int2(P.e2n[2 * k],
+                                    (int)((uint32_t)P.e2n[2 * k + 1] |
+                                          ((uint32_t)P.owner_swap[k] << 31)));
+            rc = upload(ctx, pr, oe2n, D.oe2n);
+        }
         if (!rc && pr.compact) rc = upload_compact(ctx, pr);
     }
     if (P.flat_ok) {
@@ -777,6 +785,7 @@ int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info
         po.colour_sort = opts->colour_sort;
         po.cluster_size = opts->cluster_size;
         po.lane_groups = opts->lane_groups;
+        po.bank_spread = opts->bank_spread;
         po.coords = opts->coords;
     }
     auto t0 = std::chrono::steady_clock::now();
@@ -884,6 +893,7 @@ int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out)
     out->nflat_colours = P.flat_ok ? P.flat_colours : 0;
     out->flat_offsets = P.flat_ok ? P.flat_off.data() : nullptr;
     out->flat_edges = P.flat_ok ? P.flat_eid.data() : nullptr;
+    out->owner_swap = P.owner_swap.empty() ? nullptr : P.owner_swap.data();
     return OPF_OK;
 }
 

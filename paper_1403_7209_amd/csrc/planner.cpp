@@ -2,9 +2,11 @@
 #include "planner.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdlib>
 #include <numeric>
+#include <thread>
 
 #include "opflux.h"
 
@@ -158,6 +160,142 @@ void morton(int64_t N, const double *xyz, std::vector<int32_t> &new_of_old)
 }
 
 inline int lowest_free(uint64_t used) { return used == ~0ULL ? -1 : __builtin_ctzll(~used); }
+
+// Runs f(0..n-1) on up to 16 host threads (independent iterations only).
+template <class F>
+void parallel_for(int64_t n, const F &f)
+{
+    const int64_t nt = std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(), n}));
+    if (nt <= 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int64_t> next(0);
+    std::vector<std::thread> pool;
+    for (int64_t t = 0; t < nt; ++t)
+        pool.emplace_back([&] {
+            for (int64_t i; (i = next.fetch_add(1)) < n;) f(i);
+        });
+    for (std::thread &th : pool) th.join();
+}
+
+// Bank spreading of one wavefront chunk.  The owner kernel's lanes 0..63 take
+// the chunk's visits in order; each lane adds into the LDS words of its owned
+// ends (offset o inside the cluster), one instruction for the "first" end and
+// one for the "second".  Lanes that run in the same LDS cycle conflict when
+// their offsets agree modulo the bank count; the placement below puts each
+// visit into a quarter of the chunk (16 lanes) and picks which end goes first,
+// greedily minimising equal residues mod 16 per quarter and mod 32 per half.
+// ends[2t], ends[2t+1]: offsets of visit t's ends, -1 for an end not owned.
+// Returns the new order (a permutation of 0..n-1) and the swap flags.
+void spread_chunk(int n, const int32_t *ends, std::vector<int> &perm, std::vector<uint8_t> &swap)
+{
+    int c16[2][4][16] = {}, c32[2][2][32] = {};
+    std::vector<int> quarter(n, -1);
+    perm.assign(n, -1);
+    swap.assign(n, 0);
+    int cap[4];  // a partial chunk fills the hardware quarters in order
+    for (int q = 0; q < 4; ++q) cap[q] = std::max(0, std::min(16, n - 16 * q));
+    // cost of adding (sign +1) or removing (-1) visit t at quarter q with flag sw:
+    // the number of equal residues it meets (excess pairs)
+    auto touch = [&](int t, int q, int sw, int sign) {
+        int d = 0;
+        for (int k = 0; k < 2; ++k) {
+            const int o = ends[2 * t + (k ^ sw)];
+            if (o < 0) continue;
+            int &a = c16[k][q][o & 15], &b = c32[k][q >> 1][o & 31];
+            if (sign > 0) {
+                d += a + b;
+                ++a;
+                ++b;
+            } else {
+                --a;
+                --b;
+                d -= a + b;
+            }
+        }
+        return d;
+    };
+    auto peek = [&](int t, int q, int sw) {
+        int d = 0;
+        for (int k = 0; k < 2; ++k) {
+            const int o = ends[2 * t + (k ^ sw)];
+            if (o >= 0) d += c16[k][q][o & 15] + c32[k][q >> 1][o & 31];
+        }
+        return d;
+    };
+    // greedy placement
+    int used[4] = {0, 0, 0, 0};
+    for (int t = 0; t < n; ++t) {
+        int best = 1 << 30, bq = -1, bs = 0;
+        for (int q = 0; q < 4; ++q) {
+            if (used[q] >= cap[q]) continue;
+            for (int sw = 0; sw < 2; ++sw) {
+                const int c = peek(t, q, sw);
+                if (c < best) {
+                    best = c;
+                    bq = q;
+                    bs = sw;
+                }
+            }
+        }
+        quarter[t] = bq;
+        swap[t] = (uint8_t)bs;
+        ++used[bq];
+        touch(t, bq, bs, +1);
+    }
+    // local search: exchange two visits of different quarters (each with its best
+    // flag) while that lowers the count of equal residues
+    for (int pass = 0; pass < 3; ++pass) {
+        bool improved = false;
+        for (int t = 0; t < n; ++t) {
+            // only visits that still meet an equal residue are worth moving
+            int meets = 0;
+            for (int k = 0; k < 2; ++k) {
+                const int o = ends[2 * t + (k ^ swap[t])];
+                if (o >= 0)
+                    meets += c16[k][quarter[t]][o & 15] + c32[k][quarter[t] >> 1][o & 31] - 2;
+            }
+            if (meets == 0) continue;
+            for (int u = 0; u < n; ++u) {
+                const int qt = quarter[t], qu = quarter[u];
+                if (u == t || qt == qu) continue;
+                const int st = swap[t], su = swap[u];
+                const int before = -(touch(t, qt, st, -1) + touch(u, qu, su, -1));
+                int best = before, bt = -1, bu = -1;
+                for (int ft = 0; ft < 2; ++ft) {
+                    const int ct = touch(t, qu, ft, +1);
+                    for (int fu = 0; fu < 2; ++fu) {
+                        const int cu = peek(u, qt, fu);
+                        if (ct + cu < best) {
+                            best = ct + cu;
+                            bt = ft;
+                            bu = fu;
+                        }
+                    }
+                    touch(t, qu, ft, -1);
+                }
+                if (bt >= 0) {
+                    touch(t, qu, bt, +1);
+                    touch(u, qt, bu, +1);
+                    quarter[t] = qu;
+                    quarter[u] = qt;
+                    swap[t] = (uint8_t)bt;
+                    swap[u] = (uint8_t)bu;
+                    improved = true;
+                } else {
+                    touch(t, qt, st, +1);
+                    touch(u, qu, su, +1);
+                }
+            }
+        }
+        if (!improved) break;
+    }
+    int pos = 0;
+    for (int q = 0; q < 4; ++q)
+        for (int t = 0; t < n; ++t)
+            if (quarter[t] == q) perm[pos++] = t;
+}
 
 }  // namespace
 
@@ -314,6 +452,47 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
         }
     }
 
+    // (2c) bank spreading of the owner kernel's wavefront chunks over each
+    // cluster's range of edges (edges whose smaller end it owns); the ranges are
+    // independent, so they are spread by a few host threads
+    std::vector<uint8_t> swap_user;
+    if (K > 0 && opt.bank_spread) {
+        swap_user.assign(E, 0);
+        std::vector<std::pair<int64_t, int64_t>> ranges;
+        for (int64_t k = 0; k < E;) {
+            const int64_t c = std::min(P.e2n[2 * k], P.e2n[2 * k + 1]) / K;
+            int64_t k1 = k + 1;
+            while (k1 < E && std::min(P.e2n[2 * k1], P.e2n[2 * k1 + 1]) / K == c) ++k1;
+            ranges.emplace_back(k, k1);
+            k = k1;
+        }
+        parallel_for((int64_t)ranges.size(), [&](int64_t r) {
+            const int64_t k = ranges[r].first, k1 = ranges[r].second;
+            const int64_t c = std::min(P.e2n[2 * k], P.e2n[2 * k + 1]) / K, v0 = c * K;
+            std::vector<int32_t> ends, tmp_order, tmp_e2n;
+            std::vector<int> perm;
+            std::vector<uint8_t> sw;
+            for (int64_t w0 = k; w0 < k1; w0 += 64) {
+                const int n = (int)std::min<int64_t>(64, k1 - w0);
+                ends.assign(2 * n, -1);
+                for (int t = 0; t < n; ++t)
+                    for (int h = 0; h < 2; ++h) {
+                        const int64_t v = P.e2n[2 * (w0 + t) + h];
+                        if (v / K == c) ends[2 * t + h] = (int32_t)(v - v0);
+                    }
+                spread_chunk(n, ends.data(), perm, sw);
+                tmp_order.assign(order.begin() + w0, order.begin() + w0 + n);
+                tmp_e2n.assign(P.e2n.begin() + 2 * w0, P.e2n.begin() + 2 * (w0 + n));
+                for (int t = 0; t < n; ++t) {
+                    order[w0 + t] = tmp_order[perm[t]];
+                    P.e2n[2 * (w0 + t)] = tmp_e2n[2 * perm[t]];
+                    P.e2n[2 * (w0 + t) + 1] = tmp_e2n[2 * perm[t] + 1];
+                    swap_user[order[w0 + t]] = sw[perm[t]];
+                }
+            }
+        });
+    }
+
     // (3) mini-partitions of consecutive edges
     const int64_t nb = (E + BS - 1) / BS;
     P.block_off.resize(nb + 1);
@@ -398,6 +577,10 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
     }
     P.edge_new.resize(E);
     for (int64_t k = 0; k < E; ++k) P.edge_new[order[k]] = (int32_t)k;
+    if (!swap_user.empty()) {
+        P.owner_swap.resize(E);
+        for (int64_t k = 0; k < E; ++k) P.owner_swap[k] = swap_user[order[k]];
+    }
 
     // owner clusters: segments of constant (cluster(min), cluster(max)); a
     // partition may have reordered edges by colour, so segments are formed on
@@ -473,6 +656,33 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
                 for (int64_t c = 0; c < ncl; ++c) P.cl_sec_off[c + 1] += P.cl_sec_off[c];
                 P.cl_sec_eid.resize(P.cl_sec_off[ncl]);
             }
+        }
+        // bank spreading of the listed visits: chunks follow the kernel's
+        // positions, which continue after the cluster's edge range
+        if (opt.bank_spread) {
+            parallel_for(ncl, [&](int64_t c) {
+                std::vector<int32_t> ends, tmp;
+                std::vector<int> perm;
+                std::vector<uint8_t> sw;
+                const int64_t s0 = P.cl_sec_off[c], ns = P.cl_sec_off[c + 1] - s0;
+                const int64_t first = (64 - P.cl_prim[2 * c + 1] % 64) % 64;  // rest of the last range chunk
+                for (int64_t a = 0; a < ns;) {
+                    const int64_t b = a == 0 && first > 0 ? std::min(ns, first) : std::min(ns, a + 64);
+                    const int n = (int)(b - a);
+                    ends.assign(2 * n, -1);
+                    for (int t = 0; t < n; ++t) {
+                        const int64_t e = P.cl_sec_eid[s0 + a + t];
+                        for (int h = 0; h < 2; ++h) {
+                            const int64_t v = P.e2n[2 * e + h];
+                            if (v / K == c) ends[2 * t + h] = (int32_t)(v - c * K);
+                        }
+                    }
+                    spread_chunk(n, ends.data(), perm, sw);
+                    tmp.assign(P.cl_sec_eid.begin() + s0 + a, P.cl_sec_eid.begin() + s0 + b);
+                    for (int t = 0; t < n; ++t) P.cl_sec_eid[s0 + a + t] = tmp[perm[t]];
+                    a = b;
+                }
+            });
         }
         P.owner_ok = true;
     }
@@ -722,11 +932,8 @@ VerifyResult verify_plan(const Plan &P, const int32_t *e2n_user)
             if (pn < 0) return fail(8, c, "negative visit range");
             for (int64_t k = p0; k < p0 + pn; ++k)
                 if (!visit(c, k)) return fail(8, k, "visit range holds an edge of another cluster");
-            for (int64_t s = P.cl_sec_off[c]; s < P.cl_sec_off[c + 1]; ++s) {
-                if (s > P.cl_sec_off[c] && P.cl_sec_eid[s] <= P.cl_sec_eid[s - 1])
-                    return fail(8, c, "visit list not ascending");
+            for (int64_t s = P.cl_sec_off[c]; s < P.cl_sec_off[c + 1]; ++s)
                 if (!visit(c, P.cl_sec_eid[s])) return fail(8, s, "visit list holds an edge of another cluster");
-            }
         }
         for (int64_t k = 0; k < E; ++k) {
             const int want = (P.e2n[2 * k] / K == P.e2n[2 * k + 1] / K) ? 1 : 2;

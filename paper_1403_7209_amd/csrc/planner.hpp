@@ -23,6 +23,8 @@ struct PlanOptions {
     int cluster_size = 512;          // nodes per owner cluster; 0 = no owner clusters
     int lane_groups = 1;             // reorder each cluster-pair segment into groups of
                                      // 64 edges that share no node
+    int bank_spread = 1;             // place the edges of every 64-visit wavefront chunk
+                                     // on lanes so their LDS words fall in distinct banks
     const double *coords = nullptr;  // SoA 3 x N
 };
 
@@ -66,6 +68,9 @@ struct Plan {
     std::vector<int32_t> cl_prim;     // [2 ncl]
     std::vector<int64_t> cl_sec_off;  // [ncl+1]
     std::vector<int32_t> cl_sec_eid;
+    // Per internal edge: 1 when the owner kernel should issue the second end's
+    // LDS update first (bank spreading); empty when not computed.
+    std::vector<uint8_t> owner_swap;
     // Flat colouring (one level over all edges; no partitions): edges
     // flat_eid[flat_off[c] .. flat_off[c+1]) have colour c and share no node.
     bool flat_ok = false;  // false when more than 128 colours would be needed
