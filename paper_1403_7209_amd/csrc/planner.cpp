@@ -179,122 +179,76 @@ void parallel_for(int64_t n, const F &f)
     for (std::thread &th : pool) th.join();
 }
 
-// Bank spreading of one wavefront chunk.  The owner kernel's lanes 0..63 take
-// the chunk's visits in order; each lane adds into the LDS words of its owned
-// ends (offset o inside the cluster), one instruction for the "first" end and
-// one for the "second".  Lanes that run in the same LDS cycle conflict when
-// their offsets agree modulo the bank count; the placement below puts each
-// visit into a quarter of the chunk (16 lanes) and picks which end goes first,
-// greedily minimising equal residues mod 16 per quarter and mod 32 per half.
-// ends[2t], ends[2t+1]: offsets of visit t's ends, -1 for an end not owned.
-// Returns the new order (a permutation of 0..n-1) and the swap flags.
-void spread_chunk(int n, const int32_t *ends, std::vector<int> &perm, std::vector<uint8_t> &swap)
+// Bank spreading.  The owner kernel's lanes take a cluster's visits in order;
+// per lane the LDS words of its owned ends (offset o inside the cluster) are
+// updated by two instructions, "first" and "second" end.  The LDS serves a
+// quarter-wavefront (16 lanes) per pass and its 8-byte words fall in 16 banks
+// (o mod 16), so 16 lanes conflict-free need 16 distinct residues per
+// instruction.  quarter_groups() splits a list of visits into groups of 16
+// with distinct residues in each slot (first fit over open groups; an edge
+// with two owned ends may go either way round), full groups first, so the
+// groups line up with quarter-wavefronts.  ends[2t], ends[2t+1]: offsets of
+// visit t's ends (-1: not owned); fixed[t] >= 0 forces the orientation.
+void quarter_groups(int n, const int32_t *ends, const int8_t *fixed, int lead, std::vector<int> &perm,
+                    std::vector<uint8_t> &swap)
 {
-    int c16[2][4][16] = {}, c32[2][2][32] = {};
-    std::vector<int> quarter(n, -1);
-    perm.assign(n, -1);
+    struct Group {
+        uint16_t a = 0, b = 0;
+        std::vector<int> members;
+    };
+    std::vector<Group> open, done;
+    perm.clear();
     swap.assign(n, 0);
-    int cap[4];  // a partial chunk fills the hardware quarters in order
-    for (int q = 0; q < 4; ++q) cap[q] = std::max(0, std::min(16, n - 16 * q));
-    // cost of adding (sign +1) or removing (-1) visit t at quarter q with flag sw:
-    // the number of equal residues it meets (excess pairs)
-    auto touch = [&](int t, int q, int sw, int sign) {
-        int d = 0;
-        for (int k = 0; k < 2; ++k) {
-            const int o = ends[2 * t + (k ^ sw)];
-            if (o < 0) continue;
-            int &a = c16[k][q][o & 15], &b = c32[k][q >> 1][o & 31];
-            if (sign > 0) {
-                d += a + b;
-                ++a;
-                ++b;
-            } else {
-                --a;
-                --b;
-                d -= a + b;
-            }
-        }
-        return d;
-    };
-    auto peek = [&](int t, int q, int sw) {
-        int d = 0;
-        for (int k = 0; k < 2; ++k) {
-            const int o = ends[2 * t + (k ^ sw)];
-            if (o >= 0) d += c16[k][q][o & 15] + c32[k][q >> 1][o & 31];
-        }
-        return d;
-    };
-    // greedy placement
-    int used[4] = {0, 0, 0, 0};
+    const size_t kMaxOpen = 1024;
     for (int t = 0; t < n; ++t) {
-        int best = 1 << 30, bq = -1, bs = 0;
-        for (int q = 0; q < 4; ++q) {
-            if (used[q] >= cap[q]) continue;
-            for (int sw = 0; sw < 2; ++sw) {
-                const int c = peek(t, q, sw);
-                if (c < best) {
-                    best = c;
-                    bq = q;
-                    bs = sw;
+        const int r0 = ends[2 * t] < 0 ? -1 : ends[2 * t] & 15;
+        const int r1 = ends[2 * t + 1] < 0 ? -1 : ends[2 * t + 1] & 15;
+        int where = -1, orient = 0;
+        for (size_t g = 0; g < open.size() && where < 0; ++g)
+            for (int o = 0; o < 2; ++o) {
+                if (fixed[t] >= 0 && o != fixed[t]) continue;
+                const int ra = o ? r1 : r0, rb = o ? r0 : r1;
+                if ((ra < 0 || !((open[g].a >> ra) & 1)) && (rb < 0 || !((open[g].b >> rb) & 1))) {
+                    where = (int)g;
+                    orient = o;
+                    break;
                 }
             }
+        if (where < 0) {
+            if (open.size() >= kMaxOpen) {  // too many open groups: close the fullest
+                size_t best = 0;
+                for (size_t g = 1; g < open.size(); ++g)
+                    if (open[g].members.size() > open[best].members.size()) best = g;
+                done.push_back(std::move(open[best]));
+                open.erase(open.begin() + best);
+            }
+            open.emplace_back();
+            where = (int)open.size() - 1;
+            orient = fixed[t] >= 0 ? fixed[t] : 0;
         }
-        quarter[t] = bq;
-        swap[t] = (uint8_t)bs;
-        ++used[bq];
-        touch(t, bq, bs, +1);
-    }
-    // local search: exchange two visits of different quarters (each with its best
-    // flag) while that lowers the count of equal residues
-    for (int pass = 0; pass < 3; ++pass) {
-        bool improved = false;
-        for (int t = 0; t < n; ++t) {
-            // only visits that still meet an equal residue are worth moving
-            int meets = 0;
-            for (int k = 0; k < 2; ++k) {
-                const int o = ends[2 * t + (k ^ swap[t])];
-                if (o >= 0)
-                    meets += c16[k][quarter[t]][o & 15] + c32[k][quarter[t] >> 1][o & 31] - 2;
-            }
-            if (meets == 0) continue;
-            for (int u = 0; u < n; ++u) {
-                const int qt = quarter[t], qu = quarter[u];
-                if (u == t || qt == qu) continue;
-                const int st = swap[t], su = swap[u];
-                const int before = -(touch(t, qt, st, -1) + touch(u, qu, su, -1));
-                int best = before, bt = -1, bu = -1;
-                for (int ft = 0; ft < 2; ++ft) {
-                    const int ct = touch(t, qu, ft, +1);
-                    for (int fu = 0; fu < 2; ++fu) {
-                        const int cu = peek(u, qt, fu);
-                        if (ct + cu < best) {
-                            best = ct + cu;
-                            bt = ft;
-                            bu = fu;
-                        }
-                    }
-                    touch(t, qu, ft, -1);
-                }
-                if (bt >= 0) {
-                    touch(t, qu, bt, +1);
-                    touch(u, qt, bu, +1);
-                    quarter[t] = qu;
-                    quarter[u] = qt;
-                    swap[t] = (uint8_t)bt;
-                    swap[u] = (uint8_t)bu;
-                    improved = true;
-                } else {
-                    touch(t, qt, st, +1);
-                    touch(u, qu, su, +1);
-                }
-            }
+        Group &G = open[where];
+        const int ra = orient ? r1 : r0, rb = orient ? r0 : r1;
+        if (ra >= 0) G.a |= (uint16_t)(1u << ra);
+        if (rb >= 0) G.b |= (uint16_t)(1u << rb);
+        G.members.push_back(t);
+        swap[t] = (uint8_t)orient;
+        if (G.members.size() == 16) {
+            done.push_back(std::move(G));
+            open.erase(open.begin() + where);
         }
-        if (!improved) break;
     }
-    int pos = 0;
-    for (int q = 0; q < 4; ++q)
-        for (int t = 0; t < n; ++t)
-            if (quarter[t] == q) perm[pos++] = t;
+    // full groups line up with quarter-wavefronts; the partial ones go last,
+    // except that `lead` visits taken from them fill the quarter that precedes
+    // the list (the list starts `lead` lanes before a quarter boundary)
+    std::vector<int> full, rest;
+    for (const Group &g : done)
+        (g.members.size() == 16 ? full : rest).insert(g.members.size() == 16 ? full.end() : rest.end(),
+                                                      g.members.begin(), g.members.end());
+    for (const Group &g : open) rest.insert(rest.end(), g.members.begin(), g.members.end());
+    const int take = std::min<int>(lead, (int)rest.size());
+    perm.assign(rest.end() - take, rest.end());
+    perm.insert(perm.end(), full.begin(), full.end());
+    perm.insert(perm.end(), rest.begin(), rest.end() - take);
 }
 
 }  // namespace
@@ -470,25 +424,35 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
             const int64_t k = ranges[r].first, k1 = ranges[r].second;
             const int64_t c = std::min(P.e2n[2 * k], P.e2n[2 * k + 1]) / K, v0 = c * K;
             std::vector<int32_t> ends, tmp_order, tmp_e2n;
+            std::vector<int8_t> fixed;
             std::vector<int> perm;
             std::vector<uint8_t> sw;
-            for (int64_t w0 = k; w0 < k1; w0 += 64) {
-                const int n = (int)std::min<int64_t>(64, k1 - w0);
+            // one segment (edges to one neighbour cluster, or inside the
+            // cluster) at a time, so that a wavefront's lanes gather from one
+            // place and take the same branch
+            for (int64_t s0 = k; s0 < k1;) {
+                const int64_t cx = std::max(P.e2n[2 * s0], P.e2n[2 * s0 + 1]) / K;
+                int64_t s1 = s0 + 1;
+                while (s1 < k1 && std::max(P.e2n[2 * s1], P.e2n[2 * s1 + 1]) / K == cx) ++s1;
+                const int64_t n = s1 - s0;
                 ends.assign(2 * n, -1);
-                for (int t = 0; t < n; ++t)
+                fixed.assign(n, -1);
+                tmp_order.assign(order.begin() + s0, order.begin() + s1);
+                tmp_e2n.assign(P.e2n.begin() + 2 * s0, P.e2n.begin() + 2 * s1);
+                for (int64_t t = 0; t < n; ++t)
                     for (int h = 0; h < 2; ++h) {
-                        const int64_t v = P.e2n[2 * (w0 + t) + h];
+                        const int64_t v = tmp_e2n[2 * t + h];
                         if (v / K == c) ends[2 * t + h] = (int32_t)(v - v0);
                     }
-                spread_chunk(n, ends.data(), perm, sw);
-                tmp_order.assign(order.begin() + w0, order.begin() + w0 + n);
-                tmp_e2n.assign(P.e2n.begin() + 2 * w0, P.e2n.begin() + 2 * (w0 + n));
-                for (int t = 0; t < n; ++t) {
-                    order[w0 + t] = tmp_order[perm[t]];
-                    P.e2n[2 * (w0 + t)] = tmp_e2n[2 * perm[t]];
-                    P.e2n[2 * (w0 + t) + 1] = tmp_e2n[2 * perm[t] + 1];
-                    swap_user[order[w0 + t]] = sw[perm[t]];
+                const int lead = (int)((16 - (s0 - k) % 16) % 16);
+                quarter_groups((int)n, ends.data(), fixed.data(), lead, perm, sw);
+                for (int64_t t = 0; t < n; ++t) {
+                    order[s0 + t] = tmp_order[perm[t]];
+                    P.e2n[2 * (s0 + t)] = tmp_e2n[2 * perm[t]];
+                    P.e2n[2 * (s0 + t) + 1] = tmp_e2n[2 * perm[t] + 1];
+                    swap_user[order[s0 + t]] = sw[perm[t]];
                 }
+                s0 = s1;
             }
         });
     }
@@ -659,27 +623,42 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
         }
         // bank spreading of the listed visits: chunks follow the kernel's
         // positions, which continue after the cluster's edge range
-        if (opt.bank_spread) {
+        if (opt.bank_spread && !P.owner_swap.empty()) {
+            // the listed visits have one owned end each, whose instruction the
+            // edge's flag (set for the cluster of its smaller end) already fixes
             parallel_for(ncl, [&](int64_t c) {
+                const int64_t s0 = P.cl_sec_off[c], ns = P.cl_sec_off[c + 1] - s0;
                 std::vector<int32_t> ends, tmp;
+                std::vector<int8_t> fixed;
                 std::vector<int> perm;
                 std::vector<uint8_t> sw;
-                const int64_t s0 = P.cl_sec_off[c], ns = P.cl_sec_off[c + 1] - s0;
-                const int64_t first = (64 - P.cl_prim[2 * c + 1] % 64) % 64;  // rest of the last range chunk
+                // one neighbour cluster at a time (the list is in edge order,
+                // which groups the edges by the cluster of their smaller end)
                 for (int64_t a = 0; a < ns;) {
-                    const int64_t b = a == 0 && first > 0 ? std::min(ns, first) : std::min(ns, a + 64);
-                    const int n = (int)(b - a);
+                    const int64_t ea = P.cl_sec_eid[s0 + a];
+                    const int64_t cx = std::min(P.e2n[2 * ea], P.e2n[2 * ea + 1]) / K;
+                    int64_t b = a + 1;
+                    while (b < ns) {
+                        const int64_t eb = P.cl_sec_eid[s0 + b];
+                        if (std::min(P.e2n[2 * eb], P.e2n[2 * eb + 1]) / K != cx) break;
+                        ++b;
+                    }
+                    const int64_t n = b - a;
                     ends.assign(2 * n, -1);
-                    for (int t = 0; t < n; ++t) {
-                        const int64_t e = P.cl_sec_eid[s0 + a + t];
+                    fixed.assign(n, 0);
+                    tmp.assign(P.cl_sec_eid.begin() + s0 + a, P.cl_sec_eid.begin() + s0 + b);
+                    for (int64_t t = 0; t < n; ++t) {
+                        const int64_t e = tmp[t];
                         for (int h = 0; h < 2; ++h) {
                             const int64_t v = P.e2n[2 * e + h];
                             if (v / K == c) ends[2 * t + h] = (int32_t)(v - c * K);
                         }
+                        fixed[t] = (int8_t)P.owner_swap[e];
                     }
-                    spread_chunk(n, ends.data(), perm, sw);
-                    tmp.assign(P.cl_sec_eid.begin() + s0 + a, P.cl_sec_eid.begin() + s0 + b);
-                    for (int t = 0; t < n; ++t) P.cl_sec_eid[s0 + a + t] = tmp[perm[t]];
+                    const int64_t pos = P.cl_prim[2 * c + 1] + a;  // kernel position of the run
+                    const int lead = (int)((16 - pos % 16) % 16);
+                    quarter_groups((int)n, ends.data(), fixed.data(), lead, perm, sw);
+                    for (int64_t t = 0; t < n; ++t) P.cl_sec_eid[s0 + a + t] = tmp[perm[t]];
                     a = b;
                 }
             });

@@ -183,8 +183,9 @@ def test_lane_groups_make_wavefront_endpoints_distinct():
 def owner_bank_conflicts(v):
     """Excess same-bank LDS words over the owner kernel's wavefronts: lanes run
     the cluster's visits in order; per lane the first and second owned end (the
-    swap flag reverses them) each form one LDS instruction; count equal offsets
-    mod 16 per quarter-wave and mod 32 per half-wave, beyond the first."""
+    swap flag reverses them) each form one LDS instruction; the LDS serves a
+    quarter-wave per pass with 16 banks of 8-byte words, so count equal offsets
+    mod 16 per quarter-wave beyond the first."""
     K, e2n = v["cluster_size"], v["e2n"].astype(np.int64)
     rng, loff, led = v["cluster_range"], v["cluster_list_offsets"], v["cluster_list_edges"]
     swap = v["owner_swap"]
@@ -193,7 +194,7 @@ def owner_bank_conflicts(v):
         vis = np.concatenate([np.arange(rng[c, 0], rng[c, 0] + rng[c, 1]), led[loff[c]:loff[c + 1]]])
         ends = e2n[vis].copy()
         if swap is not None:
-            s = swap[vis].astype(bool) & (np.arange(len(vis)) < rng[c, 1])
+            s = swap[vis].astype(bool)
             ends[s] = ends[s][:, ::-1]
         own = np.where(ends // K == c, ends - c * K, -1)
         lane = np.arange(len(vis)) % 64
@@ -201,10 +202,9 @@ def owner_bank_conflicts(v):
         for slot in range(2):
             o = own[:, slot]
             m = o >= 0
-            for width, mod in ((16, 16), (32, 32)):
-                key = (chunk[m] * 4 + lane[m] // width) * 64 + o[m] % mod
-                _, cnt = np.unique(key, return_counts=True)
-                total += int((cnt - 1).sum())
+            key = (chunk[m] * 4 + lane[m] // 16) * 16 + o[m] % 16
+            _, cnt = np.unique(key, return_counts=True)
+            total += int((cnt - 1).sum())
     return total
 
 
