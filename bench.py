@@ -7,12 +7,16 @@ and synthetic.
 
 One step = one 5-stage Runge-Kutta iteration in FP64 (5 edge-flux loops + 5
 stage updates with residual norms), the same iteration in the FP32-storage
-form, and one FP64 adjoint edge sweep: 11 edge loops over all edges.
+form, and one FP64 adjoint edge sweep: 11 edge loops over all edges.  With the
+owner variant (the default) each stage update is fused into its edge loop
+(opf_edge_flux_stage); other variants run the two loops separately.
 
 value = 11 * E / (seconds per step): edges per second over the whole step,
-inputs resident in HBM.  The roofline entry is the FP64 edge-flux loop,
-priced in algorithmic bytes (32 B per edge: map 8 + weights 24; 96 B per
-node: state read 48 + residual write 48) against 8 TB/s.
+inputs resident in HBM.  The roofline entry is the dominant kernel: the fused
+FP64 edge-flux + stage loop, priced in algorithmic bytes (32 B per edge: map 8
++ weights 24; 152 B per node: state 48 + stage base 48 + volume 8 read, new
+state 48 written), or for other variants the FP64 edge-flux loop (32 B per
+edge; 96 B per node: state read 48 + residual write 48), against 8 TB/s.
 
 After the timed steps it also times, outside `value`, the Green-Gauss
 gradient loop, the second-order edge loop, the local time-step loop and the
@@ -36,6 +40,10 @@ HBM_PEAK_GBS = 8000.0
 BYTES = {  # algorithmic bytes: (per edge, per node[, per tet])
     "fp64": (32, 96),
     "fp32": (20, 72),
+    # the owner loop with the stage update fused in: q read 48 + q0 48 + vol 8 + q
+    # written 48 per node (FP32 storage: 24 + 24 + 8 + 24); no residual traffic
+    "fp64_fused": (32, 152),
+    "fp32_fused": (20, 80),
     "adjoint": (56, 144),
     "rk64": (0, 152),
     "rk32": (0, 104),
@@ -160,7 +168,8 @@ def main():
     q0_init64, q0_init32 = p64.qa.clone(), p32.qa.clone()
 
     stream = torch.cuda.current_stream(dev)
-    timers = {k: [] for k in ("fp64", "fp32", "adjoint", "rk64", "rk32")}
+    timers = {k: [] for k in ("fp64", "fp32", "adjoint", "rk64", "rk32", "fp64_fused",
+                              "fp32_fused")}
     if args.copy_probe:
         src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -176,9 +185,26 @@ def main():
     # the owner variant writes each residual once, so the stage need not zero it
     ra, rk = (pk.WRITE, pk.READ) if variant == pk.OWNER else (pk.INC, pk.RW)
 
+    fused = variant == pk.OWNER
+    for p in (p64, p32):
+        p.qc = torch.empty_like(p.qa)
+
     def rk_iter(p, kflux, krk, rec):
         qa, qb = p.dat(p.qa, "qa"), p.dat(p.qb, "qb")
         p.ss.zero_()
+        if fused:  # stage k reads stage k-1's state and writes the other buffer
+            bufs = (qb, p.dat(p.qc, "qc"))
+            src = qa
+            for k in range(5):
+                a = ev() if rec else None
+                p.ctx.edge_flux_stage(p.edges, p.e2n, src, p.w, qa, p.vol, bufs[k % 2],
+                                      pk.RK_ALPHA[k] * dt, p.ss[k], p.gamma)
+                b = ev() if rec else None
+                if rec:
+                    timers[kflux + "_fused"].append((a, b))
+                src = bufs[k % 2]
+            p.qa, p.qb = p.qb, p.qa
+            return
         for k in range(5):
             a = ev() if rec else None
             p.ctx.edge_flux(p.edges, p.e2n, qa if k == 0 else qb, p.w, p.res_d, p.gamma, variant,
@@ -222,6 +248,18 @@ def main():
     ctx.sync()
     if not ctx.check_finite(p64.ss) or not ctx.check_finite(p32.ss):
         log("warning: non-finite residual norm")
+
+    # the plain edge loops (residual written), beside the step when it fuses the stage
+    if fused:
+        for rec in (False, True):
+            for _ in range(3 if rec else 1):
+                for p, key in ((p64, "fp64"), (p32, "fp32")):
+                    a = ev()
+                    p.ctx.edge_flux(p.edges, p.e2n, p.dat(p.qa, "qa"), p.w, p.res_d, p.gamma,
+                                    variant, pk.WRITE)
+                    b = ev()
+                    if rec:
+                        timers[key].append((a, b))
 
     # loops beside the step: Green-Gauss gradient, second-order flux, local dt
     p64.set_edge_vectors(meshgen.edge_vectors(mesh))
@@ -269,6 +307,8 @@ def main():
 
     per = {}
     for k, lst in timers.items():
+        if not lst:
+            continue
         ms = float(np.mean([a.elapsed_time(b) for a, b in lst]))
         be, bn, bt = (*BYTES[k], 0)[:3]
         gbs = (be * E + bn * N + bt * T) / (ms * 1e-3) / 1e9
@@ -278,13 +318,14 @@ def main():
             per[k]["edges_per_s"] = round(E / (ms * 1e-3), 1)
         log(f"{k:8s} {ms * 1e3:9.1f} us  {gbs:8.1f} GB/s algorithmic  "
             f"({100 * gbs / HBM_PEAK_GBS:.1f} % of 8 TB/s)")
-    speedup32 = per["fp64"]["ms"] / per["fp32"]["ms"]
+    main64, main32 = ("fp64_fused", "fp32_fused") if fused else ("fp64", "fp32")
+    speedup32 = per[main64]["ms"] / per[main32]["ms"]
     value = 11 * E / (ms_step * 1e-3)
     log(f"step {ms_step:.3f} ms (wall {1e3 * wall / args.steps:.3f} ms), {value:.4e} edges/s, "
         f"FP32/FP64 loop speedup {speedup32:.3f}")
 
-    dom = per["fp64"]
-    be, bn = BYTES["fp64"]
+    dom = per[main64]
+    be, bn = BYTES[main64]
     config_key = (f"n={args.n} variant={args.variant} renumber={args.renumber} "
                   f"cluster={args.cluster_size} block={args.block_size} "
                   f"lane_groups={not args.no_lane_groups} colour_sort={bool(args.colour_sort)}")
@@ -317,7 +358,8 @@ def main():
         "forms": per,
         "fp32_speedup_over_fp64": round(speedup32, 4),
         "roofline": {
-            "kernel": "FP64 edge-flux loop (opf_edge_flux)",
+            "kernel": ("FP64 edge-flux loop with the stage update fused (opf_edge_flux_stage)"
+                       if fused else "FP64 edge-flux loop (opf_edge_flux)"),
             "bound": "hbm",
             "achieved": dom["algorithmic_GBs"],
             "peak": HBM_PEAK_GBS,

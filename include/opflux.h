@@ -388,6 +388,21 @@ int opf_edge_gradient(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_d
 int opf_edge_flux2(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat G, opf_dat vol,
                    opf_dat n, opf_dat dx, opf_dat res, double gamma, int variant, int res_access,
                    void *stream);
+/* The EDGE_FLUX loop (OWNER variant) and the RK stage update fused: each
+ * owner workgroup turns its nodes' residual totals straight into
+ * qout = q0 - alpha * res / vol (alpha * dt_i * res / vol when dt >= 0 names a
+ * per-node step dat) and adds sum res^2 per component to ss_dev (6 device
+ * doubles; per-cluster partials summed in a fixed order).  The residual is not
+ * written.  q: node dat (6, T = F64 or F32) read through e2n; n: edge dat
+ * (3, T); q0, qout: node dats (6, T); vol: node dat (1, F64).  q may be q0;
+ * qout must differ from both (other workgroups still read q).  A fusion of two
+ * loops of the paper's iteration (the edge flux and the direct update of
+ * Sec. 2), possible because the owner variant completes every node's total
+ * inside one workgroup.  Errors: as opf_par_loop; OPF_EINVAL without owner
+ * clusters or on aliasing. */
+int opf_edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
+                        opf_dat q0, opf_dat vol, opf_dat dt, opf_dat qout, double gamma,
+                        double alpha, double *ss_dev, void *stream);
 int opf_geometry(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x, double period,
                  opf_dat w, opf_dat vol, void *stream);
 int opf_geometry_adjoint(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x,

@@ -48,7 +48,7 @@ SYMBOLS = ("opf_init", "opf_finalize", "opf_last_error", "opf_set_allocator", "o
            "opf_decl_map", "opf_plan", "opf_get_perm", "opf_plan_view_get", "opf_plan_verify",
            "opf_decl_dat", "opf_par_loop", "opf_edge_flux", "opf_edge_flux_adjoint",
            "opf_edge_specrad", "opf_edge_gradient", "opf_edge_flux2", "opf_rk_stage",
-           "opf_rk_stage_local", "opf_local_dt", "opf_dt_min", "opf_geometry",
+           "opf_rk_stage_local", "opf_local_dt", "opf_dt_min", "opf_edge_flux_stage", "opf_geometry",
            "opf_geometry_adjoint",
            "opf_sync", "opf_check_finite")
 
@@ -157,6 +157,7 @@ def load():
     lib.opf_rk_stage_local.argtypes = [vp, i32, i32, i32, i32, i32, i32, d, vp, ctypes.c_int, vp]
     lib.opf_local_dt.argtypes = [vp, i32, i32, i32, d, i32, vp]
     lib.opf_geometry.argtypes = [vp, i32, i32, i32, i32, d, i32, i32, vp]
+    lib.opf_edge_flux_stage.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i32, d, d, vp, vp]
     lib.opf_geometry_adjoint.argtypes = [vp, i32, i32, i32, i32, d, i32, i32, i32, vp]
     lib.opf_sync.argtypes = [vp, vp]
     lib.opf_check_finite.argtypes = [vp, vp, ctypes.c_int, vp]
@@ -366,6 +367,15 @@ class Context:
                                             variant, res_access, _stream_ptr(stream, self.device)),
                     "opf_edge_flux2")
 
+    def edge_flux_stage(self, edges, e2n, q, n, q0, vol, qout, alpha, ss, gamma=1.4, dt=-1,
+                        stream=None):
+        """Owner edge-flux loop with the stage update fused: qout = q0 - alpha res/vol
+        (alpha dt_i res/vol with a per-node step dat), ss += sum res^2."""
+        self._check(self.lib.opf_edge_flux_stage(self._ctx, edges, e2n, q, n, q0, vol, dt, qout,
+                                                 gamma, float(alpha), ctypes.c_void_p(ss.data_ptr()),
+                                                 _stream_ptr(stream, self.device)),
+                    "opf_edge_flux_stage")
+
     def geometry(self, tets, t2n, t2e, x, w, vol, period=1.0, stream=None):
         """w (edge dat, 3) and vol (node dat) += median-dual weights and volumes of the tets."""
         self._check(self.lib.opf_geometry(self._ctx, tets, t2n, t2e, x, float(period), w, vol,
@@ -501,9 +511,30 @@ class FluxProblem:
         self.ctx.dt_min(self.nodes, self.vol, self.lam_d, cfl, self.dt_t, stream)
         return float(self.dt_t.item())
 
-    def rk_iteration(self, dt, variant=COLOURED, stream=None):
+    def _rk_fused(self, alpha_of_stage, dt_dat, stream):
+        """Five stages of the owner loop with the update fused in; stage k reads
+        the state of stage k-1 and writes the other of two stage buffers."""
+        if not hasattr(self, "qc"):
+            self.qc = torch.empty_like(self.qa)
+        qa = self.dat(self.qa, "qa")
+        bufs = (self.dat(self.qb, "qb"), self.dat(self.qc, "qc"))
+        self.ss.zero_()
+        src = qa
+        for k in range(5):
+            dst = bufs[k % 2]
+            self.ctx.edge_flux_stage(self.edges, self.e2n, src, self.w, qa, self.vol, dst,
+                                     alpha_of_stage(k), self.ss[k], self.gamma, dt_dat, stream)
+            src = dst
+        # stage 5 wrote qb (k = 4 -> bufs[0])
+        self.qa, self.qb = self.qb, self.qa
+
+    def rk_iteration(self, dt, variant=COLOURED, stream=None, fused=True):
         """One 5-stage iteration; the new state is left in self.qa.  self.ss
-        (5, 6) receives each stage's per-variable sum of squared residuals."""
+        (5, 6) receives each stage's per-variable sum of squared residuals.
+        With the OWNER variant the stage update is fused into the edge loop
+        unless fused=False."""
+        if variant == OWNER and fused:
+            return self._rk_fused(lambda k: RK_ALPHA[k] * dt, -1, stream)
         qa, qb = self.dat(self.qa, "qa"), self.dat(self.qb, "qb")
         # the owner variant writes each residual once: no zeroing pass needed
         ra, rk = (WRITE, READ) if variant == OWNER else (INC, RW)
@@ -573,9 +604,11 @@ class FluxProblem:
         self.ctx.local_dt(self.nodes, self.vol, self.lam_d, cfl, self.dtl_d, stream)
         return self.dtl
 
-    def rk_iteration_local(self, variant=COLOURED, stream=None):
+    def rk_iteration_local(self, variant=COLOURED, stream=None, fused=True):
         """One 5-stage iteration with the per-node steps of the last
         compute_local_dt; otherwise as rk_iteration."""
+        if variant == OWNER and fused:
+            return self._rk_fused(lambda k: RK_ALPHA[k], self.dtl_d, stream)
         qa, qb = self.dat(self.qa, "qa"), self.dat(self.qb, "qb")
         ra, rk = (WRITE, READ) if variant == OWNER else (INC, RW)
         self.ss.zero_()

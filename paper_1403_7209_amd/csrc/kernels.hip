@@ -28,6 +28,7 @@
 // with a wavefront + LDS reduction per workgroup and a fixed-order second
 // pass over the per-workgroup partial sums.
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -38,7 +39,7 @@
 #define OPF_FLUX64_BATCH 2
 #endif
 #ifndef OPF_FLUX64_WAVES
-#define OPF_FLUX64_WAVES 6
+#define OPF_FLUX64_WAVES 4
 #endif
 #ifndef OPF_ADJ_BATCH
 #define OPF_ADJ_BATCH 1
@@ -625,6 +626,28 @@ __global__ __launch_bounds__(256) void k_edge_flat(const int2 *__restrict__ e2n,
     }
 }
 
+// Sum over a workgroup of NWAVE wavefronts; out[v] in a fixed order.
+template <int NV, int NWAVE = 4>
+__device__ __forceinline__ void block_sum(double (&acc)[NV], double *out)
+{
+    __shared__ double red[NWAVE][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        for (int off = 32; off > 0; off >>= 1) acc[v] += __shfl_down(acc[v], off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) red[wave][v] = acc[v];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int v = threadIdx.x;
+        double t = red[0][v];
+#pragma unroll
+        for (int w = 1; w < NWAVE; ++w) t += red[w][v];
+        out[v] = t;
+    }
+}
+
 // ------------------------------------------------------- owner kernel -- */
 
 // One workgroup per cluster of K consecutive nodes.  It runs every edge with
@@ -634,9 +657,24 @@ __global__ __launch_bounds__(256) void k_edge_flat(const int2 *__restrict__ e2n,
 // writes its nodes' totals once.
 __host__ __device__ constexpr int owner_acc_rows(int K) { return K; }
 
-template <typename T, class Op, int NT, bool COMPACT>
+// The stage update fused into the owner loop: each workgroup turns its nodes'
+// totals straight into q = q0 - adt * res / vol (adt * dt_i with per-node
+// steps) and a partial sum of res^2 per component, so the residual never
+// goes to HBM.
+template <typename T>
+struct StagePtrs {
+    const T *q0[6];
+    T *q[6];
+    const double *vol;
+    const double *dt;  // per-node steps or null
+    double adt;
+    double *partial;   // [ncl][6]
+};
+
+template <typename T, class Op, int NT, bool COMPACT, bool STAGE = false>
 __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>::WAVES : 1)) void k_edge_owner(
-    OwnerPtrs p, Arrays<T> a, T gamma, int N, int K, int ncl, int remap, int overwrite)
+    OwnerPtrs p, Arrays<T> a, T gamma, int N, int K, int ncl, int remap, int overwrite,
+    StagePtrs<T> sp = {})
 {
     constexpr int B = OwnerTune<T, Op>::B;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -656,6 +694,16 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
         const int n0 = p.nb_off[c], nn = p.nb_off[c + 1] - n0;
         for (int t = threadIdx.x; t < nn; t += NT) s_nb[t] = p.nb[n0 + t];
         nbt = s_nb;
+    }
+    // fused stage: fetch this thread's node's q0 and vol now, so that the
+    // update at the end does not wait for them (one node per thread when K <= NT)
+    [[maybe_unused]] double pq0[6], pvol = 1.0;
+    if constexpr (STAGE) {
+        if (K <= NT && (int)threadIdx.x < nown) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) pq0[k] = (double)ld(sp.q0[k], v0 + (int)threadIdx.x);
+            pvol = ld(sp.vol, v0 + (int)threadIdx.x);
+        }
     }
     // stage the owned nodes (contiguous ids: coalesced), clear the accumulator
     for (int v = threadIdx.x; v < nown; v += NT) {
@@ -743,34 +791,34 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
         }
     }
     __syncthreads();
-    for (int v = threadIdx.x; v < nown; v += NT) {
+    if constexpr (STAGE) {
+        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int v = threadIdx.x; v < nown; v += NT) {
+            const int g = v0 + v;
+            const bool pre = K <= NT;
+            const double vi = pre ? pvol : ld(sp.vol, g);
+            const double adt = sp.dt ? sp.adt * ld(sp.dt, g) : sp.adt;
 #pragma unroll
-        for (int k = 0; k < Op::NOUT; ++k) {
-            const double acc = sy[k * AR + v];
-            st(a.y[k], v0 + v, overwrite ? acc : ld(a.y[k], v0 + v) + acc);
+            for (int k = 0; k < 6; ++k) {
+                const double r = sy[k * AR + v];
+                acc[k] += r * r;
+                const double base = pre ? pq0[k] : (double)ld(sp.q0[k], g);
+                st(sp.q[k], g, (T)(base - adt * r / vi));
+            }
+        }
+        block_sum<6, NT / 64>(acc, sp.partial + 6 * c);
+    } else {
+        for (int v = threadIdx.x; v < nown; v += NT) {
+#pragma unroll
+            for (int k = 0; k < Op::NOUT; ++k) {
+                const double acc = sy[k * AR + v];
+                st(a.y[k], v0 + v, overwrite ? acc : ld(a.y[k], v0 + v) + acc);
+            }
         }
     }
 }
 
 // ------------------------------------------------------ reductions -- */
-
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&acc)[NV], double *out)
-{
-    __shared__ double red[4][NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-        for (int off = 32; off > 0; off >>= 1) acc[v] += __shfl_down(acc[v], off, 64);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) red[wave][v] = acc[v];
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        const int v = threadIdx.x;
-        out[v] = ((red[0][v] + red[1][v]) + red[2][v]) + red[3][v];
-    }
-}
 
 template <typename T>
 struct RkPtrs {
@@ -952,6 +1000,35 @@ int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t s
     return (int)hipGetLastError();
 }
 
+template <typename T>
+int run_owner_stage(const DevPlan &P, const EdgeArrays &a, const NodeArrays &na, double gamma,
+                    double adt, double *ss, hipStream_t st, const LaunchOpts &lo)
+{
+    if (!P.owner_ok || P.ncl <= 0 || !P.stage_partial) return (int)hipErrorInvalidValue;
+    const size_t lds = owner_dyn_lds<T, OpFlux>(P.K);
+    const OwnerPtrs op{P.oe2n ? P.oe2n : P.e2n, P.prim, P.sec_off, P.sec_eid, P.pmap, P.smap,
+                       P.nbr_off, P.nbr};
+    StagePtrs<T> sp;
+    for (int k = 0; k < 6; ++k) {
+        sp.q0[k] = static_cast<const T *>(na.q0[k]);
+        sp.q[k] = static_cast<T *>(na.q[k]);
+    }
+    sp.vol = na.vol;
+    sp.dt = na.dt;
+    sp.adt = adt;
+    sp.partial = P.stage_partial;
+    if (P.compact && lo.compact)
+        hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, true, true>), dim3(P.ncl),
+                           dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
+                           lo.xcd_remap, 0, sp);
+    else
+        hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, false, true>), dim3(P.ncl),
+                           dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
+                           lo.xcd_remap, 0, sp);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, P.ncl, P.stage_partial, ss);
+    return (int)hipGetLastError();
+}
+
 template <typename T, class Op>
 int run_edge(int variant, const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
              const LaunchOpts &lo)
@@ -1006,6 +1083,14 @@ int raise_all(size_t bytes)
     if (!rc)
         rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, true>),
                        bytes);
+    if constexpr (std::is_same<Op, OpFlux>::value) {
+        if (!rc)
+            rc = raise_one(
+                reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, false, true>), bytes);
+        if (!rc)
+            rc = raise_one(
+                reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, true, true>), bytes);
+    }
     return rc;
 }
 
@@ -1018,11 +1103,11 @@ size_t owner_dyn_lds_bytes(int op, bool fp32, int K)
     return fp32 ? owner_dyn_lds<float, OpFlux>(K) : owner_dyn_lds<double, OpFlux>(K);
 }
 
-// Dynamic LDS of an owner workgroup; the compact form adds a static table of
-// kCompactMaxNeighbours ints, which the limits below include.
+// LDS of an owner workgroup: the dynamic part plus a static allowance for the
+// compact form's neighbour table and the fused stage's reduction.
 size_t owner_lds_bytes(int op, bool fp32, int K)
 {
-    return owner_dyn_lds_bytes(op, fp32, K) + sizeof(int) * kCompactMaxNeighbours;
+    return owner_dyn_lds_bytes(op, fp32, K) + 2048;
 }
 
 }  // namespace
@@ -1073,6 +1158,13 @@ int launch_edge(int op, bool fp32, int variant, const DevPlan &P, const EdgeArra
         return run_edge<double, OpFlux2>(variant, P, a, gamma, st, lo);
     default: return (int)hipErrorInvalidValue;
     }
+}
+
+int launch_edge_stage(bool fp32, const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
+                      double gamma, double adt, double *ss, hipStream_t st, const LaunchOpts &lo)
+{
+    return fp32 ? run_owner_stage<float>(P, a, na, gamma, adt, ss, st, lo)
+                : run_owner_stage<double>(P, a, na, gamma, adt, ss, st, lo);
 }
 
 template <typename T>

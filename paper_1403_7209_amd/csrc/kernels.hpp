@@ -52,6 +52,7 @@ struct DevPlan {
     const int *nbr_off = nullptr;    // [ncl+1]
     const int *nbr = nullptr;        // neighbour clusters of each cluster, by slot
     // flat colouring: colour c runs edges flat_eid[flat_off[c] .. flat_off[c+1])
+    double *stage_partial = nullptr;  // [ncl][6] partial sums of the fused stage
     int nflat = 0;
     std::vector<int64_t> flat_off;  // host copy [nflat+1]
     const int *flat_eid = nullptr;  // [E]
@@ -91,6 +92,13 @@ constexpr int kRkThreads = 256;
 constexpr int kRkBlocks = 2048;
 int launch_rk_stage(bool fp32, int N, const NodeArrays &a, double alpha_dt, double *ss,
                     double *partial, bool keep_res, hipStream_t stream);
+
+// The owner FP64/FP32 edge-flux loop with the stage update fused into it:
+// q = q0 - adt * res / vol (adt * dt_i when a.dt is set) for every node, and
+// ss[v] += sum res^2 (per-cluster partials, fixed-order second pass); the
+// residual is never written.  The plan must have owner clusters.
+int launch_edge_stage(bool fp32, const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
+                      double gamma, double adt, double *ss, hipStream_t stream, const LaunchOpts &lo);
 
 // dt = min(dt, cfl * min_i vol_i / lam_i); `partial` holds kRkBlocks doubles.
 int launch_dt_min(int N, const double *vol, const double *lam, double cfl, double *dt,

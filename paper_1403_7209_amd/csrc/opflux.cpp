@@ -251,6 +251,13 @@ int upload_plan(opf_ctx *ctx, PlanRec &pr)
             rc = upload(ctx, pr, oe2n, D.oe2n);
         }
         if (!rc && pr.compact) rc = upload_compact(ctx, pr);
+        if (!rc) {
+            D.stage_partial = static_cast<double *>(ctx->dalloc(sizeof(double) * 6 * D.ncl));
+            if (!D.stage_partial)
+                rc = ctx->fail(OPF_ENOMEM, "device allocation of plan arrays failed");
+            else
+                pr.bufs.push_back(D.stage_partial);
+        }
     }
     if (P.flat_ok) {
         D.nflat = P.flat_colours;
@@ -1044,6 +1051,73 @@ int opf_edge_flux2(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat 
                            {res, 1, e2n, 6, OPF_F64, res_access}};
     const opf_gbl g[1] = {{&gamma, 1, OPF_F64, OPF_READ, 0}};
     return opf_par_loop(ctx, OPF_K_EDGE_FLUX2, edges, 10, a, 1, g, variant, stream);
+}
+
+int opf_edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
+                        opf_dat q0, opf_dat vol, opf_dat dt, opf_dat qout, double gamma,
+                        double alpha, double *ss_dev, void *stream)
+{
+    if (!ctx) return OPF_EINVAL;
+    ctx->err.clear();
+    if (!ctx->set_ok(edges) || !ctx->map_ok(e2n)) return ctx->fail(OPF_EINVAL, "invalid handle");
+    const MapRec &mr = ctx->maps[e2n];
+    if (mr.dim != 2 || mr.from != edges)
+        return ctx->fail(OPF_EINVAL, "the loop set must be the source set of an arity-2 map");
+    const opf_set nodes = mr.to;
+    if (!ctx->dat_ok(q)) return ctx->fail(OPF_EINVAL, "argument 0: invalid dat");
+    const int T = ctx->dats[q].type;
+    if (T != OPF_F64 && T != OPF_F32) return ctx->fail(OPF_ETYPE, "argument 0: unknown type");
+    const opf_arg a[7] = {{q, 0, e2n, 6, T, OPF_READ},         {n, -1, OPF_ID, 3, T, OPF_READ},
+                          {q0, -1, OPF_ID, 6, T, OPF_READ},    {vol, -1, OPF_ID, 1, OPF_F64, OPF_READ},
+                          {qout, -1, OPF_ID, 6, T, OPF_WRITE}, {dt, -1, OPF_ID, 1, OPF_F64, OPF_READ},
+                          {q, 1, e2n, 6, T, OPF_READ}};
+    const Want w[7] = {{nodes, 0, e2n, 6, T, OPF_READ},         {edges, -1, OPF_ID, 3, T, OPF_READ},
+                       {nodes, -1, OPF_ID, 6, T, OPF_READ},     {nodes, -1, OPF_ID, 1, OPF_F64, OPF_READ},
+                       {nodes, -1, OPF_ID, 6, T, OPF_WRITE},    {nodes, -1, OPF_ID, 1, OPF_F64, OPF_READ},
+                       {nodes, 1, e2n, 6, T, OPF_READ}};
+    int rc = OPF_OK;
+    for (int k = 0; k < 7 && !rc; ++k) {
+        if (k == 5 && dt < 0) continue;  // no per-node step
+        rc = check_arg(ctx, a[k], w[k], k);
+    }
+    if (rc) return rc;
+    if (qout == q || qout == q0) return ctx->fail(OPF_EINVAL, "qout must not alias q or q0");
+    if (!ss_dev) return ctx->fail(OPF_EINVAL, "ss must be device memory");
+    auto it = ctx->plans.find(e2n);
+    if (it == ctx->plans.end()) return ctx->fail(OPF_ESTATE, "no plan for this map: call opf_plan");
+    PlanRec &pr = *it->second;
+    if (pr.map_version != mr.version) return ctx->fail(OPF_ESTATE, "plan is stale: map re-declared");
+    if (!pr.host.owner_ok) return ctx->fail(OPF_EINVAL, "the fused loop needs owner clusters");
+    rc = device_ready(ctx);
+    if (rc) return rc;
+    if (!pr.on_device) return ctx->fail(OPF_ESTATE, "plan is not on the device");
+    const bool fp32 = T == OPF_F32;
+    const size_t lds = opf::gpu::edge_lds_bytes(opf::gpu::OP_FLUX, fp32, OPF_V_OWNER, pr.dev.umax,
+                                                pr.dev.K);
+    if (lds > ctx->max_lds)
+        return ctx->fail(OPF_EINVAL, "a workgroup needs " + std::to_string(lds) + " B of LDS");
+    if (lds > ctx->lds_limit) {
+        int e = opf::gpu::set_lds_limit(ctx->max_lds);
+        if (e) return hip_fail(ctx, (hipError_t)e, "raising the LDS limit");
+        ctx->lds_limit = ctx->max_lds;
+    }
+    opf::gpu::EdgeArrays ea;
+    const DatRec &qd = ctx->dats[q], &nd = ctx->dats[n];
+    for (int c = 0; c < 6; ++c) ea.xin[c] = comp(qd, c);
+    for (int c = 0; c < 3; ++c) ea.w[c] = comp(nd, c);
+    opf::gpu::NodeArrays na;
+    const DatRec &q0d = ctx->dats[q0], &qod = ctx->dats[qout];
+    for (int c = 0; c < 6; ++c) {
+        na.q0[c] = comp(q0d, c);
+        na.q[c] = (void *)comp(qod, c);
+    }
+    na.vol = static_cast<const double *>(ctx->dats[vol].ptr);
+    if (dt >= 0) na.dt = static_cast<const double *>(ctx->dats[dt].ptr);
+    opf::gpu::LaunchOpts lo;
+    int e = opf::gpu::launch_edge_stage(fp32, pr.dev, ea, na, gamma, alpha, ss_dev,
+                                        static_cast<hipStream_t>(stream), lo);
+    if (e) return hip_fail(ctx, (hipError_t)e, "fused loop launch");
+    return OPF_OK;
 }
 
 int opf_geometry(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x, double period,

@@ -258,6 +258,27 @@ def test_geometry_and_shape_gradient(small):
         assert report(f"shape gradient v{variant}", normwise(p.nodes_out(xs), xs_ref), TOL64)
 
 
+def test_fused_stage_matches_separate_loops(small):
+    """The owner loop with the stage update fused in gives the state and norms
+    of the separate edge loop + stage update (and both the oracle's)."""
+    name, m, q, _ = small
+    dt = oracle.dt(m.e2n, q, m.w, m.vol)
+    q_ref, ss_ref = oracle.rk_iteration(m.e2n, q, m.w, m.vol, dt)
+    for fp32 in (False, True):
+        runs = {}
+        for fused in (True, False):
+            p = problem(m, q, fp32=fp32)
+            p.rk_iteration(dt, pk.OWNER, fused=fused)
+            p.ctx.sync()
+            runs[fused] = (p.nodes_out(p.qa).astype(np.float64), p.rms())
+        tol = 1e-5 if fp32 else 1e-13
+        assert report(f"fused vs separate q fp32={fp32}", normwise(runs[True][0], runs[False][0]), tol)
+        assert report(f"fused vs separate rms fp32={fp32}", normwise(runs[True][1], runs[False][1]), tol)
+        if not fp32:
+            assert report("fused q vs oracle", normwise(runs[True][0], q_ref), TOL64)
+            assert report("fused rms vs oracle", normwise(runs[True][1], np.sqrt(ss_ref / m.N)), TOL64)
+
+
 def test_fp32_storage_stage(small):
     name, m, q, _ = small
     q32 = q.astype(np.float32).astype(np.float64)

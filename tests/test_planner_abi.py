@@ -338,6 +338,18 @@ def test_loop_argument_checks_without_device():
     assert flux(w, variant=pk.FLAT) == pk.EACCESS
     assert flux(good, variant=pk.FLAT) == pk.EDEVICE
     assert flux(good, variant=5) == pk.EINVAL
+    # fused edge loop + stage: signature and aliasing
+    q1 = dat(nodes, 6, pk.F64, 3)
+    vol1s = dat(nodes, 1, pk.F64, 3)
+    ssb = (ctypes.c_double * 6)()
+    assert lib.opf_edge_flux_stage(ctx._ctx, edges, mp, q, n, q, vol1s, -1, q1, 1.4, 0.1,
+                                   ctypes.addressof(ssb), None) == pk.EDEVICE
+    assert lib.opf_edge_flux_stage(ctx._ctx, edges, mp, q, n, q, vol1s, -1, q, 1.4, 0.1,
+                                   ctypes.addressof(ssb), None) == pk.EINVAL  # qout aliases q
+    assert lib.opf_edge_flux_stage(ctx._ctx, edges, mp, q, n, q, q, -1, q1, 1.4, 0.1,
+                                   ctypes.addressof(ssb), None) == pk.ESIZE  # vol of dim 6
+    assert lib.opf_edge_flux_stage(ctx._ctx, edges, mp, q, n, q, vol1s, q1, q1, 1.4, 0.1,
+                                   ctypes.addressof(ssb), None) == pk.ESIZE  # dt of dim 6
     # gradient and second-order loops: signatures
     G = dat(nodes, 18, pk.F64, 3)
     dx = dat(edges, 3, pk.F64, 2)
