@@ -3,7 +3,8 @@
 Workload: the periodic 160^3 box (4,096,000 nodes) split into a layered mix of
 5- and 6-tet cubes (26,624,000 edges), nodes jittered by U(-0.25h, 0.25h) and
 randomly relabelled, then renumbered by the planner.  All inputs are seeded
-and synthetic.
+and synthetic.  `--mesh B` runs the same step on the 1,000,000-node 100^3 box
+of 6-tet cubes jittered by U(-0.2h, 0.2h).
 
 One step = one 5-stage Runge-Kutta iteration in FP64 (5 edge-flux loops + 5
 stage updates with residual norms), the same iteration in the FP32-storage
@@ -55,11 +56,27 @@ BYTES = {  # algorithmic bytes: (per edge, per node[, per tet])
     "geometry": (24, 32, 40),
     # per tet: maps 40; per edge: wbar 24; per node: x 24 + volbar 8 + xbar written 24
     "geometry_adj": (24, 56, 40),
+    "geometry_atomic": (24, 32, 40),
+    "geometry_adj_atomic": (24, 56, 40),
 }
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_1403_7209_amd", "csrc", "kernels.hip")
+# the sources that decide the dominant kernel's traffic: its code and the plan
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_1403_7209_amd", "csrc", f)
+                   for f in ("kernels.hip", "planner.cpp")]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "edge_flux_fp64_owner_E_traffic.txt")
+MESHES = {  # name: (nodes per axis, split, jitter / h, description)
+    "E": (160, 1, 0.25, "layered 5/6-tet mix"),
+    "B": (100, 0, 0.2, "6 tets per cube"),
+}
+
+
+def sources_sha():
+    h = hashlib.sha256()
+    for path in TRAFFIC_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -76,9 +93,7 @@ def measured_traffic(config_key):
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    with open(KERNEL_SRC, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if kv.get("kernels_source_sha256") != sha or kv.get("config") != config_key:
+    if kv.get("sources_sha256") != sources_sha() or kv.get("config") != config_key:
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
@@ -112,10 +127,13 @@ def main():
                     choices=["owner", "coloured", "atomic", "coloured-lds-atomic", "flat"])
     ap.add_argument("--cluster-size", type=int, default=512)
     ap.add_argument("--no-lane-groups", action="store_true")
+    ap.add_argument("--no-bank-spread", action="store_true")
+    ap.add_argument("--no-halo-order", action="store_true")
     ap.add_argument("--renumber", choices=["rcm", "morton", "none"], default="morton")
     ap.add_argument("--block-size", type=int, default=512)
     ap.add_argument("--colour-sort", action="store_true")
-    ap.add_argument("--n", type=int, default=160, help="nodes per axis of the layered box")
+    ap.add_argument("--mesh", choices=sorted(MESHES), default="E",
+                    help="E: 160^3 layered 5/6-tet box (4.1M nodes); B: 100^3 6-tet box (1M nodes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device copy first (calibrates profiler byte counters)")
@@ -139,7 +157,8 @@ def main():
     variant = pk.VARIANTS[args.variant]
 
     t0 = time.perf_counter()
-    mesh = meshgen.build_mesh(args.n, 1, 0.25)
+    mn, msplit, mjit, mdesc = MESHES[args.mesh]
+    mesh = meshgen.build_mesh(mn, msplit, mjit)
     q = meshgen.state(mesh.N, mesh.perm)
     N, E = mesh.N, mesh.E
     log(f"mesh: N={N} E={E} ({time.perf_counter() - t0:.1f} s)")
@@ -151,7 +170,8 @@ def main():
     p64 = pk.FluxProblem(ctx, mesh.e2n, mesh.w, mesh.vol, q, renumber=args.renumber,
                          block_size=args.block_size, colour_sort=args.colour_sort,
                          coords=mesh.xyz, cluster_size=args.cluster_size,
-                         lane_groups=not args.no_lane_groups, tets=t2n, tet_edges=t2e)
+                         lane_groups=not args.no_lane_groups, tets=t2n, tet_edges=t2e,
+                         bank_spread=not args.no_bank_spread, halo_order=not args.no_halo_order)
     T = len(t2n)
     p32 = pk.FluxProblem(ctx, mesh.e2n, mesh.w, mesh.vol, q, fp32=True, like=p64)
     info = p64.info
@@ -292,17 +312,18 @@ def main():
     xbar = torch.empty((3, N), dtype=torch.float64, device=dev)
     for rec in (False, True):
         for _ in range(3 if rec else 1):
-            wg.zero_()
-            volg.zero_()
-            xbar.zero_()
-            a = ev()
-            p64.geometry(x, wg, volg)
-            b = ev()
-            p64.geometry_adjoint(x, nbar, volg, xbar)
-            c = ev()
-            if rec:
-                timers.setdefault("geometry", []).append((a, b))
-                timers.setdefault("geometry_adj", []).append((b, c))
+            for variant, tag in ((pk.OWNER, ""), (pk.ATOMIC, "_atomic")):
+                wg.zero_()
+                volg.zero_()
+                xbar.zero_()
+                a = ev()
+                p64.geometry(x, wg, volg, variant=variant)
+                b = ev()
+                p64.geometry_adjoint(x, nbar, volg, xbar, variant=variant)
+                c = ev()
+                if rec:
+                    timers.setdefault("geometry" + tag, []).append((a, b))
+                    timers.setdefault("geometry_adj" + tag, []).append((b, c))
     torch.cuda.synchronize()
 
     per = {}
@@ -326,9 +347,10 @@ def main():
 
     dom = per[main64]
     be, bn = BYTES[main64]
-    config_key = (f"n={args.n} variant={args.variant} renumber={args.renumber} "
+    config_key = (f"n={mn} variant={args.variant} renumber={args.renumber} "
                   f"cluster={args.cluster_size} block={args.block_size} "
-                  f"lane_groups={not args.no_lane_groups} colour_sort={bool(args.colour_sort)}")
+                  f"lane_groups={not args.no_lane_groups} colour_sort={bool(args.colour_sort)} "
+                  f"bank_spread={not args.no_bank_spread} halo_order={not args.no_halo_order}")
     out = {
         "metric": "edges/s of edge-flux residual loop (FP64, FP32, adjoint) + % HBM roofline",
         "value": round(value, 1),
@@ -343,7 +365,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"periodic {args.n}^3 box, layered 5/6-tet mix, jitter 0.25h: "
+            "workload": f"periodic {mn}^3 box, {mdesc}, jitter {mjit}h: "
                         f"N={N} nodes, E={E} edges; step = FP64 RK5 iteration + FP32-storage "
                         f"RK5 iteration + 1 FP64 adjoint sweep (11 edge loops)",
             "variant": args.variant,
@@ -352,6 +374,8 @@ def main():
             "colour_sort": bool(args.colour_sort),
             "cluster_size": args.cluster_size,
             "lane_groups": not args.no_lane_groups,
+            "bank_spread": not args.no_bank_spread,
+            "halo_order": not args.no_halo_order,
             "plan": {k: info[k] for k in ("nblocks", "nblock_colours", "sum_unique", "max_unique",
                                           "mean_elem_colours", "nclusters", "owner_edge_visits")},
         },

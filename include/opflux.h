@@ -165,7 +165,10 @@ typedef struct {
                               the OWNER variant so that their LDS words fall in
                               distinct banks as far as possible, and choose
                               which end each lane updates first              */
-    int32_t pad;
+    int32_t halo_order;    /* 1: inside each owner cluster, number the interior
+                              nodes first and then the boundary nodes grouped by
+                              the other clusters they are joined to, so that a
+                              neighbour's gathers of them hit contiguous runs   */
     const double *coords;  /* host, SoA 3 x to.size; required for MORTON          */
 } opf_plan_opts;
 
@@ -330,7 +333,10 @@ typedef struct {
  *   q_L = q_i + 1/2 (G_i/vol_i).dx_e and q_R = q_j - 1/2 (G_j/vol_j).dx_e,
  *   dx_e = x_j - x_i; WRITE increments with the OWNER variant as above.
  *  In every edge loop the increment target must not be one of the inputs.
- *  GEOMETRY over tets (ATOMIC variant only):
+ *  GEOMETRY over tets (variant ATOMIC: one thread per tet scattering with
+ *  FP64 atomics, summation order varies; variant OWNER: one thread per edge
+ *  and per node summing over its incident tets in a fixed order, no atomics,
+ *  deterministic; any other variant is OPF_EINVAL):
  *     (x, ALL, t2n, 3, F64, READ) (w, ALL, t2e, 3, F64, INC)
  *     (vol, ALL, t2n, 1, F64, INC) gbl (period, 1, F64, READ, host)
  *   t2n (tets -> nodes, arity 4) lists positively oriented tets; t2e (tets ->
@@ -343,7 +349,7 @@ typedef struct {
  *   volume to each vertex.  period > 0: vertices are unwrapped to the image
  *   nearest vertex 0 in a periodic box of that side.  Summation order is not
  *   fixed (FP64 atomics).
- *  GEOMETRY_ADJ over tets (ATOMIC): (x, ALL, t2n, 3, READ)
+ *  GEOMETRY_ADJ over tets (ATOMIC or OWNER as above): (x, ALL, t2n, 3, READ)
  *     (wbar, ALL, t2e, 3, READ) (volbar, ALL, t2n, 1, READ)
  *     (xbar, ALL, t2n, 3, INC) gbl period
  *   xbar += (dw/dx)^T wbar + (dvol/dx)^T volbar (shape sensitivities when
@@ -404,9 +410,10 @@ int opf_edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf
                         opf_dat q0, opf_dat vol, opf_dat dt, opf_dat qout, double gamma,
                         double alpha, double *ss_dev, void *stream);
 int opf_geometry(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x, double period,
-                 opf_dat w, opf_dat vol, void *stream);
+                 opf_dat w, opf_dat vol, int variant, void *stream);
 int opf_geometry_adjoint(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x,
-                         double period, opf_dat wbar, opf_dat volbar, opf_dat xbar, void *stream);
+                         double period, opf_dat wbar, opf_dat volbar, opf_dat xbar, int variant,
+                         void *stream);
 int opf_rk_stage(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol, opf_dat q,
                  double alpha_dt, double *ss_dev, int res_access, void *stream);
 int opf_rk_stage_local(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol,

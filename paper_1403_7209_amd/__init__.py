@@ -63,7 +63,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("renumber", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("colour_sort", ctypes.c_int32), ("cluster_size", ctypes.c_int32),
                 ("lane_groups", ctypes.c_int32), ("owner_compact", ctypes.c_int32),
-                ("bank_spread", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("bank_spread", ctypes.c_int32), ("halo_order", ctypes.c_int32),
                 ("coords", ctypes.c_void_p)]
 
 
@@ -232,11 +232,13 @@ class Context:
         return out.value
 
     def plan(self, m, renumber="rcm", block_size=512, colour_sort=False, coords=None,
-             cluster_size=512, lane_groups=True, owner_compact=False, bank_spread=True):
+             cluster_size=512, lane_groups=True, owner_compact=False, bank_spread=True,
+             halo_order=True):
         c = None if coords is None else np.ascontiguousarray(coords, dtype=np.float64)
         opts = PlanOpts(RENUMBER[renumber], block_size, 1 if colour_sort else 0, cluster_size,
                         1 if lane_groups else 0, 1 if owner_compact else 0,
-                        1 if bank_spread else 0, 0, None if c is None else c.ctypes.data)
+                        1 if bank_spread else 0, 1 if halo_order else 0,
+                        None if c is None else c.ctypes.data)
         info = PlanInfo()
         self._check(self.lib.opf_plan(self._ctx, m, ctypes.byref(opts), ctypes.byref(info)),
                     "opf_plan")
@@ -376,15 +378,18 @@ class Context:
                                                  _stream_ptr(stream, self.device)),
                     "opf_edge_flux_stage")
 
-    def geometry(self, tets, t2n, t2e, x, w, vol, period=1.0, stream=None):
-        """w (edge dat, 3) and vol (node dat) += median-dual weights and volumes of the tets."""
+    def geometry(self, tets, t2n, t2e, x, w, vol, period=1.0, variant=OWNER, stream=None):
+        """w (edge dat, 3) and vol (node dat) += median-dual weights and volumes of the
+        tets (OWNER: gather over incident tets, deterministic; ATOMIC: scatter)."""
         self._check(self.lib.opf_geometry(self._ctx, tets, t2n, t2e, x, float(period), w, vol,
-                                          _stream_ptr(stream, self.device)), "opf_geometry")
+                                          variant, _stream_ptr(stream, self.device)),
+                    "opf_geometry")
 
-    def geometry_adjoint(self, tets, t2n, t2e, x, wbar, volbar, xbar, period=1.0, stream=None):
+    def geometry_adjoint(self, tets, t2n, t2e, x, wbar, volbar, xbar, period=1.0, variant=OWNER,
+                         stream=None):
         """xbar (node dat, 3) += (dw/dx)^T wbar + (dvol/dx)^T volbar."""
         self._check(self.lib.opf_geometry_adjoint(self._ctx, tets, t2n, t2e, x, float(period),
-                                                  wbar, volbar, xbar,
+                                                  wbar, volbar, xbar, variant,
                                                   _stream_ptr(stream, self.device)),
                     "opf_geometry_adjoint")
 
@@ -435,7 +440,7 @@ class FluxProblem:
     def __init__(self, ctx, e2n, w, vol, q, fp32=False, renumber="rcm", block_size=512,
                  colour_sort=False, coords=None, gamma=1.4, index_base=0, like=None,
                  cluster_size=512, lane_groups=True, tets=None, tet_edges=None,
-                 owner_compact=False, bank_spread=True):
+                 owner_compact=False, bank_spread=True, halo_order=True):
         self.ctx, self.gamma, self.fp32 = ctx, float(gamma), fp32
         if like is not None:  # same mesh, sets, map and plan; other dats
             if like.ctx is not ctx:
@@ -460,7 +465,8 @@ class FluxProblem:
             self.info = ctx.plan(self.e2n, renumber=renumber, block_size=block_size,
                                  colour_sort=colour_sort, coords=coords,
                                  cluster_size=cluster_size, lane_groups=lane_groups,
-                                 owner_compact=owner_compact, bank_spread=bank_spread)
+                                 owner_compact=owner_compact, bank_spread=bank_spread,
+                                 halo_order=halo_order)
             self.node_new = ctx.get_perm(self.nodes, self.N)
             self.edge_new = ctx.get_perm(self.edges, self.E)
         dev = ctx.torch_device
@@ -547,18 +553,19 @@ class FluxProblem:
                               self.ss[k], rk, stream)
         self.qa, self.qb = self.qb, self.qa
 
-    def geometry(self, x_t, w_t, vol_t, period=1.0, stream=None):
+    def geometry(self, x_t, w_t, vol_t, period=1.0, variant=OWNER, stream=None):
         """w_t (3, E) and vol_t (N,) += weights and volumes of the tets at node
         coordinates x_t (3, N); all internal numbering, FP64."""
         self.ctx.geometry(self.tets, self.t2n, self.t2e, self.dat(x_t, "x"),
                           self.dat(w_t, "w", edges=True), self.dat(vol_t[None], "vol_out"),
-                          period, stream)
+                          period, variant, stream)
 
-    def geometry_adjoint(self, x_t, wbar_t, volbar_t, xbar_t, period=1.0, stream=None):
+    def geometry_adjoint(self, x_t, wbar_t, volbar_t, xbar_t, period=1.0, variant=OWNER,
+                         stream=None):
         self.ctx.geometry_adjoint(self.tets, self.t2n, self.t2e, self.dat(x_t, "x"),
                                   self.dat(wbar_t, "wbar", edges=True),
                                   self.dat(volbar_t[None], "volbar"), self.dat(xbar_t, "xbar"),
-                                  period, stream)
+                                  period, variant, stream)
 
     def shape_gradient(self, x_t, rbar_t, period=1.0, variant=COLOURED, stream=None):
         """d(rbar . R(q, w(x)))/dx at the current state (FP64): the flux adjoint
@@ -573,7 +580,7 @@ class FluxProblem:
                                    stream)
         xbar = torch.zeros((3, self.N), dtype=torch.float64, device=dev)
         volbar = torch.zeros(self.N, dtype=torch.float64, device=dev)
-        self.geometry_adjoint(x_t, nbar, volbar, xbar, period, stream)
+        self.geometry_adjoint(x_t, nbar, volbar, xbar, period, OWNER, stream)
         return xbar
 
     def set_edge_vectors(self, dx):

@@ -695,16 +695,6 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
         for (int t = threadIdx.x; t < nn; t += NT) s_nb[t] = p.nb[n0 + t];
         nbt = s_nb;
     }
-    // fused stage: fetch this thread's node's q0 and vol now, so that the
-    // update at the end does not wait for them (one node per thread when K <= NT)
-    [[maybe_unused]] double pq0[6], pvol = 1.0;
-    if constexpr (STAGE) {
-        if (K <= NT && (int)threadIdx.x < nown) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) pq0[k] = (double)ld(sp.q0[k], v0 + (int)threadIdx.x);
-            pvol = ld(sp.vol, v0 + (int)threadIdx.x);
-        }
-    }
     // stage the owned nodes (contiguous ids: coalesced), clear the accumulator
     for (int v = threadIdx.x; v < nown; v += NT) {
         T rec[Op::NS];
@@ -790,6 +780,17 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
             }
         }
     }
+    // fused stage: issue this thread's node's q0 and vol loads before the
+    // barrier, so that they arrive while the slower lanes finish their edges
+    // (one node per thread when K <= NT; held in registers only from here on)
+    [[maybe_unused]] double pq0[6], pvol = 1.0;
+    if constexpr (STAGE) {
+        if (K <= NT && (int)threadIdx.x < nown) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) pq0[k] = (double)ld(sp.q0[k], v0 + (int)threadIdx.x);
+            pvol = ld(sp.vol, v0 + (int)threadIdx.x);
+        }
+    }
     __syncthreads();
     if constexpr (STAGE) {
         double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -858,15 +859,30 @@ __global__ __launch_bounds__(kRkThreads) void k_local_dt(int N, const double *__
         dt[i] = cfl * vol[i] / lam[i];
 }
 
-__global__ __launch_bounds__(256) void k_sum_partials(int nparts, const double *partial,
-                                                      double *ss)
+// ss[0..5] += the sum of nparts rows of 6 partial sums.  One workgroup; each
+// thread owns a fixed set of rows and issues the loads of kSumUnroll rows at
+// once (the kernel is latency-bound), so the order of the additions is fixed.
+constexpr int kSumThreads = 1024, kSumUnroll = 4;
+
+__global__ __launch_bounds__(kSumThreads) void k_sum_partials(int nparts, const double *partial,
+                                                              double *ss)
 {
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int k = threadIdx.x; k < nparts; k += 256)
+    for (int k0 = threadIdx.x; k0 < nparts; k0 += kSumThreads * kSumUnroll) {
+        double r[kSumUnroll][6];
 #pragma unroll
-        for (int v = 0; v < 6; ++v) acc[v] += partial[6 * k + v];
+        for (int u = 0; u < kSumUnroll; ++u) {
+            const int k = k0 + u * kSumThreads;
+#pragma unroll
+            for (int v = 0; v < 6; ++v) r[u][v] = k < nparts ? partial[6 * k + v] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSumUnroll; ++u)
+#pragma unroll
+            for (int v = 0; v < 6; ++v) acc[v] += r[u][v];
+    }
     __shared__ double tot[6];
-    block_sum<6>(acc, tot);
+    block_sum<6, kSumThreads / 64>(acc, tot);
     __syncthreads();
     if (threadIdx.x < 6) ss[threadIdx.x] += tot[threadIdx.x];
 }
@@ -1025,7 +1041,8 @@ int run_owner_stage(const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
         hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, false, true>), dim3(P.ncl),
                            dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
                            lo.xcd_remap, 0, sp);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, P.ncl, P.stage_partial, ss);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSumThreads), 0, st, P.ncl, P.stage_partial,
+                       ss);
     return (int)hipGetLastError();
 }
 
@@ -1182,7 +1199,7 @@ static int run_rk(int N, const NodeArrays &a, double alpha_dt, double *ss, doubl
     const int grid = std::min(kRkBlocks, std::max(1, (N + kRkThreads - 1) / kRkThreads));
     hipLaunchKernelGGL((k_rk_stage<T>), dim3(grid), dim3(kRkThreads), 0, st, N, p, alpha_dt,
                        partial, keep_res ? 1 : 0);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, grid, partial, ss);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSumThreads), 0, st, grid, partial, ss);
     return (int)hipGetLastError();
 }
 

@@ -110,12 +110,21 @@ struct TetArrays {
     const int *t2n = nullptr;
     const int *t2e = nullptr;
     const int2 *e2n = nullptr;
+    // gather form: incident tets of every edge (tet * 8 + local edge) and of
+    // every node (tet * 4 + local vertex), CSR in internal numbering
+    const int *e2t_off = nullptr, *e2t = nullptr;
+    const int *n2t_off = nullptr, *n2t = nullptr;
+    int N = 0, E = 0;
     const double *x[3] = {};
     double *w[3] = {};      // GEOMETRY: weights (INC); ADJ: wbar (read)
     double *vol = nullptr;  // GEOMETRY: volumes (INC); ADJ: volbar (read)
     double *xbar[3] = {};   // ADJ only
 };
-int launch_geometry(bool adjoint, int T, const TetArrays &a, double period, hipStream_t stream);
+// gather = false: one thread per tet, FP64 atomics (summation order varies);
+// gather = true: one thread per edge (weights) and per node (volumes, reverse)
+// summing over the incident tets in a fixed order (deterministic, no atomics).
+int launch_geometry(bool adjoint, bool gather, int T, const TetArrays &a, double period,
+                    hipStream_t stream);
 
 // dt[i] = cfl * vol[i] / lam[i].
 int launch_local_dt(int N, const double *vol, const double *lam, double cfl, double *dt,

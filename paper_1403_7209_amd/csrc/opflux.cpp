@@ -65,6 +65,13 @@ struct DevMap {
     int32_t *ptr = nullptr;
 };
 
+// Incident tets of every edge and node (gather form of the tet loops), keyed
+// by the (t2n, t2e) pair.
+struct DevTetInverse {
+    uint64_t vn = 0, ve = 0;
+    int32_t *e2t_off = nullptr, *e2t = nullptr, *n2t_off = nullptr, *n2t = nullptr;
+};
+
 struct opf_ctx {
     int device = -1;
     std::string err;
@@ -73,6 +80,7 @@ struct opf_ctx {
     std::vector<DatRec> dats;
     std::map<int, std::unique_ptr<PlanRec>> plans;
     std::map<int, DevMap> dmaps;
+    std::map<std::pair<int, int>, DevTetInverse> tinv;
     void *(*alloc_fn)(void *, size_t) = nullptr;
     void (*free_fn)(void *, void *) = nullptr;
     void *alloc_user = nullptr;
@@ -521,6 +529,61 @@ int device_map(opf_ctx *ctx, opf_map m, const int32_t *&out)
     return OPF_OK;
 }
 
+// CSR of the incident (tet, local index) pairs of every element of the map's
+// target set, in internal numbering, packed as tet * stride + local index.
+void invert_map(const opf_ctx *ctx, const MapRec &m, int stride, std::vector<int32_t> &off,
+                std::vector<int32_t> &lst)
+{
+    const std::vector<int32_t> *pf = set_perm(ctx, m.from), *pt = set_perm(ctx, m.to);
+    const int64_t nt = ctx->sets[m.to].size, nf = ctx->sets[m.from].size;
+    off.assign(nt + 1, 0);
+    for (int32_t x : m.idx) ++off[(pt ? (*pt)[x] : x) + 1];
+    for (int64_t i = 0; i < nt; ++i) off[i + 1] += off[i];
+    lst.resize(m.idx.size());
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int64_t t = 0; t < nf; ++t) {
+        const int64_t row = pf ? (*pf)[t] : t;
+        for (int k = 0; k < m.dim; ++k) {
+            const int32_t x = m.idx[(size_t)t * m.dim + k];
+            lst[fill[pt ? (*pt)[x] : x]++] = (int32_t)(row * stride + k);
+        }
+    }
+    if (pf)  // ascending internal tet order within each list
+        for (int64_t i = 0; i < nt; ++i) std::sort(lst.begin() + off[i], lst.begin() + off[i + 1]);
+}
+
+int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, DevTetInverse *&out)
+{
+    DevTetInverse &d = ctx->tinv[std::make_pair((int)t2n, (int)t2e)];
+    const MapRec &mn = ctx->maps[t2n], &me = ctx->maps[t2e];
+    if (d.e2t && d.vn == mn.version && d.ve == me.version) {
+        out = &d;
+        return OPF_OK;
+    }
+    if (ctx->sets[mn.from].size * 8 >= ((int64_t)1 << 31))
+        return ctx->fail(OPF_ESIZE, "too many tets for the gather form");
+    std::vector<int32_t> eo, el, no, nl;
+    invert_map(ctx, me, 8, eo, el);
+    invert_map(ctx, mn, 4, no, nl);
+    for (int32_t *p : {d.e2t_off, d.e2t, d.n2t_off, d.n2t}) ctx->dfree(p);
+    d = DevTetInverse();
+    auto up = [&](const std::vector<int32_t> &v, int32_t *&dst) {
+        dst = static_cast<int32_t *>(ctx->dalloc(v.size() * sizeof(int32_t)));
+        if (!dst) return ctx->fail(OPF_ENOMEM, "device allocation of tet incidence failed");
+        hipError_t e = hipMemcpy(dst, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        return e == hipSuccess ? OPF_OK : hip_fail(ctx, e, "tet incidence upload");
+    };
+    int rc = up(eo, d.e2t_off);
+    if (!rc) rc = up(el, d.e2t);
+    if (!rc) rc = up(no, d.n2t_off);
+    if (!rc) rc = up(nl, d.n2t);
+    if (rc) return rc;
+    d.vn = mn.version;
+    d.ve = me.version;
+    out = &d;
+    return OPF_OK;
+}
+
 int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args, int ngbl,
              const opf_gbl *gbls, int variant, hipStream_t st)
 {
@@ -529,7 +592,9 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
     if (nargs != want_args || !args)
         return ctx->fail(OPF_EINVAL, "expected " + std::to_string(want_args) + " arguments");
     if (ngbl != 1 || !gbls) return ctx->fail(OPF_EINVAL, "expected one global (period)");
-    if (variant != OPF_V_ATOMIC) return ctx->fail(OPF_EINVAL, "the tet loops run as ATOMIC only");
+    if (variant != OPF_V_ATOMIC && variant != OPF_V_OWNER)
+        return ctx->fail(OPF_EINVAL, "the tet loops run as ATOMIC (scatter) or OWNER (gather)");
+    const bool gather = variant == OPF_V_OWNER;
     const opf_map t2n = args[0].map, t2e = args[1].map;
     if (!ctx->map_ok(t2n) || !ctx->map_ok(t2e)) return ctx->fail(OPF_EINVAL, "invalid map");
     const MapRec &mn = ctx->maps[t2n], &me = ctx->maps[t2e];
@@ -564,7 +629,19 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
     opf::gpu::TetArrays ta;
     rc = device_map(ctx, t2n, ta.t2n);
     if (!rc) rc = device_map(ctx, t2e, ta.t2e);
+    if (!rc && gather) {
+        DevTetInverse *inv = nullptr;
+        rc = tet_inverse(ctx, t2n, t2e, inv);
+        if (!rc) {
+            ta.e2t_off = inv->e2t_off;
+            ta.e2t = inv->e2t;
+            ta.n2t_off = inv->n2t_off;
+            ta.n2t = inv->n2t;
+        }
+    }
     if (rc) return rc;
+    ta.N = (int)ctx->sets[nodes].size;
+    ta.E = (int)ctx->sets[edges].size;
     ta.e2n = it->second->dev.e2n;
     const DatRec &x = ctx->dats[args[0].dat], &wd = ctx->dats[args[1].dat];
     const DatRec &vd = ctx->dats[args[2].dat];
@@ -578,7 +655,7 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
         for (int d = 0; d < 3; ++d) ta.xbar[d] = (double *)comp(xb, d);
     }
     const int64_t T = ctx->sets[s].size;
-    int e = opf::gpu::launch_geometry(adj, (int)T, ta, period, st);
+    int e = opf::gpu::launch_geometry(adj, gather, (int)T, ta, period, st);
     if (e) return hip_fail(ctx, (hipError_t)e, "tet loop launch");
     return OPF_OK;
 }
@@ -697,6 +774,12 @@ int opf_finalize(opf_ctx *ctx)
         (void)hipDeviceSynchronize();
         for (auto &kv : ctx->plans) free_plan(ctx, *kv.second);
         for (auto &kv : ctx->dmaps) ctx->dfree(kv.second.ptr);
+        for (auto &kv : ctx->tinv) {
+            ctx->dfree(kv.second.e2t_off);
+            ctx->dfree(kv.second.e2t);
+            ctx->dfree(kv.second.n2t_off);
+            ctx->dfree(kv.second.n2t);
+        }
         ctx->dfree(ctx->scratch);
     }
     delete ctx;
@@ -793,6 +876,7 @@ int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info
         po.cluster_size = opts->cluster_size;
         po.lane_groups = opts->lane_groups;
         po.bank_spread = opts->bank_spread;
+        po.halo_order = opts->halo_order;
         po.coords = opts->coords;
     }
     auto t0 = std::chrono::steady_clock::now();
@@ -1121,18 +1205,19 @@ int opf_edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf
 }
 
 int opf_geometry(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x, double period,
-                 opf_dat w, opf_dat vol, void *stream)
+                 opf_dat w, opf_dat vol, int variant, void *stream)
 {
     if (!ctx) return OPF_EINVAL;
     const opf_arg a[3] = {{x, OPF_ALL, t2n, 3, OPF_F64, OPF_READ},
                           {w, OPF_ALL, t2e, 3, OPF_F64, OPF_INC},
                           {vol, OPF_ALL, t2n, 1, OPF_F64, OPF_INC}};
     const opf_gbl g[1] = {{&period, 1, OPF_F64, OPF_READ, 0}};
-    return opf_par_loop(ctx, OPF_K_GEOMETRY, tets, 3, a, 1, g, OPF_V_ATOMIC, stream);
+    return opf_par_loop(ctx, OPF_K_GEOMETRY, tets, 3, a, 1, g, variant, stream);
 }
 
 int opf_geometry_adjoint(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x,
-                         double period, opf_dat wbar, opf_dat volbar, opf_dat xbar, void *stream)
+                         double period, opf_dat wbar, opf_dat volbar, opf_dat xbar, int variant,
+                         void *stream)
 {
     if (!ctx) return OPF_EINVAL;
     const opf_arg a[4] = {{x, OPF_ALL, t2n, 3, OPF_F64, OPF_READ},
@@ -1140,7 +1225,7 @@ int opf_geometry_adjoint(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, o
                           {volbar, OPF_ALL, t2n, 1, OPF_F64, OPF_READ},
                           {xbar, OPF_ALL, t2n, 3, OPF_F64, OPF_INC}};
     const opf_gbl g[1] = {{&period, 1, OPF_F64, OPF_READ, 0}};
-    return opf_par_loop(ctx, OPF_K_GEOMETRY_ADJ, tets, 4, a, 1, g, OPF_V_ATOMIC, stream);
+    return opf_par_loop(ctx, OPF_K_GEOMETRY_ADJ, tets, 4, a, 1, g, variant, stream);
 }
 
 int opf_rk_stage_local(opf_ctx *ctx, opf_set nodes, opf_dat q0, opf_dat res, opf_dat vol,

@@ -306,6 +306,37 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
         std::iota(P.node_new.begin(), P.node_new.end(), 0);
     }
 
+    // (1b) inside each owner cluster, interior nodes first, then the nodes on
+    // the cluster's boundary grouped by the other clusters they are joined to:
+    // a neighbouring cluster then gathers its halo from a few contiguous runs
+    // of each state component instead of scattered words
+    if (K > 0 && opt.halo_order) {
+        std::vector<int32_t> fmin(N, INT32_MAX), fmax(N, -1);
+        for (int64_t e = 0; e < E; ++e) {
+            const int32_t a = P.node_new[e2n_user[2 * e]], b = P.node_new[e2n_user[2 * e + 1]];
+            const int32_t ca = a / K, cb = b / K;
+            if (ca == cb) continue;
+            fmin[a] = std::min(fmin[a], cb);
+            fmax[a] = std::max(fmax[a], cb);
+            fmin[b] = std::min(fmin[b], ca);
+            fmax[b] = std::max(fmax[b], ca);
+        }
+        std::vector<int32_t> relabel(N);
+        const int64_t ncl = (N + K - 1) / K;
+        parallel_for(ncl, [&](int64_t c) {
+            const int32_t lo = (int32_t)(c * K), hi = (int32_t)std::min<int64_t>(N, (c + 1) * K);
+            std::vector<int32_t> v(hi - lo);
+            std::iota(v.begin(), v.end(), lo);
+            std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) {
+                if ((fmax[x] >= 0) != (fmax[y] >= 0)) return fmax[x] < 0;
+                if (fmin[x] != fmin[y]) return fmin[x] < fmin[y];
+                return fmax[x] < fmax[y];
+            });
+            for (int32_t k = 0; k < hi - lo; ++k) relabel[v[k]] = lo + k;
+        });
+        for (int64_t i = 0; i < N; ++i) P.node_new[i] = relabel[P.node_new[i]];
+    }
+
     lap(0);
     // (2) relabel and order edges by (min, max) internal node: counting sort by
     // the smaller endpoint, then by the larger one inside each bucket.

@@ -25,6 +25,8 @@ struct PlanOptions {
                                      // 64 edges that share no node
     int bank_spread = 1;             // place the edges of every 64-visit wavefront chunk
                                      // on lanes so their LDS words fall in distinct banks
+    int halo_order = 1;              // inside each cluster: interior nodes first, then
+                                     // boundary nodes grouped by the clusters they border
     const double *coords = nullptr;  // SoA 3 x N
 };
 

@@ -121,20 +121,25 @@ def test_geometry_full(mesh_e):
     ctx = pk.Context(DEV)
     p = pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, coords=m.xyz, tets=t2n, tet_edges=t2e, **BENCH)
     x = p.nodes_in(m.xyz)
-    w = torch.zeros((3, m.E), dtype=torch.float64, device=DEV)
-    vol = torch.zeros(m.N, dtype=torch.float64, device=DEV)
-    p.geometry(x, w, vol)
-    p.ctx.sync()
-    assert report("E geometry w", normwise(p.nodes_out(w, edges=True), w_ref), 1e-12)
-    assert report("E geometry vol", normwise(p.nodes_out(vol[None]), vol_ref[None]), 1e-12)
     rng = np.random.default_rng(42)
     wbar = rng.normal(size=(3, m.E))
     xb_ref = oracle.geometry_adjoint(m.e2n, t2n, t2e, m.xyz, wbar, np.zeros(m.N))
-    xbar = torch.zeros((3, m.N), dtype=torch.float64, device=DEV)
-    p.geometry_adjoint(x, p.nodes_in(wbar, edges=True),
-                       torch.zeros(m.N, dtype=torch.float64, device=DEV), xbar)
-    p.ctx.sync()
-    assert report("E geometry xbar", normwise(p.nodes_out(xbar), xb_ref), 1e-12)
+    wbar_d = p.nodes_in(wbar, edges=True)
+    for variant in (pk.OWNER, pk.ATOMIC):
+        w = torch.zeros((3, m.E), dtype=torch.float64, device=DEV)
+        vol = torch.zeros(m.N, dtype=torch.float64, device=DEV)
+        p.geometry(x, w, vol, variant=variant)
+        p.ctx.sync()
+        assert report(f"E geometry w v{variant}", normwise(p.nodes_out(w, edges=True), w_ref),
+                      1e-12)
+        assert report(f"E geometry vol v{variant}",
+                      normwise(p.nodes_out(vol[None]), vol_ref[None]), 1e-12)
+        del w, vol
+        xbar = torch.zeros((3, m.N), dtype=torch.float64, device=DEV)
+        p.geometry_adjoint(x, wbar_d, torch.zeros(m.N, dtype=torch.float64, device=DEV), xbar,
+                           variant=variant)
+        p.ctx.sync()
+        assert report(f"E geometry xbar v{variant}", normwise(p.nodes_out(xbar), xb_ref), 1e-12)
 
 
 def test_adjoint_sampled_full(prob_e, mesh_e):

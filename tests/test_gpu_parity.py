@@ -234,20 +234,34 @@ def test_geometry_and_shape_gradient(small):
     p = pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, renumber="morton", coords=m.xyz,
                        tets=t2n, tet_edges=t2e)
     x = p.nodes_in(m.xyz)
-    w = torch.zeros((3, m.E), dtype=torch.float64, device=DEV)
-    vol = torch.zeros(m.N, dtype=torch.float64, device=DEV)
-    p.geometry(x, w, vol)
-    p.ctx.sync()
-    assert report("geometry w", normwise(p.nodes_out(w, edges=True), w_ref), TOL64)
-    assert report("geometry vol", normwise(p.nodes_out(vol[None]), vol_ref[None]), TOL64)
     rng = np.random.default_rng(41)
     wbar, volbar = rng.normal(size=(3, m.E)), rng.normal(size=m.N)
     xb_ref = oracle.geometry_adjoint(m.e2n, t2n, t2e, m.xyz, wbar, volbar)
-    xbar = torch.zeros((3, m.N), dtype=torch.float64, device=DEV)
-    p.geometry_adjoint(x, p.nodes_in(wbar, edges=True), p.nodes_in(volbar[None])[0].contiguous(),
-                       xbar)
+    for variant in (pk.OWNER, pk.ATOMIC):
+        # the loop increments: start from values of the result's size (the mesh's
+        # own weights and volumes), so that taking them off again loses nothing
+        w0, vol0 = p.nodes_in(m.w, edges=True), p.nodes_in(m.vol[None])[0].contiguous()
+        w, vol = w0.clone(), vol0.clone()
+        p.geometry(x, w, vol, variant=variant)
+        p.ctx.sync()
+        assert report(f"geometry w v{variant}", normwise(p.nodes_out(w - w0, edges=True), w_ref),
+                      TOL64)
+        assert report(f"geometry vol v{variant}",
+                      normwise(p.nodes_out((vol - vol0)[None]), vol_ref[None]), TOL64)
+        xbar = torch.zeros((3, m.N), dtype=torch.float64, device=DEV)
+        p.geometry_adjoint(x, p.nodes_in(wbar, edges=True),
+                           p.nodes_in(volbar[None])[0].contiguous(), xbar, variant=variant)
+        p.ctx.sync()
+        assert report(f"geometry xbar v{variant}", normwise(p.nodes_out(xbar), xb_ref), TOL64)
+    # the gather form sums in a fixed order: repeated calls agree bit for bit
+    w1 = torch.zeros((3, m.E), dtype=torch.float64, device=DEV)
+    w2 = torch.zeros((3, m.E), dtype=torch.float64, device=DEV)
+    v1 = torch.zeros(m.N, dtype=torch.float64, device=DEV)
+    v2 = torch.zeros(m.N, dtype=torch.float64, device=DEV)
+    p.geometry(x, w1, v1)
+    p.geometry(x, w2, v2)
     p.ctx.sync()
-    assert report("geometry xbar", normwise(p.nodes_out(xbar), xb_ref), TOL64)
+    assert torch.equal(w1, w2) and torch.equal(v1, v2)
     # shape sensitivities of rbar . R(q, w(x))
     rbar = rng.normal(size=(6, m.N))
     _, nbar = oracle.adjoint(m.e2n, q, m.w, rbar)

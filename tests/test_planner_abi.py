@@ -222,6 +222,50 @@ def test_bank_spreading_cuts_lds_bank_conflicts():
     assert out[True] < 0.5 * out[False]
 
 
+def halo_lines(m, node_new, K, L=16):
+    """Distinct L-node lines of one state component that the clusters' foreign
+    gathers touch, and the number of (cluster, foreign node) pairs."""
+    a, b = node_new[m.e2n[:, 0]].astype(np.int64), node_new[m.e2n[:, 1]].astype(np.int64)
+    cut = a // K != b // K
+    g = np.concatenate([a[cut] // K, b[cut] // K])
+    f = np.concatenate([b[cut], a[cut]])
+    pairs = np.unique(g * m.N + f)
+    return np.unique((pairs // m.N) * (m.N // L + 1) + (pairs % m.N) // L).size, pairs.size
+
+
+def test_halo_order_groups_boundary_nodes():
+    m = meshgen.build_mesh(24, 1, 0.25)
+    K = 512
+    lines = {}
+    for ho in (False, True):
+        ctx, nodes, edges, mp, info = host_problem(m, renumber="morton", cluster_size=K,
+                                                   halo_order=ho)
+        assert ctx.plan_verify(mp)["ok"]
+        check_plan_properties(m, ctx, nodes, edges, mp)
+        node_new = ctx.get_perm(nodes, m.N)
+        lines[ho] = halo_lines(m, node_new, K)
+        if not ho:
+            base = node_new
+            continue
+        # the same clusters, only relabelled inside each one
+        assert np.array_equal(base // K, node_new // K)
+        # inside each cluster: interior nodes first, then boundary nodes in order of
+        # (smallest, largest) other cluster they are joined to
+        a, b = node_new[m.e2n[:, 0]], node_new[m.e2n[:, 1]]
+        fmin = np.full(m.N, np.iinfo(np.int64).max)
+        fmax = np.full(m.N, -1)
+        cut = a // K != b // K
+        for x, y in ((a, b), (b, a)):
+            np.minimum.at(fmin, x[cut], y[cut] // K)
+            np.maximum.at(fmax, x[cut], y[cut] // K)
+        key = np.where(fmax < 0, -1, fmin) * (m.N // K + 2) + np.where(fmax < 0, -1, fmax)
+        for c0 in range(0, m.N, K):
+            k = key[c0:c0 + K]
+            assert np.all(k[1:] >= k[:-1]), f"cluster at {c0} not grouped"
+    assert lines[True][1] == lines[False][1]  # same halos
+    assert lines[True][0] < 0.8 * lines[False][0]
+
+
 def test_declaration_errors():
     ctx = pk.Context(None)
     with pytest.raises(pk.OpfError) as e:
@@ -405,15 +449,20 @@ def test_tet_loop_checks_without_device():
 
     ctx_size = {nodes: m.N, edges: m.E, tets: len(t2n)}
     x, w, vol, xb = dat(nodes, 3), dat(edges, 3), dat(nodes, 1), dat(nodes, 3)
+    O, A = pk.OWNER, pk.ATOMIC
     # before the plan the edges have no orientation map on the device
-    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, vol, None) == pk.ESTATE
+    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, vol, O, None) == pk.ESTATE
     ctx.plan(mp, block_size=256, cluster_size=256)
-    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, vol, None) == pk.EDEVICE
-    assert lib.opf_geometry(ctx._ctx, tets, te, tn, x, 1.0, w, vol, None) == pk.EINVAL  # swapped
-    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, -1.0, w, vol, None) == pk.EINVAL
-    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, x, None) == pk.ESIZE  # vol dim 3
-    assert lib.opf_geometry_adjoint(ctx._ctx, tets, tn, te, x, 1.0, w, vol, xb, None) == pk.EDEVICE
-    assert lib.opf_geometry_adjoint(ctx._ctx, tets, tn, te, x, 1.0, w, vol, x, None) == pk.EINVAL
+    for v in (O, A):
+        assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, vol, v, None) == pk.EDEVICE
+    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, vol, pk.FLAT, None) == pk.EINVAL
+    assert lib.opf_geometry(ctx._ctx, tets, te, tn, x, 1.0, w, vol, O, None) == pk.EINVAL  # swapped
+    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, -1.0, w, vol, O, None) == pk.EINVAL
+    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, x, O, None) == pk.ESIZE  # vol dim 3
+    assert lib.opf_geometry_adjoint(ctx._ctx, tets, tn, te, x, 1.0, w, vol, xb, O,
+                                    None) == pk.EDEVICE
+    assert lib.opf_geometry_adjoint(ctx._ctx, tets, tn, te, x, 1.0, w, vol, x, O,
+                                    None) == pk.EINVAL
     a = (pk.Arg * 3)(pk.Arg(x, pk.ALL, tn, 3, pk.F64, pk.READ), pk.Arg(w, pk.ALL, te, 3, pk.F64, pk.INC),
                      pk.Arg(vol, pk.ALL, tn, 1, pk.F64, pk.INC))
     period = ctypes.c_double(1.0)
