@@ -69,6 +69,7 @@ struct DevMap {
 // by the (t2n, t2e) pair.
 struct DevTetInverse {
     uint64_t vn = 0, ve = 0;
+    int32_t *t2n = nullptr, *t2e = nullptr;  // tets in the gather order
     int32_t *e2t_off = nullptr, *e2t = nullptr, *n2t_off = nullptr, *n2t = nullptr;
 };
 
@@ -529,29 +530,11 @@ int device_map(opf_ctx *ctx, opf_map m, const int32_t *&out)
     return OPF_OK;
 }
 
-// CSR of the incident (tet, local index) pairs of every element of the map's
-// target set, in internal numbering, packed as tet * stride + local index.
-void invert_map(const opf_ctx *ctx, const MapRec &m, int stride, std::vector<int32_t> &off,
-                std::vector<int32_t> &lst)
-{
-    const std::vector<int32_t> *pf = set_perm(ctx, m.from), *pt = set_perm(ctx, m.to);
-    const int64_t nt = ctx->sets[m.to].size, nf = ctx->sets[m.from].size;
-    off.assign(nt + 1, 0);
-    for (int32_t x : m.idx) ++off[(pt ? (*pt)[x] : x) + 1];
-    for (int64_t i = 0; i < nt; ++i) off[i + 1] += off[i];
-    lst.resize(m.idx.size());
-    std::vector<int32_t> fill(off.begin(), off.end() - 1);
-    for (int64_t t = 0; t < nf; ++t) {
-        const int64_t row = pf ? (*pf)[t] : t;
-        for (int k = 0; k < m.dim; ++k) {
-            const int32_t x = m.idx[(size_t)t * m.dim + k];
-            lst[fill[pt ? (*pt)[x] : x]++] = (int32_t)(row * stride + k);
-        }
-    }
-    if (pf)  // ascending internal tet order within each list
-        for (int64_t i = 0; i < nt; ++i) std::sort(lst.begin() + off[i], lst.begin() + off[i + 1]);
-}
-
+// The gather form's copies of the tet maps: tets reordered by their lowest
+// internal vertex (so that the tets around a node or an edge sit close
+// together), both maps in internal numbering, and the CSR lists of the
+// (tet, local index) pairs of every edge and node in that tet order,
+// packed as tet * 8 + local edge and tet * 4 + local vertex.
 int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, DevTetInverse *&out)
 {
     DevTetInverse &d = ctx->tinv[std::make_pair((int)t2n, (int)t2e)];
@@ -560,12 +543,53 @@ int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, DevTetInverse *&out)
         out = &d;
         return OPF_OK;
     }
-    if (ctx->sets[mn.from].size * 8 >= ((int64_t)1 << 31))
-        return ctx->fail(OPF_ESIZE, "too many tets for the gather form");
+    const int64_t T = ctx->sets[mn.from].size, N = ctx->sets[mn.to].size,
+                  E = ctx->sets[me.to].size;
+    if (T * 8 >= ((int64_t)1 << 31)) return ctx->fail(OPF_ESIZE, "too many tets for the gather form");
+    const std::vector<int32_t> *pn = set_perm(ctx, mn.to), *pe = set_perm(ctx, me.to);
+    // counting sort of the tets by their lowest internal vertex
+    std::vector<int64_t> cnt(N + 1, 0);
+    std::vector<int32_t> lowest(T);
+    for (int64_t t = 0; t < T; ++t) {
+        int32_t lo = INT32_MAX;
+        for (int v = 0; v < 4; ++v) {
+            const int32_t x = mn.idx[t * 4 + v];
+            lo = std::min(lo, pn ? (*pn)[x] : x);
+        }
+        lowest[t] = lo;
+        ++cnt[lo + 1];
+    }
+    for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> ord(T);
+    for (int64_t t = 0; t < T; ++t) ord[cnt[lowest[t]]++] = (int32_t)t;
+    std::vector<int32_t>().swap(lowest);
+    std::vector<int32_t> tn(T * 4), te(T * 6);
+    for (int64_t k = 0; k < T; ++k) {
+        const int64_t t = ord[k];
+        for (int v = 0; v < 4; ++v) {
+            const int32_t x = mn.idx[t * 4 + v];
+            tn[k * 4 + v] = pn ? (*pn)[x] : x;
+        }
+        for (int j = 0; j < 6; ++j) {
+            const int32_t x = me.idx[t * 6 + j];
+            te[k * 6 + j] = pe ? (*pe)[x] : x;
+        }
+    }
+    std::vector<int32_t>().swap(ord);
+    auto invert = [](const std::vector<int32_t> &m, int dim, int stride, int64_t n,
+                     std::vector<int32_t> &off, std::vector<int32_t> &lst) {
+        off.assign(n + 1, 0);
+        for (int32_t x : m) ++off[x + 1];
+        for (int64_t i = 0; i < n; ++i) off[i + 1] += off[i];
+        lst.resize(m.size());
+        std::vector<int32_t> fill(off.begin(), off.end() - 1);
+        for (size_t k = 0; k < m.size(); ++k)  // ascending tet order within each list
+            lst[fill[m[k]]++] = (int32_t)((k / dim) * stride + k % dim);
+    };
     std::vector<int32_t> eo, el, no, nl;
-    invert_map(ctx, me, 8, eo, el);
-    invert_map(ctx, mn, 4, no, nl);
-    for (int32_t *p : {d.e2t_off, d.e2t, d.n2t_off, d.n2t}) ctx->dfree(p);
+    invert(te, 6, 8, E, eo, el);
+    invert(tn, 4, 4, N, no, nl);
+    for (int32_t *p : {d.t2n, d.t2e, d.e2t_off, d.e2t, d.n2t_off, d.n2t}) ctx->dfree(p);
     d = DevTetInverse();
     auto up = [&](const std::vector<int32_t> &v, int32_t *&dst) {
         dst = static_cast<int32_t *>(ctx->dalloc(v.size() * sizeof(int32_t)));
@@ -573,7 +597,9 @@ int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, DevTetInverse *&out)
         hipError_t e = hipMemcpy(dst, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
         return e == hipSuccess ? OPF_OK : hip_fail(ctx, e, "tet incidence upload");
     };
-    int rc = up(eo, d.e2t_off);
+    int rc = up(tn, d.t2n);
+    if (!rc) rc = up(te, d.t2e);
+    if (!rc) rc = up(eo, d.e2t_off);
     if (!rc) rc = up(el, d.e2t);
     if (!rc) rc = up(no, d.n2t_off);
     if (!rc) rc = up(nl, d.n2t);
@@ -627,17 +653,20 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
     if (rc) return rc;
     if (!it->second->on_device) return ctx->fail(OPF_ESTATE, "plan is not on the device");
     opf::gpu::TetArrays ta;
-    rc = device_map(ctx, t2n, ta.t2n);
-    if (!rc) rc = device_map(ctx, t2e, ta.t2e);
-    if (!rc && gather) {
+    if (gather) {
         DevTetInverse *inv = nullptr;
         rc = tet_inverse(ctx, t2n, t2e, inv);
         if (!rc) {
+            ta.t2n = inv->t2n;
+            ta.t2e = inv->t2e;
             ta.e2t_off = inv->e2t_off;
             ta.e2t = inv->e2t;
             ta.n2t_off = inv->n2t_off;
             ta.n2t = inv->n2t;
         }
+    } else {
+        rc = device_map(ctx, t2n, ta.t2n);
+        if (!rc) rc = device_map(ctx, t2e, ta.t2e);
     }
     if (rc) return rc;
     ta.N = (int)ctx->sets[nodes].size;
@@ -775,6 +804,8 @@ int opf_finalize(opf_ctx *ctx)
         for (auto &kv : ctx->plans) free_plan(ctx, *kv.second);
         for (auto &kv : ctx->dmaps) ctx->dfree(kv.second.ptr);
         for (auto &kv : ctx->tinv) {
+            ctx->dfree(kv.second.t2n);
+            ctx->dfree(kv.second.t2e);
             ctx->dfree(kv.second.e2t_off);
             ctx->dfree(kv.second.e2t);
             ctx->dfree(kv.second.n2t_off);
