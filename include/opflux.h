@@ -334,9 +334,12 @@ typedef struct {
  *   dx_e = x_j - x_i; WRITE increments with the OWNER variant as above.
  *  In every edge loop the increment target must not be one of the inputs.
  *  GEOMETRY over tets (variant ATOMIC: one thread per tet scattering with
- *  FP64 atomics, summation order varies; variant OWNER: one thread per edge
- *  and per node summing over its incident tets in a fixed order, no atomics,
- *  deterministic; any other variant is OPF_EINVAL):
+ *  FP64 atomics, summation order varies; variant OWNER: each tet's results
+ *  go to a library-owned device scratch buffer of 152 bytes per tet, then
+ *  each edge and node sums over its incident tets in a fixed order: no
+ *  atomics, deterministic.  The first OWNER call on a pair of tet maps
+ *  builds the incidence lists and the buffer, kept until the maps are
+ *  declared again or opf_finalize; any other variant is OPF_EINVAL):
  *     (x, ALL, t2n, 3, F64, READ) (w, ALL, t2e, 3, F64, INC)
  *     (vol, ALL, t2n, 1, F64, INC) gbl (period, 1, F64, READ, host)
  *   t2n (tets -> nodes, arity 4) lists positively oriented tets; t2e (tets ->
@@ -347,8 +350,7 @@ typedef struct {
  *   edge (p, q) with (p, q, r, s) an even permutation of the vertices, to w
  *   (signed from the edge's first to its second node) and a quarter of its
  *   volume to each vertex.  period > 0: vertices are unwrapped to the image
- *   nearest vertex 0 in a periodic box of that side.  Summation order is not
- *   fixed (FP64 atomics).
+ *   nearest vertex 0 in a periodic box of that side.
  *  GEOMETRY_ADJ over tets (ATOMIC or OWNER as above): (x, ALL, t2n, 3, READ)
  *     (wbar, ALL, t2e, 3, READ) (volbar, ALL, t2n, 1, READ)
  *     (xbar, ALL, t2n, 3, INC) gbl period

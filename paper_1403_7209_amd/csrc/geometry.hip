@@ -10,10 +10,12 @@
 // the device, and their reverse, lets the flux adjoint's weight sensitivities
 // reach the node coordinates.
 //
-// One thread per tet; the six face vectors and four volume quarters go to HBM
-// with FP64 atomic adds (a tet's edges and vertices are shared with its
-// neighbours).  The loop runs once per mesh (or once per design step for the
-// reverse), so it is priced by its gathers, not tuned like the edge loops.
+// Two forms.  Scatter: one thread per tet adds its six face vectors and four
+// volume quarters (or, in reverse, its four x-bar shares) to HBM with FP64
+// atomics.  Gather: one thread per tet writes those results to a scratch
+// buffer, then one thread per edge or node sums its incident tets' entries in
+// a fixed order: no atomics, the same bits on every run.  The loop runs once
+// per mesh (or once per design step for the reverse).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -157,51 +159,39 @@ __global__ __launch_bounds__(256) void k_geometry_adj(int T, TetArrays a, double
 }
 
 // ---------------------------------------------------------- gather form -- */
+//
+// Phase 1, one thread per tet (tets in the order of the incidence lists, so
+// the map reads coalesce): the tet's results go to the scratch buffer as one
+// record per tet.  Phase 2, one thread per edge or node: the sum over its
+// incident tets, in list order; the tets around an edge or a node are close
+// in that order, so their records share cache lines.
 
-// Face vector of local edge k of tet t, oriented from local vertex p to q.
-__device__ __forceinline__ void face_vector(const double x[4][3], int k, double c[3])
+// record of tet t (kTetScratch doubles at t * kTetScratch): the signed face
+// vector of local edge k / 24 at 3k + d, the volume determinant / 24 at 18
+__global__ __launch_bounds__(256) void k_tet_forward(int T, TetArrays a, double period)
 {
-    const int p = kTetEdge[k][0], q = kTetEdge[k][1], r = kTetEdge[k][2], s = kTetEdge[k][3];
-    double u[3], v[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        u[d] = x[r][d] + x[s][d] - x[p][d] - x[q][d];
-        v[d] = x[s][d] - x[r][d];
-    }
-    cross3(u, v, c);
-}
-
-__device__ __forceinline__ void load_tet(const TetArrays &a, int t, double period, int g[4],
-                                         double x[4][3])
-{
+    const int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (t >= T) return;
+    int g[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) g[v] = a.t2n[4 * t + v];
+    double x[4][3];
     tet_x(a, g, period, x);
-}
-
-// w[e] = sum over the tets around edge e of the dual-face vector, in CSR order.
-__global__ __launch_bounds__(256) void k_geometry_w(TetArrays a, double period)
-{
-    const int e = (int)blockIdx.x * 256 + (int)threadIdx.x;
-    if (e >= a.E) return;
-    const int2 ij = a.e2n[e];
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int j = a.e2t_off[e]; j < a.e2t_off[e + 1]; ++j) {
-        const int tk = a.e2t[j], t = tk >> 3, k = tk & 7;
-        int g[4];
-        double x[4][3], c[3];
-        load_tet(a, t, period, g, x);
-        face_vector(x, k, c);
-        const double sg = g[kTetEdge[k][0]] == ij.x ? 1.0 : -1.0;
+    double *rec = a.scratch + (size_t)t * kTetScratch;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) acc[d] += sg * c[d];
+    for (int k = 0; k < 6; ++k) {
+        const int p = kTetEdge[k][0], q = kTetEdge[k][1], r = kTetEdge[k][2], s = kTetEdge[k][3];
+        double u[3], v[3], c[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            u[d] = x[r][d] + x[s][d] - x[p][d] - x[q][d];
+            v[d] = x[s][d] - x[r][d];
+        }
+        cross3(u, v, c);
+        const double sg = orient(a.e2n, a.t2e[6 * t + k], g[p]) * (1.0 / 24.0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) rec[3 * k + d] = sg * c[d];
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) a.w[d][e] += acc[d] * (1.0 / 24.0);
-}
-
-__device__ __forceinline__ double tet_det(const double x[4][3])
-{
     double e1[3], e2[3], e3[3], c[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -210,78 +200,108 @@ __device__ __forceinline__ double tet_det(const double x[4][3])
         e3[d] = x[3][d] - x[0][d];
     }
     cross3(e2, e3, c);
-    return e1[0] * c[0] + e1[1] * c[1] + e1[2] * c[2];
+    rec[18] = (e1[0] * c[0] + e1[1] * c[1] + e1[2] * c[2]) * (1.0 / 24.0);
 }
 
-// vol[i] = sum over the tets around node i of a quarter of the tet volume.
-__global__ __launch_bounds__(256) void k_geometry_vol(TetArrays a, double period)
+// w[e] += sum over the tets around e of their face vector of e
+__global__ __launch_bounds__(256) void k_edge_sum_faces(TetArrays a)
+{
+    const int e = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (e >= a.E) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int j = a.e2t_off[e]; j < a.e2t_off[e + 1]; ++j) {
+        const int tk = a.e2t[j];
+        const double *rec = a.scratch + (size_t)(tk >> 3) * kTetScratch + 3 * (tk & 7);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc[d] += rec[d];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.w[d][e] += acc[d];
+}
+
+// vol[i] += sum over the tets around i of a quarter of their volume
+__global__ __launch_bounds__(256) void k_node_sum_vol(TetArrays a)
 {
     const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
     if (i >= a.N) return;
     double acc = 0.0;
-    for (int j = a.n2t_off[i]; j < a.n2t_off[i + 1]; ++j) {
-        int g[4];
-        double x[4][3];
-        load_tet(a, a.n2t[j] >> 2, period, g, x);
-        acc += tet_det(x);
-    }
-    a.vol[i] += acc * (1.0 / 24.0);
+    for (int j = a.n2t_off[i]; j < a.n2t_off[i + 1]; ++j)
+        acc += a.scratch[(size_t)(a.n2t[j] >> 2) * kTetScratch + 18];
+    a.vol[i] += acc;
 }
 
-// xbar[i] = sum over the tets around node i of that vertex's share of the
-// tet's reverse (all six faces and the volume), recomputed per vertex.
-__global__ __launch_bounds__(256) void k_geometry_adj_gather(TetArrays a, double period)
+// record of tet t (12 doubles at t * 12): its share of x-bar at local vertex v
+// at 3v + d
+__global__ __launch_bounds__(256) void k_tet_reverse(int T, TetArrays a, double period)
+{
+    const int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (t >= T) return;
+    int g[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) g[v] = a.t2n[4 * t + v];
+    double x[4][3], xb[4][3];
+    tet_x(a, g, period, x);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xb[v][d] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int p = kTetEdge[k][0], q = kTetEdge[k][1], r = kTetEdge[k][2], s = kTetEdge[k][3];
+        const int ed = a.t2e[6 * t + k];
+        const double sg = orient(a.e2n, ed, g[p]) * (1.0 / 24.0);
+        double u[3], v[3], cb[3], ub[3], vb[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            u[d] = x[r][d] + x[s][d] - x[p][d] - x[q][d];
+            v[d] = x[s][d] - x[r][d];
+            cb[d] = sg * a.w[d][ed];
+        }
+        cross3(v, cb, ub);
+        cross3(cb, u, vb);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            xb[p][d] -= ub[d];
+            xb[q][d] -= ub[d];
+            xb[r][d] += ub[d] - vb[d];
+            xb[s][d] += ub[d] + vb[d];
+        }
+    }
+    const double Vb = 0.25 * (a.vol[g[0]] + a.vol[g[1]] + a.vol[g[2]] + a.vol[g[3]]) * (1.0 / 6.0);
+    double e1[3], e2[3], e3[3], c1[3], c2[3], c3[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        e1[d] = x[1][d] - x[0][d];
+        e2[d] = x[2][d] - x[0][d];
+        e3[d] = x[3][d] - x[0][d];
+    }
+    cross3(e2, e3, c1);
+    cross3(e3, e1, c2);
+    cross3(e1, e2, c3);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        xb[1][d] += Vb * c1[d];
+        xb[2][d] += Vb * c2[d];
+        xb[3][d] += Vb * c3[d];
+        xb[0][d] -= Vb * (c1[d] + c2[d] + c3[d]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.scratch[(size_t)t * 12 + 3 * v + d] = xb[v][d];
+}
+
+// xbar[i] += sum over the tets around i of their share at i
+__global__ __launch_bounds__(256) void k_node_sum_xbar(TetArrays a)
 {
     const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
     if (i >= a.N) return;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int j = a.n2t_off[i]; j < a.n2t_off[i + 1]; ++j) {
-        const int t = a.n2t[j] >> 2, me = a.n2t[j] & 3;
-        int g[4];
-        double x[4][3];
-        load_tet(a, t, period, g, x);
+        const int tv = a.n2t[j];
+        const double *rec = a.scratch + (size_t)(tv >> 2) * 12 + 3 * (tv & 3);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const int p = kTetEdge[k][0], q = kTetEdge[k][1], r = kTetEdge[k][2], s = kTetEdge[k][3];
-            // this vertex's coefficient in u = x_r + x_s - x_p - x_q and v = x_s - x_r
-            const double cu = (me == r || me == s) ? 1.0 : -1.0;
-            const double cv = me == s ? 1.0 : me == r ? -1.0 : 0.0;
-            const int ed = a.t2e[6 * t + k];
-            const double sg = (a.e2n[ed].x == g[p] ? 1.0 : -1.0) * (1.0 / 24.0);
-            double u[3], v[3], cb[3], ub[3], vb[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                u[d] = x[r][d] + x[s][d] - x[p][d] - x[q][d];
-                v[d] = x[s][d] - x[r][d];
-                cb[d] = sg * a.w[d][ed];
-            }
-            cross3(v, cb, ub);
-            cross3(cb, u, vb);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) acc[d] += cu * ub[d] + cv * vb[d];
-        }
-        const double Vb =
-            0.25 * (a.vol[g[0]] + a.vol[g[1]] + a.vol[g[2]] + a.vol[g[3]]) * (1.0 / 6.0);
-        double e1[3], e2[3], e3[3], c[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            e1[d] = x[1][d] - x[0][d];
-            e2[d] = x[2][d] - x[0][d];
-            e3[d] = x[3][d] - x[0][d];
-        }
-        if (me == 1) cross3(e2, e3, c);
-        else if (me == 2) cross3(e3, e1, c);
-        else if (me == 3) cross3(e1, e2, c);
-        else {
-            double c1[3], c2[3], c3[3];
-            cross3(e2, e3, c1);
-            cross3(e3, e1, c2);
-            cross3(e1, e2, c3);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) c[d] = -(c1[d] + c2[d] + c3[d]);
-        }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) acc[d] += Vb * c[d];
+        for (int d = 0; d < 3; ++d) acc[d] += rec[d];
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) a.xbar[d][i] += acc[d];
@@ -294,12 +314,14 @@ int launch_geometry(bool adjoint, bool gather, int T, const TetArrays &a, double
 {
     if (T <= 0) return 0;
     if (gather) {
+        const dim3 gt((T + 255) / 256), ge((a.E + 255) / 256), gn((a.N + 255) / 256);
         if (adjoint) {
-            hipLaunchKernelGGL(k_geometry_adj_gather, dim3((a.N + 255) / 256), dim3(256), 0, st, a,
-                               period);
+            hipLaunchKernelGGL(k_tet_reverse, gt, dim3(256), 0, st, T, a, period);
+            hipLaunchKernelGGL(k_node_sum_xbar, gn, dim3(256), 0, st, a);
         } else {
-            hipLaunchKernelGGL(k_geometry_w, dim3((a.E + 255) / 256), dim3(256), 0, st, a, period);
-            hipLaunchKernelGGL(k_geometry_vol, dim3((a.N + 255) / 256), dim3(256), 0, st, a, period);
+            hipLaunchKernelGGL(k_tet_forward, gt, dim3(256), 0, st, T, a, period);
+            hipLaunchKernelGGL(k_edge_sum_faces, ge, dim3(256), 0, st, a);
+            hipLaunchKernelGGL(k_node_sum_vol, gn, dim3(256), 0, st, a);
         }
         return (int)hipGetLastError();
     }

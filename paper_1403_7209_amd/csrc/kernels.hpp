@@ -104,8 +104,8 @@ int launch_edge_stage(bool fp32, const DevPlan &P, const EdgeArrays &a, const No
 int launch_dt_min(int N, const double *vol, const double *lam, double cfl, double *dt,
                   double *partial, hipStream_t stream);
 
-// Tet loops (one thread per tet, FP64 atomics).  t2n [4T] and t2e [6T] in
-// internal numbering; e2n orients the edges.  Pointers are SoA components.
+// Tet loops.  t2n [4T] and t2e [6T] in internal numbering; e2n orients the
+// edges.  Pointers are SoA components.
 struct TetArrays {
     const int *t2n = nullptr;
     const int *t2e = nullptr;
@@ -114,15 +114,20 @@ struct TetArrays {
     // every node (tet * 4 + local vertex), CSR in internal numbering
     const int *e2t_off = nullptr, *e2t = nullptr;
     const int *n2t_off = nullptr, *n2t = nullptr;
+    double *scratch = nullptr;  // gather form: kTetScratch x T doubles
     int N = 0, E = 0;
     const double *x[3] = {};
     double *w[3] = {};      // GEOMETRY: weights (INC); ADJ: wbar (read)
     double *vol = nullptr;  // GEOMETRY: volumes (INC); ADJ: volbar (read)
     double *xbar[3] = {};   // ADJ only
 };
+// Per-tet results of the gather form: 6 signed face vectors + 1 volume
+// determinant (forward) or 4 vertex shares of x-bar (reverse, 12 values).
+constexpr int kTetScratch = 19;
 // gather = false: one thread per tet, FP64 atomics (summation order varies);
-// gather = true: one thread per edge (weights) and per node (volumes, reverse)
-// summing over the incident tets in a fixed order (deterministic, no atomics).
+// gather = true: one thread per tet writes its results to the scratch
+// buffer, then one thread per edge (weights) and per node (volumes, reverse)
+// sums them over the incident tets in a fixed order (deterministic, no atomics).
 int launch_geometry(bool adjoint, bool gather, int T, const TetArrays &a, double period,
                     hipStream_t stream);
 

@@ -71,6 +71,7 @@ struct DevTetInverse {
     uint64_t vn = 0, ve = 0;
     int32_t *t2n = nullptr, *t2e = nullptr;  // tets in the gather order
     int32_t *e2t_off = nullptr, *e2t = nullptr, *n2t_off = nullptr, *n2t = nullptr;
+    double *scratch = nullptr;  // kTetScratch values per tet
 };
 
 struct opf_ctx {
@@ -534,7 +535,8 @@ int device_map(opf_ctx *ctx, opf_map m, const int32_t *&out)
 // internal vertex (so that the tets around a node or an edge sit close
 // together), both maps in internal numbering, and the CSR lists of the
 // (tet, local index) pairs of every edge and node in that tet order,
-// packed as tet * 8 + local edge and tet * 4 + local vertex.
+// packed as tet * 8 + local edge and tet * 4 + local vertex; plus the scratch
+// buffer of the per-tet results (kTetScratch doubles per tet).
 int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, DevTetInverse *&out)
 {
     DevTetInverse &d = ctx->tinv[std::make_pair((int)t2n, (int)t2e)];
@@ -590,6 +592,7 @@ int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, DevTetInverse *&out)
     invert(te, 6, 8, E, eo, el);
     invert(tn, 4, 4, N, no, nl);
     for (int32_t *p : {d.t2n, d.t2e, d.e2t_off, d.e2t, d.n2t_off, d.n2t}) ctx->dfree(p);
+    ctx->dfree(d.scratch);
     d = DevTetInverse();
     auto up = [&](const std::vector<int32_t> &v, int32_t *&dst) {
         dst = static_cast<int32_t *>(ctx->dalloc(v.size() * sizeof(int32_t)));
@@ -604,6 +607,9 @@ int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, DevTetInverse *&out)
     if (!rc) rc = up(no, d.n2t_off);
     if (!rc) rc = up(nl, d.n2t);
     if (rc) return rc;
+    d.scratch = static_cast<double *>(
+        ctx->dalloc((size_t)T * opf::gpu::kTetScratch * sizeof(double)));
+    if (!d.scratch) return ctx->fail(OPF_ENOMEM, "device allocation of the tet scratch failed");
     d.vn = mn.version;
     d.ve = me.version;
     out = &d;
@@ -663,6 +669,7 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
             ta.e2t = inv->e2t;
             ta.n2t_off = inv->n2t_off;
             ta.n2t = inv->n2t;
+            ta.scratch = inv->scratch;
         }
     } else {
         rc = device_map(ctx, t2n, ta.t2n);
@@ -804,6 +811,7 @@ int opf_finalize(opf_ctx *ctx)
         for (auto &kv : ctx->plans) free_plan(ctx, *kv.second);
         for (auto &kv : ctx->dmaps) ctx->dfree(kv.second.ptr);
         for (auto &kv : ctx->tinv) {
+            ctx->dfree(kv.second.scratch);
             ctx->dfree(kv.second.t2n);
             ctx->dfree(kv.second.t2e);
             ctx->dfree(kv.second.e2t_off);

@@ -4,6 +4,8 @@ the FP64 oracle: whole arrays where the oracle finishes in seconds, sampled
 outputs computed one by one where it does not (the adjoint), and properties
 that hold at any size for the 100-iteration FP32 trajectory.
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -222,3 +224,57 @@ def test_fp32_trajectory_100_iterations():
     print(f"  FP32 vs FP64 state error every 20 iterations: {errs}", flush=True)
     assert max(errs) <= 1e-5
     assert ctx.check_finite(p64.ss) and ctx.check_finite(p32.ss)
+
+
+def test_adjoint_config_d():
+    """The adjoint on the 1M-node jittered box: a dot-product test against the
+    oracle's forward JVP on random directions, and central differences of the
+    GPU residual in the weights of 64 random edges (step 1e-6 of the weight
+    vector's length: the flux is homogeneous of degree one in it)."""
+    print("[1M-node jittered box: adjoint dot product and central differences]", flush=True)
+    m = meshgen.config_mesh("D")
+    q = meshgen.state(m.N, m.perm)
+    ctx = pk.Context(DEV)
+    p = pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, coords=m.xyz, **BENCH)
+    rbar = meshgen.normal(6 * m.N, purpose=31).reshape(6, m.N)
+    dq = meshgen.normal(6 * m.N, purpose=32).reshape(6, m.N) * np.abs(q).max(axis=1, keepdims=True)
+    dw = meshgen.normal(3 * m.E, purpose=33).reshape(3, m.E) * np.abs(m.w).max()
+    qbar = torch.empty((6, m.N), dtype=torch.float64, device=DEV)
+    nbar = torch.empty((3, m.E), dtype=torch.float64, device=DEV)
+    ctx.edge_flux_adjoint(p.edges, p.e2n, p.dat(p.qa), p.w, p.dat(p.nodes_in(rbar)), p.dat(qbar),
+                          p.dat(nbar, edges=True), p.gamma, pk.OWNER, pk.WRITE)
+    ctx.sync()
+    qbar_h, nbar_h = p.nodes_out(qbar), p.nodes_out(nbar, edges=True)
+    # <rbar, J (dq, dw)> = <qbar, dq> + <nbar, dw>
+    jv = oracle.jvp(m.e2n, q, m.w, dq, dw)
+    lhs = math.fsum((rbar * jv).ravel())
+    rhs = math.fsum((qbar_h * dq).ravel()) + math.fsum((nbar_h * dw).ravel())
+    rel = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
+    print(f"  dot product: {lhs:.15e} vs {rhs:.15e}, relative {rel:.3e}", flush=True)
+    assert rel <= 1e-10
+    # central differences of rbar . R(q, w) in single weights, formed from the two
+    # nodes the edge touches (the residual changes nowhere else)
+    rng = np.random.default_rng(65)
+    edges = rng.choice(m.E, 64, replace=False)
+    res = torch.empty((6, m.N), dtype=torch.float64, device=DEV)
+    fd, ad = [], []
+    for e in edges:
+        i, j = m.e2n[e]
+        ii, jj = p.node_new[i], p.node_new[j]
+        k = int(rng.integers(3))
+        ew = int(p.edge_new[e])
+        w0 = float(p.w_t[k, ew])
+        h = 1e-6 * float(np.linalg.norm(m.w[:, e]))  # relative to the weight's size
+        vals = []
+        for s in (1.0, -1.0):
+            p.w_t[k, ew] = w0 + s * h
+            p.residual(p.qa, res, pk.OWNER, pk.WRITE)
+            r = res[:, [ii, jj]].cpu().numpy()
+            vals.append(rbar[:, i] @ r[:, 0] + rbar[:, j] @ r[:, 1])
+        p.w_t[k, ew] = w0
+        fd.append((vals[0] - vals[1]) / (2 * h))
+        ad.append(nbar_h[k, e])
+    fd, ad = np.array(fd), np.array(ad)
+    err = np.abs(fd - ad).max() / np.abs(ad).max()
+    print(f"  central differences on 64 edge weights: max relative error {err:.3e}", flush=True)
+    assert err <= 1e-6
