@@ -648,6 +648,43 @@ __device__ __forceinline__ void block_sum(double (&acc)[NV], double *out)
     }
 }
 
+// out[0..5] = the sums over the workgroup's NT threads of acc[0..5], through
+// LDS (buf: 6 * NT doubles, free for this use) in a fixed tree: 64 lanes x 8,
+// then 8, then the last 8.  Three LDS rounds instead of the 36 dependent
+// cross-lane shuffles of a wavefront reduction of six doubles.
+template <int NT>
+__device__ __forceinline__ void lds_sum6(const double (&acc)[6], double *buf, double *out)
+{
+    static_assert(NT == 512, "the tree is laid out for 512 threads");
+    const int t = threadIdx.x;
+    __syncthreads();  // buf may still be read
+#pragma unroll
+    for (int k = 0; k < 6; ++k) buf[k * NT + t] = acc[k];
+    __syncthreads();
+    if (t < 6 * 64) {
+        const int k = t >> 6, j = t & 63;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) s += buf[k * NT + j + 64 * i];
+        buf[k * NT + j] = s;
+    }
+    __syncthreads();
+    if (t < 6 * 8) {
+        const int k = t >> 3, j = t & 7;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += buf[k * NT + j + 8 * i];
+        buf[k * NT + j] = s;
+    }
+    __syncthreads();
+    if (t < 6) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += buf[t * NT + i];
+        out[t] = s;
+    }
+}
+
 // ------------------------------------------------------- owner kernel -- */
 
 // One workgroup per cluster of K consecutive nodes.  It runs every edge with
@@ -807,7 +844,14 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
                 st(sp.q[k], g, (T)(base - adt * r / vi));
             }
         }
-        block_sum<6, NT / 64>(acc, sp.partial + 6 * c);
+        bool done = false;
+        if constexpr (NT == 512) {
+            if (K >= NT) {  // the accumulators hold 6 * NT doubles
+                lds_sum6<NT>(acc, sy, sp.partial + 6 * c);
+                done = true;
+            }
+        }
+        if (!done) block_sum<6, NT / 64>(acc, sp.partial + 6 * c);
     } else {
         for (int v = threadIdx.x; v < nown; v += NT) {
 #pragma unroll
