@@ -80,10 +80,11 @@ __device__ __forceinline__ float tabs(float x) { return fabsf(x); }
 
 // F = 1/2 (f(q_i) + f(q_j)).n - 1/2 lambda (q_j - q_i),
 // lambda = |1/2 (U_i + U_j)| + 1/2 (c_i + c_j) |n|, U = u.n; +F to node i,
-// -F to node j.  Staged record: rho, u[0..2], rho E, rho phi, p, c (the
-// momentum is rebuilt as rho u).
+// -F to node j.  Staged record: rho, u[0..2], rho E, rho phi, c (the
+// momentum is rebuilt as rho u, the pressure as rho c^2 / gamma: seven values
+// per node keep three FP64 owner workgroups within one CU's LDS).
 struct OpFlux {
-    static constexpr int NIN = 6, NS = 8, NOUT = 6, NW = 3, NWOUT = 0, MODE = ANTI;
+    static constexpr int NIN = 6, NS = 7, NOUT = 6, NW = 3, NWOUT = 0, MODE = ANTI;
     template <typename T>
     __device__ static __forceinline__ void stage(const T *x, T *s, T gamma)
     {
@@ -95,8 +96,7 @@ struct OpFlux {
         s[4] = x[4];
         s[5] = x[5];
         const T p = (gamma - T(1)) * (x[4] - T(0.5) * (x[1] * s[1] + x[2] * s[2] + x[3] * s[3]));
-        s[6] = p;
-        s[7] = tsqrt(gamma * p * ir);
+        s[6] = tsqrt(gamma * p * ir);
     }
     template <typename T>
     __device__ static __forceinline__ void edge(const T *a, const T *b, const T *n, T gamma,
@@ -106,14 +106,16 @@ struct OpFlux {
         const T Ua = a[1] * n[0] + a[2] * n[1] + a[3] * n[2];
         const T Ub = b[1] * n[0] + b[2] * n[1] + b[3] * n[2];
         const T nn = tsqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        const T hl = h * (tabs(h * (Ua + Ub)) + h * (a[7] + b[7]) * nn);
+        const T hl = h * (tabs(h * (Ua + Ub)) + h * (a[6] + b[6]) * nn);
         const T ma = a[0] * Ua, mb = b[0] * Ub;  // mass fluxes
-        const T pp = a[6] + b[6];
+        const T ig = T(1) / gamma;
+        const T pa = a[0] * a[6] * a[6] * ig, pb = b[0] * b[6] * b[6] * ig;
+        const T pp = pa + pb;
         yi[0] = (double)(h * (ma + mb) - hl * (b[0] - a[0]));
         yi[1] = (double)(h * (ma * a[1] + mb * b[1] + pp * n[0]) - hl * (b[0] * b[1] - a[0] * a[1]));
         yi[2] = (double)(h * (ma * a[2] + mb * b[2] + pp * n[1]) - hl * (b[0] * b[2] - a[0] * a[2]));
         yi[3] = (double)(h * (ma * a[3] + mb * b[3] + pp * n[2]) - hl * (b[0] * b[3] - a[0] * a[3]));
-        yi[4] = (double)(h * ((a[4] + a[6]) * Ua + (b[4] + b[6]) * Ub) - hl * (b[4] - a[4]));
+        yi[4] = (double)(h * ((a[4] + pa) * Ua + (b[4] + pb) * Ub) - hl * (b[4] - a[4]));
         yi[5] = (double)(h * (a[5] * Ua + b[5] * Ub) - hl * (b[5] - a[5]));
     }
 };
@@ -421,43 +423,75 @@ __device__ __forceinline__ void load_stage(const Arrays<T> &a, int g, T gamma, T
     Op::stage(x, s, gamma);
 }
 
-// LDS node records of NS values (NS * sizeof(T) a multiple of 16 bytes) are
-// kept as W planes of 16-byte words: plane k holds word k of every record.  A
-// wavefront gathering records of random nodes then spreads each 16-byte read
-// over all 8 word positions of the 128-byte LDS row, and every read is one
-// ds_read_b128.  Accumulators are NOUT planes of doubles.
+// LDS node records of NS values are kept as planes: W16 planes of 16-byte
+// words (plane k holds word k of every record), then at most one plane of
+// 8-byte and one of 4-byte words for the rest of the record.  A wavefront
+// gathering records of random nodes then spreads each 16-byte read over all 8
+// word positions of the 128-byte LDS row, and every read is one ds_read_b128
+// (b64, b32 for the tail planes).  Accumulators are NOUT planes of doubles.
 template <typename T, int NS>
 struct Rec {
-    static_assert((NS * sizeof(T)) % 16 == 0, "record must be a multiple of 16 bytes");
-    static constexpr int W = NS * (int)sizeof(T) / 16;
+    static constexpr int B = NS * (int)sizeof(T);
+    static_assert(B % 4 == 0, "records are whole 4-byte words");
+    static constexpr int W16 = B / 16, W8 = (B % 16) / 8, W4 = (B % 8) / 4;
 };
 
 template <typename T, int NS>
 __device__ __forceinline__ void lds_get(const T *base, int rows, int idx, T *out)
 {
-    constexpr int W = Rec<T, NS>::W;
-    const uint4 *src = reinterpret_cast<const uint4 *>(base);
-    uint4 tmp[W];
+    using R = Rec<T, NS>;
+    alignas(16) unsigned char tmp[R::B];
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(base);
 #pragma unroll
-    for (int k = 0; k < W; ++k) tmp[k] = src[k * rows + idx];
-    __builtin_memcpy(out, tmp, sizeof(tmp));
+    for (int k = 0; k < R::W16; ++k) {
+        const uint4 w = reinterpret_cast<const uint4 *>(b)[k * rows + idx];
+        __builtin_memcpy(tmp + 16 * k, &w, 16);
+    }
+    b += (size_t)16 * R::W16 * rows;
+    if constexpr (R::W8) {
+        const uint2 w = reinterpret_cast<const uint2 *>(b)[idx];
+        __builtin_memcpy(tmp + 16 * R::W16, &w, 8);
+        b += (size_t)8 * rows;
+    }
+    if constexpr (R::W4) {
+        const unsigned w = reinterpret_cast<const unsigned *>(b)[idx];
+        __builtin_memcpy(tmp + 16 * R::W16 + 8 * R::W8, &w, 4);
+    }
+    __builtin_memcpy(out, tmp, R::B);
 }
 
 template <typename T, int NS>
 __device__ __forceinline__ void lds_put(T *base, int rows, int idx, const T *in)
 {
-    constexpr int W = Rec<T, NS>::W;
-    uint4 tmp[W];
-    __builtin_memcpy(tmp, in, sizeof(tmp));
-    uint4 *dst = reinterpret_cast<uint4 *>(base);
+    using R = Rec<T, NS>;
+    alignas(16) unsigned char tmp[R::B];
+    __builtin_memcpy(tmp, in, R::B);
+    unsigned char *b = reinterpret_cast<unsigned char *>(base);
 #pragma unroll
-    for (int k = 0; k < W; ++k) dst[k * rows + idx] = tmp[k];
+    for (int k = 0; k < R::W16; ++k) {
+        uint4 w;
+        __builtin_memcpy(&w, tmp + 16 * k, 16);
+        reinterpret_cast<uint4 *>(b)[k * rows + idx] = w;
+    }
+    b += (size_t)16 * R::W16 * rows;
+    if constexpr (R::W8) {
+        uint2 w;
+        __builtin_memcpy(&w, tmp + 16 * R::W16, 8);
+        reinterpret_cast<uint2 *>(b)[idx] = w;
+        b += (size_t)8 * rows;
+    }
+    if constexpr (R::W4) {
+        unsigned w;
+        __builtin_memcpy(&w, tmp + 16 * R::W16 + 8 * R::W8, 4);
+        reinterpret_cast<unsigned *>(b)[idx] = w;
+    }
 }
 
+// LDS bytes of `rows` records, rounded up to 16 (the accumulators follow).
 template <typename T, class Op>
 __host__ __device__ constexpr size_t stage_bytes(int rows)
 {
-    return (size_t)Rec<T, Op::NS>::W * 16 * rows;
+    return ((size_t)Rec<T, Op::NS>::B * rows + 15) / 16 * 16;
 }
 
 template <typename T, class Op>
@@ -925,10 +959,34 @@ __global__ __launch_bounds__(kSumThreads) void k_sum_partials(int nparts, const 
 #pragma unroll
             for (int v = 0; v < 6; ++v) acc[v] += r[u][v];
     }
-    __shared__ double tot[6];
-    block_sum<6, kSumThreads / 64>(acc, tot);
+    // fixed tree through LDS: 64 lanes x 16 per component, then 8 x 8, then 8
+    __shared__ double buf[6 * kSumThreads];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) buf[v * kSumThreads + t] = acc[v];
     __syncthreads();
-    if (threadIdx.x < 6) ss[threadIdx.x] += tot[threadIdx.x];
+    if (t < 6 * 64) {
+        const int v = t >> 6, j = t & 63;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < kSumThreads / 64; ++i) s += buf[v * kSumThreads + j + 64 * i];
+        buf[v * kSumThreads + j] = s;
+    }
+    __syncthreads();
+    if (t < 6 * 8) {
+        const int v = t >> 3, j = t & 7;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += buf[v * kSumThreads + j + 8 * i];
+        buf[v * kSumThreads + j] = s;
+    }
+    __syncthreads();
+    if (t < 6) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += buf[t * kSumThreads + i];
+        ss[t] += s;
+    }
 }
 
 template <int NV>
