@@ -120,7 +120,9 @@ def tet_edges(mesh, tets):
     for k, (a, b) in enumerate(TET_LOCAL_EDGES):
         p, q = tets[:, a].astype(np.int64), tets[:, b].astype(np.int64)
         want = np.minimum(p, q) * mesh.N + np.maximum(p, q)
-        pos = np.searchsorted(skey, want)
+        wo = np.argsort(want)  # sorted queries keep the binary searches in cache
+        pos = np.empty_like(wo)
+        pos[wo] = np.searchsorted(skey, want[wo])
         if np.any(pos >= len(skey)) or np.any(skey[np.minimum(pos, len(skey) - 1)] != want):
             raise ValueError("a tet edge is missing from the edge list")
         out[:, k] = order[pos]
