@@ -166,8 +166,9 @@ __global__ __launch_bounds__(256) void k_geometry_adj(int T, TetArrays a, double
 // incident tets, in list order; the tets around an edge or a node are close
 // in that order, so their records share cache lines.
 
-// record of tet t (kTetScratch doubles at t * kTetScratch): the signed face
-// vector of local edge k / 24 at 3k + d, the volume determinant / 24 at 18
+// record of tet t: the signed face vector of local edge k / 24 at
+// scratch[18 t + 3k + d]; the volume determinant / 24 at scratch[18 T + t] (an
+// array of its own, so that the per-node sums read 16 tets per cache line)
 __global__ __launch_bounds__(256) void k_tet_forward(int T, TetArrays a, double period)
 {
     const int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(256) void k_tet_forward(int T, TetArrays a, double 
     for (int v = 0; v < 4; ++v) g[v] = a.t2n[4 * t + v];
     double x[4][3];
     tet_x(a, g, period, x);
-    double *rec = a.scratch + (size_t)t * kTetScratch;
+    double *rec = a.scratch + (size_t)t * 18;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const int p = kTetEdge[k][0], q = kTetEdge[k][1], r = kTetEdge[k][2], s = kTetEdge[k][3];
@@ -200,8 +201,12 @@ __global__ __launch_bounds__(256) void k_tet_forward(int T, TetArrays a, double 
         e3[d] = x[3][d] - x[0][d];
     }
     cross3(e2, e3, c);
-    rec[18] = (e1[0] * c[0] + e1[1] * c[1] + e1[2] * c[2]) * (1.0 / 24.0);
+    a.scratch[(size_t)18 * T + t] = (e1[0] * c[0] + e1[1] * c[1] + e1[2] * c[2]) * (1.0 / 24.0);
 }
+
+// The sums below walk a list in order; they fetch kSumAhead entries at a
+// time (these loops are latency-bound) and add them in list order.
+constexpr int kSumAhead = 4;
 
 // w[e] += sum over the tets around e of their face vector of e
 __global__ __launch_bounds__(256) void k_edge_sum_faces(TetArrays a)
@@ -209,24 +214,45 @@ __global__ __launch_bounds__(256) void k_edge_sum_faces(TetArrays a)
     const int e = (int)blockIdx.x * 256 + (int)threadIdx.x;
     if (e >= a.E) return;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int j = a.e2t_off[e]; j < a.e2t_off[e + 1]; ++j) {
-        const int tk = a.e2t[j];
-        const double *rec = a.scratch + (size_t)(tk >> 3) * kTetScratch + 3 * (tk & 7);
+    const int end = a.e2t_off[e + 1];
+    for (int j = a.e2t_off[e]; j < end; j += kSumAhead) {
+        double r[kSumAhead][3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) acc[d] += rec[d];
+        for (int u = 0; u < kSumAhead; ++u) {
+            // past the end of the list: re-read its first entry (always valid)
+            const int tk = a.e2t[j + u < end ? j + u : j];
+            const double *rec = a.scratch + (size_t)(tk >> 3) * 18 + 3 * (tk & 7);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) r[u][d] = rec[d];
+        }
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u)
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                if (j + u < end) acc[d] += r[u][d];
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) a.w[d][e] += acc[d];
 }
 
 // vol[i] += sum over the tets around i of a quarter of their volume
-__global__ __launch_bounds__(256) void k_node_sum_vol(TetArrays a)
+__global__ __launch_bounds__(256) void k_node_sum_vol(int T, TetArrays a)
 {
     const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
     if (i >= a.N) return;
+    const double *det = a.scratch + (size_t)18 * T;
     double acc = 0.0;
-    for (int j = a.n2t_off[i]; j < a.n2t_off[i + 1]; ++j)
-        acc += a.scratch[(size_t)(a.n2t[j] >> 2) * kTetScratch + 18];
+    const int end = a.n2t_off[i + 1];
+    for (int j = a.n2t_off[i]; j < end; j += kSumAhead) {
+        double r[kSumAhead];
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u) {
+            r[u] = det[a.n2t[j + u < end ? j + u : j] >> 2];
+        }
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u)
+            if (j + u < end) acc += r[u];
+    }
     a.vol[i] += acc;
 }
 
@@ -297,11 +323,21 @@ __global__ __launch_bounds__(256) void k_node_sum_xbar(TetArrays a)
     const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
     if (i >= a.N) return;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int j = a.n2t_off[i]; j < a.n2t_off[i + 1]; ++j) {
-        const int tv = a.n2t[j];
-        const double *rec = a.scratch + (size_t)(tv >> 2) * 12 + 3 * (tv & 3);
+    const int end = a.n2t_off[i + 1];
+    for (int j = a.n2t_off[i]; j < end; j += kSumAhead) {
+        double r[kSumAhead][3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) acc[d] += rec[d];
+        for (int u = 0; u < kSumAhead; ++u) {
+            const int tv = a.n2t[j + u < end ? j + u : j];
+            const double *rec = a.scratch + (size_t)(tv >> 2) * 12 + 3 * (tv & 3);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) r[u][d] = rec[d];
+        }
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u)
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                if (j + u < end) acc[d] += r[u][d];
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) a.xbar[d][i] += acc[d];
@@ -321,7 +357,7 @@ int launch_geometry(bool adjoint, bool gather, int T, const TetArrays &a, double
         } else {
             hipLaunchKernelGGL(k_tet_forward, gt, dim3(256), 0, st, T, a, period);
             hipLaunchKernelGGL(k_edge_sum_faces, ge, dim3(256), 0, st, a);
-            hipLaunchKernelGGL(k_node_sum_vol, gn, dim3(256), 0, st, a);
+            hipLaunchKernelGGL(k_node_sum_vol, gn, dim3(256), 0, st, T, a);
         }
         return (int)hipGetLastError();
     }

@@ -121,8 +121,9 @@ struct TetArrays {
     double *vol = nullptr;  // GEOMETRY: volumes (INC); ADJ: volbar (read)
     double *xbar[3] = {};   // ADJ only
 };
-// Per-tet results of the gather form: 6 signed face vectors + 1 volume
-// determinant (forward) or 4 vertex shares of x-bar (reverse, 12 values).
+// Per-tet results of the gather form: 6 signed face vectors (18 values at
+// 18 t) + 1 volume determinant (at 18 T + t) forward, or 4 vertex shares of
+// x-bar (12 values at 12 t) in reverse.
 constexpr int kTetScratch = 19;
 // gather = false: one thread per tet, FP64 atomics (summation order varies);
 // gather = true: one thread per tet writes its results to the scratch
