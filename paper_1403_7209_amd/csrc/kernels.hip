@@ -47,6 +47,21 @@
 #ifndef OPF_ADJ_WAVES
 #define OPF_ADJ_WAVES 0
 #endif
+// The gradient and second-order loops hold 24 or more values per node in LDS:
+// one workgroup per CU, so their workgroups take more threads (NT) instead
+// (1024 and 768: the second-order loop spills registers at 1024).
+#ifndef OPF_GRAD_BATCH
+#define OPF_GRAD_BATCH 2
+#endif
+#ifndef OPF_GRAD_THREADS
+#define OPF_GRAD_THREADS 1024
+#endif
+#ifndef OPF_FLUX2_BATCH
+#define OPF_FLUX2_BATCH 2
+#endif
+#ifndef OPF_FLUX2_THREADS
+#define OPF_FLUX2_THREADS 768
+#endif
 
 namespace opf {
 namespace gpu {
@@ -312,23 +327,23 @@ struct OpFlux2 {
 
 template <typename T, class Op>
 struct OwnerTune {
-    static constexpr int B = 2, WAVES = 0;
+    static constexpr int B = 2, WAVES = 0, NT = kOwnerThreads;
 };
 template <>
 struct OwnerTune<double, OpFlux> {
-    static constexpr int B = OPF_FLUX64_BATCH, WAVES = OPF_FLUX64_WAVES;
+    static constexpr int B = OPF_FLUX64_BATCH, WAVES = OPF_FLUX64_WAVES, NT = kOwnerThreads;
 };
 template <>
 struct OwnerTune<double, OpAdjoint> {
-    static constexpr int B = OPF_ADJ_BATCH, WAVES = OPF_ADJ_WAVES;
+    static constexpr int B = OPF_ADJ_BATCH, WAVES = OPF_ADJ_WAVES, NT = kOwnerThreads;
 };
 template <>
 struct OwnerTune<double, OpGrad> {
-    static constexpr int B = 1, WAVES = 0;
+    static constexpr int B = OPF_GRAD_BATCH, WAVES = 0, NT = OPF_GRAD_THREADS;
 };
 template <>
 struct OwnerTune<double, OpFlux2> {
-    static constexpr int B = 1, WAVES = 0;
+    static constexpr int B = OPF_FLUX2_BATCH, WAVES = 0, NT = OPF_FLUX2_THREADS;
 };
 
 // ----------------------------------------------------------- plumbing -- */
@@ -1107,14 +1122,13 @@ int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t s
     const size_t lds = owner_dyn_lds<T, Op>(P.K);
     const OwnerPtrs op{P.oe2n ? P.oe2n : P.e2n, P.prim, P.sec_off, P.sec_eid, P.pmap, P.smap,
                        P.nbr_off, P.nbr};
+    constexpr int NT = OwnerTune<T, Op>::NT;
     if (P.compact && lo.compact)
-        hipLaunchKernelGGL((k_edge_owner<T, Op, kOwnerThreads, true>), dim3(P.ncl),
-                           dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
-                           lo.xcd_remap, lo.overwrite);
+        hipLaunchKernelGGL((k_edge_owner<T, Op, NT, true>), dim3(P.ncl), dim3(NT), lds, st, op,
+                           typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
     else
-        hipLaunchKernelGGL((k_edge_owner<T, Op, kOwnerThreads, false>), dim3(P.ncl),
-                           dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
-                           lo.xcd_remap, lo.overwrite);
+        hipLaunchKernelGGL((k_edge_owner<T, Op, NT, false>), dim3(P.ncl), dim3(NT), lds, st, op,
+                           typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
     return (int)hipGetLastError();
 }
 
@@ -1196,12 +1210,9 @@ int raise_all(size_t bytes)
 {
     int rc = raise_coloured<T, Op, false>(bytes);
     if (!rc) rc = raise_coloured<T, Op, true>(bytes);
-    if (!rc)
-        rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, false>),
-                       bytes);
-    if (!rc)
-        rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, true>),
-                       bytes);
+    constexpr int NT = OwnerTune<T, Op>::NT;
+    if (!rc) rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, NT, false>), bytes);
+    if (!rc) rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, NT, true>), bytes);
     if constexpr (std::is_same<Op, OpFlux>::value) {
         if (!rc)
             rc = raise_one(
