@@ -42,10 +42,10 @@
 #define OPF_FLUX64_WAVES 4
 #endif
 #ifndef OPF_ADJ_BATCH
-#define OPF_ADJ_BATCH 1
+#define OPF_ADJ_BATCH 2
 #endif
 #ifndef OPF_ADJ_WAVES
-#define OPF_ADJ_WAVES 0
+#define OPF_ADJ_WAVES 4
 #endif
 // The gradient and second-order loops hold 24 or more values per node in LDS:
 // one workgroup per CU, so their workgroups take more threads (NT) instead
