@@ -338,15 +338,30 @@ def main():
                     timers.setdefault("geometry_adj" + tag, []).append((b, c))
     torch.cuda.synchronize()
 
+    # a device-to-device copy of 1 GiB for context: what plain streaming reaches here
+    src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a = ev()
+    for _ in range(5):
+        dst.copy_(src)
+    b = ev()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 8 / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    log(f"device copy {copy_gbs:.1f} GB/s (read + write)")
+
     per = {}
     for k, lst in timers.items():
         if not lst:
             continue
-        ms = float(np.mean([a.elapsed_time(b) for a, b in lst]))
+        times = [a.elapsed_time(b) for a, b in lst]
+        ms = float(np.mean(times))
         be, bn, bt = (*BYTES[k], 0)[:3]
         gbs = (be * E + bn * N + bt * T) / (ms * 1e-3) / 1e9
-        per[k] = {"ms": round(ms, 4), "algorithmic_GBs": round(gbs, 1),
-                  "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        per[k] = {"ms": round(ms, 4), "ms_median": round(float(np.median(times)), 4),
+                  "ms_min": round(float(np.min(times)), 4), "launches": len(times),
+                  "algorithmic_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
         if be:
             per[k]["edges_per_s"] = round(E / (ms * 1e-3), 1)
         log(f"{k:8s} {ms * 1e3:9.1f} us  {gbs:8.1f} GB/s algorithmic  "
@@ -391,7 +406,8 @@ def main():
             "halo_order": not args.no_halo_order,
             "owner_compact": bool(args.owner_compact),
             "plan": {k: info[k] for k in ("nblocks", "nblock_colours", "sum_unique", "max_unique",
-                                          "mean_elem_colours", "nclusters", "owner_edge_visits")},
+                                          "mean_elem_colours", "nclusters", "owner_edge_visits",
+                                          "plan_seconds")},
         },
         "forms": per,
         "fp32_speedup_over_fp64": round(speedup32, 4),
@@ -405,6 +421,7 @@ def main():
             "frac": dom["hbm_frac"],
             "bytes_per_launch": be * E + bn * N,
             "traffic": measured_traffic(config_key),
+            "device_copy_GBs": round(copy_gbs, 1),
         },
     }
     if not args.no_cpu_baseline:
