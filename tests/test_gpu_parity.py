@@ -25,13 +25,15 @@ ALL_VARIANTS = (pk.COLOURED, pk.ATOMIC, pk.OWNER, pk.COLOURED_LDS_ATOMIC, pk.FLA
 
 
 def problem(m, q, fp32=False, renumber="rcm", block_size=512, colour_sort=False,
-            cluster_size=512, lane_groups=True, owner_compact=False):
+            cluster_size=512, lane_groups=True, owner_compact=False, bank_spread=True,
+            halo_order=True):
     ctx = pk.Context(DEV)
     coords = m.xyz if renumber == "morton" else None
     return pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, fp32=fp32, renumber=renumber,
                           block_size=block_size, colour_sort=colour_sort, coords=coords,
                           cluster_size=cluster_size, lane_groups=lane_groups,
-                          owner_compact=owner_compact)
+                          owner_compact=owner_compact, bank_spread=bank_spread,
+                          halo_order=halo_order)
 
 
 def variants(p):
@@ -77,19 +79,22 @@ def small(request):
     return request.param, m, q, res
 
 
-@pytest.mark.parametrize("renumber,bs,csort,K,lg,compact", [("rcm", 512, False, 512, True, True),
-                                                            ("rcm", 512, False, 512, True, False),
-                                                            ("rcm", 64, True, 64, True, True),
-                                                            ("morton", 2048, False, 1024, False, True),
-                                                            ("morton", 256, False, 0, False, True),
-                                                            ("none", 256, False, 128, True, True),
-                                                            ("none", 256, False, 64, True, False)])
-def test_residual_small(small, renumber, bs, csort, K, lg, compact):
+@pytest.mark.parametrize("renumber,bs,csort,K,lg,compact,spread,halo", [
+    ("rcm", 512, False, 512, True, True, True, True),
+    ("rcm", 512, False, 512, True, False, True, True),
+    ("rcm", 64, True, 64, True, True, True, True),
+    ("morton", 2048, False, 1024, False, True, True, True),
+    ("morton", 256, False, 0, False, True, True, True),
+    ("morton", 512, False, 512, True, False, False, False),
+    ("morton", 512, False, 384, False, False, True, False),
+    ("none", 256, False, 128, True, True, True, True),
+    ("none", 256, False, 64, True, False, True, True)])
+def test_residual_small(small, renumber, bs, csort, K, lg, compact, spread, halo):
     name, m, q, ref = small
-    print(f"[residual {name} {renumber} bs={bs} sort={csort} K={K} groups={lg} compact={compact}]",
-          flush=True)
+    print(f"[residual {name} {renumber} bs={bs} sort={csort} K={K} groups={lg} compact={compact} "
+          f"spread={spread} halo={halo}]", flush=True)
     p = problem(m, q, renumber=renumber, block_size=bs, colour_sort=csort, cluster_size=K,
-                lane_groups=lg, owner_compact=compact)
+                lane_groups=lg, owner_compact=compact, bank_spread=spread, halo_order=halo)
     assert p.info["owner_ok"] == (K > 0)
     assert p.info["owner_compact"] == (K > 0 and compact)
     for variant in variants(p):
@@ -278,19 +283,23 @@ def test_fused_stage_matches_separate_loops(small):
     name, m, q, _ = small
     dt = oracle.dt(m.e2n, q, m.w, m.vol)
     q_ref, ss_ref = oracle.rk_iteration(m.e2n, q, m.w, m.vol, dt)
-    for fp32 in (False, True):
+    # clusters of 512 nodes (one per thread of the workgroup; partials through the
+    # LDS tree) and of 256 (the wavefront reduction)
+    for fp32, K in ((False, 512), (True, 512), (False, 256)):
         runs = {}
         for fused in (True, False):
-            p = problem(m, q, fp32=fp32)
+            p = problem(m, q, fp32=fp32, cluster_size=K)
             p.rk_iteration(dt, pk.OWNER, fused=fused)
             p.ctx.sync()
             runs[fused] = (p.nodes_out(p.qa).astype(np.float64), p.rms())
         tol = 1e-5 if fp32 else 1e-13
-        assert report(f"fused vs separate q fp32={fp32}", normwise(runs[True][0], runs[False][0]), tol)
-        assert report(f"fused vs separate rms fp32={fp32}", normwise(runs[True][1], runs[False][1]), tol)
+        tag = f"fp32={fp32} K={K}"
+        assert report(f"fused vs separate q {tag}", normwise(runs[True][0], runs[False][0]), tol)
+        assert report(f"fused vs separate rms {tag}", normwise(runs[True][1], runs[False][1]), tol)
         if not fp32:
-            assert report("fused q vs oracle", normwise(runs[True][0], q_ref), TOL64)
-            assert report("fused rms vs oracle", normwise(runs[True][1], np.sqrt(ss_ref / m.N)), TOL64)
+            assert report(f"fused q vs oracle {tag}", normwise(runs[True][0], q_ref), TOL64)
+            assert report(f"fused rms vs oracle {tag}", normwise(runs[True][1], np.sqrt(ss_ref / m.N)),
+                          TOL64)
 
 
 def test_fp32_storage_stage(small):
