@@ -3,8 +3,9 @@
 // An edge loop is an op_par_loop over edges (Sec. 3.1) with OP_READ node
 // arguments through the edge->node map, one direct 3-vector weight and OP_INC
 // node increments.  Every kernel first turns a node's inputs into a "staged"
-// record once per node (state plus primitives: 1/rho, pressure, sound speed),
-// so the per-edge work needs no division or square root besides |n_e|.
+// record once per node (state and primitives: velocity, sound speed; the
+// flux rebuilds the pressure as rho c^2 / gamma), so the per-edge work needs
+// no division or square root besides |n_e|.
 // Four ways to resolve the increments:
 //   * coloured (Sec. 4.1): one workgroup per mini-partition, one launch per
 //     partition colour.  The partition's distinct nodes are staged in LDS (the
@@ -26,7 +27,9 @@
 // Data are SoA (Sec. 4.1.2): every component is its own coalesced stream.
 // The direct stage update and its residual norm are one grid-stride pass
 // with a wavefront + LDS reduction per workgroup and a fixed-order second
-// pass over the per-workgroup partial sums.
+// pass over the per-workgroup partial sums; with the owner variant the update
+// can instead run at the end of each owner workgroup (the fused stage), whose
+// partial sums go through an LDS tree to the same second pass.
 #include <algorithm>
 #include <type_traits>
 
