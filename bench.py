@@ -271,6 +271,11 @@ def main():
     ctx.sync()
     if not ctx.check_finite(p64.ss) or not ctx.check_finite(p32.ss):
         log("warning: non-finite residual norm")
+    # both forms ran the same iterations from the same state: the FP32-storage
+    # form's error, per variable relative to the FP64 state's largest value
+    a64, a32 = p64.qa.double(), p32.qa.double()
+    err32 = float(((a64 - a32).abs().amax(dim=1) / a64.abs().amax(dim=1)).max())
+    log(f"FP32-storage state vs FP64 after {args.steps} iterations: {err32:.2e}")
 
     # the plain edge loops (residual written), beside the step when it fuses the stage
     if fused:
@@ -411,6 +416,7 @@ def main():
         },
         "forms": per,
         "fp32_speedup_over_fp64": round(speedup32, 4),
+        "fp32_error_vs_fp64": float(f"{err32:.3e}"),
         "roofline": {
             "kernel": ("FP64 edge-flux loop with the stage update fused (opf_edge_flux_stage)"
                        if fused else "FP64 edge-flux loop (opf_edge_flux)"),
