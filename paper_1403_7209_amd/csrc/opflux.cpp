@@ -935,11 +935,23 @@ int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info
         return ctx->fail(OPF_EPLAN, "plan property " + std::to_string(vr.property) + ": " + vr.message);
     pr->map_version = m.version;
     auto old = ctx->plans.find(map);
-    if (old != ctx->plans.end()) {
+    if (old != ctx->plans.end() || !ctx->dmaps.empty() || !ctx->tinv.empty()) {
         if (ctx->device >= 0) {
             (void)hipSetDevice(ctx->device);
             (void)hipDeviceSynchronize();
         }
+        // the device copies of the tet maps are in the internal numbering this
+        // plan is about to change: drop them (rebuilt on their next use)
+        for (auto &kv : ctx->dmaps) ctx->dfree(kv.second.ptr);
+        ctx->dmaps.clear();
+        for (auto &kv : ctx->tinv) {
+            DevTetInverse &d = kv.second;
+            for (int32_t *q : {d.t2n, d.t2e, d.e2t_off, d.e2t, d.n2t_off, d.n2t}) ctx->dfree(q);
+            ctx->dfree(d.scratch);
+        }
+        ctx->tinv.clear();
+    }
+    if (old != ctx->plans.end()) {
         free_plan(ctx, *old->second);
         ctx->plans.erase(old);
     }

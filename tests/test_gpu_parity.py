@@ -397,3 +397,39 @@ def test_argument_checks_on_device():
     p.residual(nanq, res)
     p.ctx.rk_stage(p.nodes, p.dat(p.qa), p.dat(res), p.vol, p.dat(p.qb), 0.1, ss)
     assert p.ctx.check_finite(ss) is False
+
+
+def test_geometry_after_replanning():
+    """A new plan renumbers the nodes and edges: the tet loops must follow it
+    (their device copies of the tet maps are rebuilt, not reused)."""
+    m = meshgen.build_mesh(8, 1, 0.25)
+    t2n = m.tets()
+    t2e = meshgen.tet_edges(m, t2n)
+    w_ref, vol_ref = oracle.geometry(m.e2n, t2n, t2e, m.xyz)
+    ctx = pk.Context(DEV)
+    nodes = ctx.decl_set(m.N, "nodes")
+    edges = ctx.decl_set(m.E, "edges")
+    tets = ctx.decl_set(len(t2n), "tets")
+    mp = ctx.decl_map(edges, nodes, 2, m.e2n, 0, "e2n")
+    tn = ctx.decl_map(tets, nodes, 4, t2n, 0, "t2n")
+    te = ctx.decl_map(tets, edges, 6, t2e, 0, "t2e")
+    for renumber in ("rcm", "morton", "none"):
+        ctx.plan(mp, renumber=renumber, coords=m.xyz, block_size=256, cluster_size=128)
+        node_new = ctx.get_perm(nodes, m.N)
+        edge_new = ctx.get_perm(edges, m.E)
+        x = np.empty((3, m.N))
+        x[:, node_new] = m.xyz
+        x_t = torch.from_numpy(x).to(DEV)
+        for variant in (pk.OWNER, pk.ATOMIC):
+            w = torch.zeros((3, m.E), dtype=torch.float64, device=DEV)
+            vol = torch.zeros((1, m.N), dtype=torch.float64, device=DEV)
+            ctx.geometry(tets, tn, te, ctx.decl_dat(nodes, x_t, "x"),
+                         ctx.decl_dat(edges, w, "w"), ctx.decl_dat(nodes, vol, "vol"),
+                         variant=variant)
+            ctx.sync()
+            tag = f"{renumber} v{variant}"
+            assert report(f"geometry w after plan {tag}",
+                          normwise(w.cpu().numpy()[:, edge_new], w_ref), TOL64)
+            assert report(f"geometry vol after plan {tag}",
+                          normwise(vol.cpu().numpy()[:, node_new], vol_ref[None]), TOL64)
+    ctx.close()
