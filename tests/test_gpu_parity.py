@@ -284,8 +284,9 @@ def test_fused_stage_matches_separate_loops(small):
     dt = oracle.dt(m.e2n, q, m.w, m.vol)
     q_ref, ss_ref = oracle.rk_iteration(m.e2n, q, m.w, m.vol, dt)
     # clusters of 512 nodes (one per thread of the workgroup; partials through the
-    # LDS tree) and of 256 (the wavefront reduction)
-    for fp32, K in ((False, 512), (True, 512), (False, 256)):
+    # LDS tree), of 1024 (two per thread, same tree) and of 256 (the wavefront
+    # reduction)
+    for fp32, K in ((False, 512), (True, 512), (False, 1024), (False, 256)):
         runs = {}
         for fused in (True, False):
             p = problem(m, q, fp32=fp32, cluster_size=K)
