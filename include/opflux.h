@@ -11,7 +11,11 @@
  * for an indirect loop it builds an execution plan once per map (Sec. 4.1):
  * mini-partitions of consecutive edges, a colouring of the mini-partitions so
  * that partitions of one colour share no node, and a colouring of the edges
- * inside each partition so that edges of one colour share no node.
+ * inside each partition so that edges of one colour share no node.  The same
+ * plan also groups the nodes into clusters of consecutive internal labels,
+ * each owned by one workgroup that runs every edge touching it and writes its
+ * nodes' totals once (the OWNER variant, the owner-compute rule of the paper's
+ * distributed back-end applied inside one GPU).
  *
  * Conventions
  *  - Every call returns an int status: OPF_OK (0) or a negative opf_status.
@@ -201,8 +205,11 @@ typedef struct {
  * bit-exactly, and uploads it to the device (device contexts only; blocks until
  * the upload is done).  The plan renumbers both sets: afterwards every dat on
  * them must be in internal numbering.  A set can be renumbered by one plan only.
+ * Planning the same map again replaces its plan and numbering (move the dats
+ * again); the library's device copies of other maps in the old numbering (the
+ * tet maps) are dropped and rebuilt on their next use.
  * `opts` NULL means RCM, block_size 512, no colour sort, cluster_size 512,
- * lane groups on, bank spreading on.
+ * lane groups on, bank spreading on, halo order on, no compact visit words.
  * `info` may be NULL.
  * Errors: OPF_EINVAL (dim != 2, self-loop edge, bad options), OPF_ESTATE (a set
  * already renumbered by another plan), OPF_ENOMEM, OPF_EDEVICE, OPF_EPLAN. */
