@@ -266,6 +266,25 @@ def test_halo_order_groups_boundary_nodes():
     assert lines[True][0] < 0.8 * lines[False][0]
 
 
+def test_plan_is_deterministic():
+    """The planner's parallel steps (bank spreading, halo order) split
+    independent work only: planning the same map twice gives the same plan."""
+    m = meshgen.build_mesh(16, 1, 0.25)
+    views = []
+    for _ in range(2):
+        ctx, nodes, edges, mp, info = host_problem(m, renumber="morton", cluster_size=512)
+        v = ctx.plan_view(mp)
+        v["node_new"] = ctx.get_perm(nodes, m.N)
+        v["edge_new"] = ctx.get_perm(edges, m.E)
+        views.append(v)
+    a, b = views
+    for k, x in a.items():
+        if isinstance(x, np.ndarray):
+            assert np.array_equal(x, b[k]), k
+        else:
+            assert x == b[k], k
+
+
 def test_declaration_errors():
     ctx = pk.Context(None)
     with pytest.raises(pk.OpfError) as e:
