@@ -118,6 +118,48 @@ def cpu_baseline(mesh, q, seconds=12.0):
                       f"of the same mesh ({el:.1f} s, one thread)"}
 
 
+def cpu_baseline_sweep():
+    """The oracle (single thread) on the host: the FP64 residual and the RK
+    stage on the 8,000-node, 1M-node and 4.1M-node meshes, and the adjoint on
+    the 1M-node mesh; the best of three runs of each, as edges/s (nodes/s for
+    the stage)."""
+    import platform
+
+    import meshgen
+    import oracle
+
+    def best(fn, reps=3):
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            t.append(time.perf_counter() - t0)
+        return min(t)
+
+    out = {"kind": "oracle", "cores": 1, "host": platform.processor() or platform.machine(),
+           "nproc": os.cpu_count(), "rows": []}
+    for name, (n, split, jit) in (("A", (20, 0, 0.0)), ("B", (100, 0, 0.2)),
+                                  ("E", (160, 1, 0.25))):
+        mesh = meshgen.build_mesh(n, split, jit)
+        q = meshgen.state(mesh.N, mesh.perm)
+        res = np.zeros_like(q)
+        t = best(lambda: oracle.residual(mesh.e2n, q, mesh.w, res=res))
+        out["rows"].append({"mesh": name, "N": mesh.N, "E": mesh.E, "loop": "FP64 residual",
+                            "s": round(t, 4), "edges_per_s": round(mesh.E / t, 1)})
+        r = np.ascontiguousarray(res)
+        t = best(lambda: oracle.rk_stage(q, r, mesh.vol, 1e-4))
+        out["rows"].append({"mesh": name, "N": mesh.N, "E": mesh.E, "loop": "RK stage + norms",
+                            "s": round(t, 4), "nodes_per_s": round(mesh.N / t, 1)})
+        if name == "B":
+            rbar = meshgen.normal(6 * mesh.N, purpose=21).reshape(6, mesh.N)
+            t = best(lambda: oracle.adjoint(mesh.e2n, q, mesh.w, rbar), reps=1)
+            out["rows"].append({"mesh": name, "N": mesh.N, "E": mesh.E,
+                                "loop": "FP64 adjoint (dual numbers)", "s": round(t, 4),
+                                "edges_per_s": round(mesh.E / t, 1)})
+        log(f"oracle on {name}: {out['rows'][-1]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,7 +181,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device copy first (calibrates profiler byte counters)")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="time the oracle on the host (three meshes) and print that JSON line")
     args = ap.parse_args()
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline_sweep()), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
