@@ -61,6 +61,8 @@ def _load():
         lib.mg_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                   ctypes.c_void_p]
         lib.mg_normal.restype = None
+        lib.mg_tet_edges.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -111,21 +113,15 @@ TET_LOCAL_EDGES = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
 def tet_edges(mesh, tets):
     """(T, 6) int32 edge ids of each tet's local edges in the order
     TET_LOCAL_EDGES (connectivity only: a lookup of node pairs in e2n)."""
-    lo = np.minimum(mesh.e2n[:, 0], mesh.e2n[:, 1]).astype(np.int64)
-    hi = np.maximum(mesh.e2n[:, 0], mesh.e2n[:, 1]).astype(np.int64)
-    key = lo * mesh.N + hi
-    order = np.argsort(key)
-    skey = key[order]
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    e2n = np.ascontiguousarray(mesh.e2n, dtype=np.int32)
     out = np.empty((tets.shape[0], 6), np.int32)
-    for k, (a, b) in enumerate(TET_LOCAL_EDGES):
-        p, q = tets[:, a].astype(np.int64), tets[:, b].astype(np.int64)
-        want = np.minimum(p, q) * mesh.N + np.maximum(p, q)
-        wo = np.argsort(want)  # sorted queries keep the binary searches in cache
-        pos = np.empty_like(wo)
-        pos[wo] = np.searchsorted(skey, want[wo])
-        if np.any(pos >= len(skey)) or np.any(skey[np.minimum(pos, len(skey) - 1)] != want):
-            raise ValueError("a tet edge is missing from the edge list")
-        out[:, k] = order[pos]
+    rc = _load().mg_tet_edges(mesh.N, e2n.shape[0], _ptr(e2n), tets.shape[0], _ptr(tets),
+                              _ptr(out))
+    if rc == -1:
+        raise ValueError("a tet edge is missing from the edge list")
+    if rc:
+        raise RuntimeError(f"mg_tet_edges failed ({rc})")
     return out
 
 

@@ -501,3 +501,52 @@ int mg_state(int64_t N, const int32_t *perm, uint64_t seed, double gamma, double
     }
     return 0;
 }
+
+/* Edge ids of the six local edges of every tet ((0,1) (0,2) (0,3) (1,2) (1,3)
+ * (2,3)), looked up in a CSR of each node's (larger neighbour, edge) pairs
+ * built from e2n.  Connectivity only.  Returns 0, or -1 when a tet edge is not
+ * in e2n, -7 on allocation failure. */
+int mg_tet_edges(int64_t N, int64_t E, const int32_t *e2n, int64_t T, const int32_t *tets,
+                 int32_t *out)
+{
+    static const int LE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    int64_t *off = calloc((size_t)N + 1, sizeof(int64_t));
+    int32_t *nb = malloc(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
+    int32_t *id = malloc(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+    if (!off || !nb || !id || !fill) {
+        free(off), free(nb), free(id), free(fill);
+        return -7;
+    }
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t a = e2n[2 * e], b = e2n[2 * e + 1];
+        ++off[(a < b ? a : b) + 1];
+    }
+    for (int64_t i = 0; i < N; ++i) off[i + 1] += off[i];
+    for (int64_t i = 0; i < N; ++i) fill[i] = off[i];
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t a = e2n[2 * e], b = e2n[2 * e + 1];
+        const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+        nb[fill[lo]] = hi;
+        id[fill[lo]++] = (int32_t)e;
+    }
+    int rc = 0;
+    for (int64_t t = 0; t < T && !rc; ++t)
+        for (int k = 0; k < 6; ++k) {
+            const int32_t p = tets[4 * t + LE[k][0]], q = tets[4 * t + LE[k][1]];
+            const int32_t lo = p < q ? p : q, hi = p < q ? q : p;
+            int32_t found = -1;
+            for (int64_t j = off[lo]; j < off[lo + 1]; ++j)
+                if (nb[j] == hi) {
+                    found = id[j];
+                    break;
+                }
+            if (found < 0) {
+                rc = -1;
+                break;
+            }
+            out[6 * t + k] = found;
+        }
+    free(off), free(nb), free(id), free(fill);
+    return rc;
+}

@@ -57,6 +57,12 @@ int mg_state(int64_t N, const int32_t *perm, uint64_t seed, double gamma, double
  * and its signed volume. */
 int mg_tet_dual(const double x[12], double nvec[18], double *vol);
 
+/* Edge ids (row of e2n) of the six local edges of each tet, in the order
+ * (0,1) (0,2) (0,3) (1,2) (1,3) (2,3): out is T x 6.  Connectivity only.
+ * Returns 0, -1 when a tet edge is missing from e2n, -7 on allocation failure. */
+int mg_tet_edges(int64_t N, int64_t E, const int32_t *e2n, int64_t T, const int32_t *tets,
+                 int32_t *out);
+
 uint64_t mg_stream(uint64_t seed, uint64_t purpose);
 void mg_uniform(uint64_t seed, uint64_t purpose, int64_t count, double lo, double hi,
                 double *out);

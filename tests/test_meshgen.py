@@ -170,3 +170,27 @@ def test_large_layered_mesh():
     assert m.six_cubes == m.N // 2
     assert m.vol.min() > 0.0
     assert abs(m.vol.sum() - 1.0) < 1e-10
+
+
+def test_tet_edges_against_a_sorted_key_lookup():
+    """The C lookup of each tet's six edges agrees with an independent numpy
+    lookup (sorted (min, max) node-pair keys), and every edge is found."""
+    for n, split in ((3, 0), (8, 1), (12, 0)):
+        m = meshgen.build_mesh(n, split, 0.2)
+        t2n = m.tets()
+        got = meshgen.tet_edges(m, t2n)
+        lo = np.minimum(m.e2n[:, 0], m.e2n[:, 1]).astype(np.int64)
+        hi = np.maximum(m.e2n[:, 0], m.e2n[:, 1]).astype(np.int64)
+        key = lo * m.N + hi
+        order = np.argsort(key)
+        for k, (a, b) in enumerate(meshgen.TET_LOCAL_EDGES):
+            p, q = t2n[:, a].astype(np.int64), t2n[:, b].astype(np.int64)
+            want = np.minimum(p, q) * m.N + np.maximum(p, q)
+            pos = np.searchsorted(key[order], want)
+            assert np.array_equal(key[order][pos], want)
+            assert np.array_equal(order[pos], got[:, k])
+    # a tet edge missing from the map is an error, not a wrong answer
+    bad = t2n.copy()
+    bad[0, 1] = bad[0, 0]
+    with pytest.raises(ValueError):
+        meshgen.tet_edges(m, bad)
