@@ -127,15 +127,20 @@ def check_plan_properties(m, ctx, nodes, edges, mp):
         return contiguous / v["nclusters"]
 
 
-@pytest.mark.parametrize("renumber,bs,K,lg,csort", [("rcm", 512, 512, True, False),
-                                                    ("morton", 64, 64, True, True),
-                                                    ("none", 256, 0, False, False),
-                                                    ("morton", 2048, 4096, False, False)])
-def test_plan_properties(renumber, bs, K, lg, csort):
+@pytest.mark.parametrize("renumber,bs,K,lg,csort,spread,halo", [
+    ("rcm", 512, 512, True, False, True, True),
+    ("morton", 64, 64, True, True, True, True),
+    ("none", 256, 0, False, False, True, True),
+    ("morton", 2048, 4096, False, False, True, True),
+    ("morton", 512, 128, True, False, False, True),
+    ("rcm", 256, 256, False, False, True, False),
+    ("morton", 512, 384, True, False, False, False)])
+def test_plan_properties(renumber, bs, K, lg, csort, spread, halo):
     m = meshgen.build_mesh(8, 1, 0.25)
     ctx, nodes, edges, mp, info = host_problem(m, renumber=renumber, block_size=bs,
                                                cluster_size=K, lane_groups=lg,
-                                               colour_sort=csort)
+                                               colour_sort=csort, bank_spread=spread,
+                                               halo_order=halo)
     assert ctx.plan_verify(mp)["ok"]
     contiguous = check_plan_properties(m, ctx, nodes, edges, mp)
     assert info["nblocks"] == -(-m.E // bs)
