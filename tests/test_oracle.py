@@ -236,11 +236,39 @@ def test_dt_closed_form_at_rest(mesh_j):
     np.add.at(ssum, m.e2n[:, 1], nn)
     expect = 0.5 * np.min(m.vol / (c * ssum))
     assert oracle.dt(m.e2n, q, m.w, m.vol) == pytest.approx(expect, rel=1e-13)
-    # hand case 1: lambda = 2.5 at both ends
-    _, qi, qj, n, _ = flux_hand_cases()[0]
-    ls = oracle.spectral_radius(np.array([[0, 1]], np.int32), np.stack([qi, qj], 1),
-                                n.reshape(3, 1))
-    np.testing.assert_allclose(ls, [2.5, 2.5], rtol=1e-15)
+    # hand cases: lambda = 2.5 at both ends, with u.n > 0 (case 1) and u.n < 0
+    # (case 2, where |1/2 (U_i + U_j)| = 0.5 only through the absolute value)
+    for case in flux_hand_cases():
+        _, qi, qj, n, _ = case
+        ls = oracle.spectral_radius(np.array([[0, 1]], np.int32), np.stack([qi, qj], 1),
+                                    n.reshape(3, 1))
+        np.testing.assert_allclose(ls, [2.5, 2.5], rtol=1e-15)
+
+
+def test_spectral_radius_is_the_flux_dissipation():
+    """lambda_e is the coefficient of the flux's dissipation: the density
+    component of F is 1/2 (rho_i U_i + rho_j U_j) - 1/2 lambda (rho_j - rho_i),
+    so lambda follows from the (hand-pinned) flux and the mass fluxes, for
+    random states and weights with u.n of either sign."""
+    rng = np.random.default_rng(1403)
+    m = 400
+    q = np.empty((6, 2 * m))
+    n = rng.normal(size=(3, m))
+    for k in range(2 * m):
+        q[:, k] = random_state(rng)
+    e2n = np.arange(2 * m, dtype=np.int32).reshape(m, 2)  # disjoint edges (2k, 2k+1)
+    ls = oracle.spectral_radius(e2n, q, n)
+    np.testing.assert_array_equal(ls[0::2], ls[1::2])
+    signs = []
+    for k in range(m):
+        qi, qj, nk = q[:, 2 * k], q[:, 2 * k + 1], n[:, k]
+        F = oracle.flux(qi, qj, nk)
+        Ui, Uj = qi[1:4] @ nk / qi[0], qj[1:4] @ nk / qj[0]
+        signs.append(np.sign(Ui + Uj))
+        lam = (qi[0] * Ui + qj[0] * Uj - 2.0 * F[0]) / (qj[0] - qi[0])
+        scale = (abs(qi[0] * Ui) + abs(qj[0] * Uj) + abs(F[0])) / abs(qj[0] - qi[0])
+        assert abs(ls[2 * k] - lam) <= 1e-13 * max(scale, lam), k
+    assert min(signs) < 0 < max(signs)
 
 
 def test_local_dt_closed_form_at_rest(mesh_j):
