@@ -25,6 +25,18 @@
  *  - A context is not thread-safe.  Loops are asynchronous on the HIP stream
  *    passed as `stream` (a hipStream_t; NULL = the null stream); the library
  *    never synchronises unless asked (opf_sync, opf_plan).
+ *  - Streams and library scratch: the direct reductions (RK stage, time
+ *    step), the fused edge loop + stage and the gather form of the tet loops
+ *    keep partial results in device scratch owned by the context (or by the
+ *    plan), shared by every call.  Such a call records an event on its stream;
+ *    the next such call on a different stream waits for that event first, so
+ *    their uses of the scratch never overlap.  Loops that use no scratch (the
+ *    plain edge loops) are not ordered across streams.
+ *  - Aliasing: every output (WRITE, RW, INC) must share no byte with any other
+ *    argument of the same call, device globals included.  Dats are compared by
+ *    the address range their elements cover ([ptr, ptr + ((dim-1)*ld + size)
+ *    * elemsize)), so two handles over one buffer are refused (OPF_EINVAL)
+ *    before anything is launched.
  *  - Data arrays ("dats") are borrowed device memory in SoA layout: component c
  *    of element k is at ptr[c * ld + k], ld >= set size.  They must be in the
  *    library's internal numbering once a plan has renumbered their set (use

@@ -332,6 +332,19 @@ class Context:
         return out.value
 
     # -- loops -----------------------------------------------------------------
+    def _gbl_ptr(self, t, n, what):
+        """Device address of a float64 global of at least n values on this
+        context's GPU (a host tensor would hand the kernel a host address)."""
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{what} must be a torch tensor")
+        if self.device < 0 or not t.is_cuda or t.device.index != self.device:
+            raise ValueError(f"{what} must be a tensor on cuda:{self.device}")
+        if t.dtype != torch.float64:
+            raise TypeError(f"{what} must be float64")
+        if t.numel() < n or not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous with at least {n} values")
+        return ctypes.c_void_p(t.data_ptr())
+
     def par_loop(self, kernel, s, args, gbls, variant=COLOURED, stream=None):
         a = (Arg * len(args))(*[Arg(*x) for x in args])
         g = (Gbl * len(gbls))(*[Gbl(*x) for x in gbls])
@@ -374,7 +387,7 @@ class Context:
         """Owner edge-flux loop with the stage update fused: qout = q0 - alpha res/vol
         (alpha dt_i res/vol with a per-node step dat), ss += sum res^2."""
         self._check(self.lib.opf_edge_flux_stage(self._ctx, edges, e2n, q, n, q0, vol, dt, qout,
-                                                 gamma, float(alpha), ctypes.c_void_p(ss.data_ptr()),
+                                                 gamma, float(alpha), self._gbl_ptr(ss, 6, "ss"),
                                                  _stream_ptr(stream, self.device)),
                     "opf_edge_flux_stage")
 
@@ -397,13 +410,13 @@ class Context:
         """ss: float64 device tensor of 6 values, incremented by sum res^2.
         res_access RW zeroes res after use, READ leaves it."""
         self._check(self.lib.opf_rk_stage(self._ctx, nodes, q0, res, vol, q, float(alpha_dt),
-                                          ctypes.c_void_p(ss.data_ptr()), res_access,
+                                          self._gbl_ptr(ss, 6, "ss"), res_access,
                                           _stream_ptr(stream, self.device)), "opf_rk_stage")
 
     def rk_stage_local(self, nodes, q0, res, vol, dt, q, alpha, ss, res_access=RW, stream=None):
         """As rk_stage with a time step per node (dat dt): q = q0 - alpha dt_i res / vol."""
         self._check(self.lib.opf_rk_stage_local(self._ctx, nodes, q0, res, vol, dt, q, float(alpha),
-                                                ctypes.c_void_p(ss.data_ptr()), res_access,
+                                                self._gbl_ptr(ss, 6, "ss"), res_access,
                                                 _stream_ptr(stream, self.device)),
                     "opf_rk_stage_local")
 
@@ -414,14 +427,14 @@ class Context:
 
     def dt_min(self, nodes, vol, lam, cfl, dt, stream=None):
         self._check(self.lib.opf_dt_min(self._ctx, nodes, vol, lam, float(cfl),
-                                        ctypes.c_void_p(dt.data_ptr()),
+                                        self._gbl_ptr(dt, 1, "dt"),
                                         _stream_ptr(stream, self.device)), "opf_dt_min")
 
     def sync(self, stream=None):
         self._check(self.lib.opf_sync(self._ctx, _stream_ptr(stream, self.device)), "opf_sync")
 
     def check_finite(self, t, stream=None):
-        rc = self.lib.opf_check_finite(self._ctx, ctypes.c_void_p(t.data_ptr()), t.numel(),
+        rc = self.lib.opf_check_finite(self._ctx, self._gbl_ptr(t, 1, "t"), t.numel(),
                                        _stream_ptr(stream, self.device))
         if rc == ENONFINITE:
             return False

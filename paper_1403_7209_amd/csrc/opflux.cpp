@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <string>
@@ -87,6 +88,14 @@ struct opf_ctx {
     void (*free_fn)(void *, void *) = nullptr;
     void *alloc_user = nullptr;
     double *scratch = nullptr;  // partial sums of the direct reductions
+    // Library-owned scratch (the reductions' partial sums, the fused stage's
+    // per-cluster partials, the tet records of the gather form) is shared by
+    // every call on this context.  After each call that uses it, an event is
+    // recorded on that call's stream; a call on another stream first waits for
+    // it, so calls on different streams never overlap on the scratch.
+    hipEvent_t scratch_ev = nullptr;
+    hipStream_t scratch_stream = nullptr;
+    bool scratch_used = false;
     size_t max_lds = 65536;
     size_t lds_limit = 65536;
     uint64_t next_version = 1;
@@ -347,6 +356,80 @@ int device_ready(opf_ctx *ctx)
     return OPF_OK;
 }
 
+// Orders a call that uses library-owned scratch on stream `st` after the last
+// such call, whatever stream that ran on.
+int scratch_begin(opf_ctx *ctx, hipStream_t st)
+{
+    if (!ctx->scratch_ev) {
+        hipError_t e = hipEventCreateWithFlags(&ctx->scratch_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(ctx, e, "scratch event");
+    }
+    if (ctx->scratch_used && st != ctx->scratch_stream) {
+        hipError_t e = hipStreamWaitEvent(st, ctx->scratch_ev, 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "waiting for the previous stream's scratch use");
+    }
+    return OPF_OK;
+}
+
+int scratch_end(opf_ctx *ctx, hipStream_t st)
+{
+    hipError_t e = hipEventRecord(ctx->scratch_ev, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "recording the scratch event");
+    ctx->scratch_used = true;
+    ctx->scratch_stream = st;
+    return OPF_OK;
+}
+
+// Byte range [lo, hi) spanned by a dat's elements (its last component ends at
+// (dim - 1) * ld + size); empty for a NULL pointer (host-only contexts).
+struct ByteRange {
+    uintptr_t lo = 0, hi = 0;
+};
+
+ByteRange dat_range(const opf_ctx *ctx, opf_dat d)
+{
+    ByteRange r;
+    const DatRec &dr = ctx->dats[d];
+    if (!dr.ptr) return r;
+    const int64_t n = ctx->sets[dr.set].size;
+    r.lo = reinterpret_cast<uintptr_t>(dr.ptr);
+    r.hi = r.lo + (uintptr_t)(((int64_t)(dr.dim - 1) * dr.ld + n) * (int64_t)type_size(dr.type));
+    return r;
+}
+
+bool overlap(ByteRange a, ByteRange b) { return a.lo < a.hi && b.lo < b.hi && a.lo < b.hi && b.lo < a.hi; }
+
+// An output (WRITE, RW or INC) must share no byte with another argument: the
+// kernels read inputs and write outputs from different workgroups in no fixed
+// order.  Dats are compared by the memory they cover, not by handle, so two
+// handles declared over one buffer are caught too.
+int check_disjoint(opf_ctx *ctx, opf_dat out, std::initializer_list<opf_dat> others, const char *what)
+{
+    const ByteRange ro = dat_range(ctx, out);
+    for (opf_dat o : others) {
+        if (o < 0) continue;  // an optional argument left out
+        if (o == out) return ctx->fail(OPF_EINVAL, std::string(what) + ": output aliases an input");
+        if (overlap(ro, dat_range(ctx, o)))
+            return ctx->fail(OPF_EINVAL, std::string(what) + ": output '" + ctx->dats[out].name +
+                                             "' overlaps the memory of '" + ctx->dats[o].name + "'");
+    }
+    return OPF_OK;
+}
+
+// The same for a device global (6 or 1 doubles) against the dats of a loop.
+int check_gbl_disjoint(opf_ctx *ctx, const void *p, size_t bytes, std::initializer_list<opf_dat> dats,
+                       const char *what)
+{
+    ByteRange g;
+    g.lo = reinterpret_cast<uintptr_t>(p);
+    g.hi = g.lo + bytes;
+    for (opf_dat d : dats)
+        if (d >= 0 && overlap(g, dat_range(ctx, d)))
+            return ctx->fail(OPF_EINVAL, std::string(what) + ": the device global overlaps '" +
+                                             ctx->dats[d].name + "'");
+    return OPF_OK;
+}
+
 int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args, int ngbl,
               const opf_gbl *gbls, int variant, hipStream_t st)
 {
@@ -426,11 +509,23 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
         rc = check_gbl(ctx, gbls[0], 1, OPF_READ, 0, 0);
         if (rc) return rc;
     }
-    // an increment target must not be one of the loop's inputs
+    // an increment target must not be one of the loop's inputs, by handle or
+    // by memory; the adjoint's direct output nbar neither
     for (int k = 0; k < yslot; ++k)
         if (args[k].dat == args[yslot].dat)
             return ctx->fail(OPF_EINVAL, "argument " + std::to_string(yslot) +
                                              " aliases input argument " + std::to_string(k));
+    for (int k = 0; k < nargs; ++k) {
+        const bool out = args[k].access != OPF_READ;
+        if (!out || (k == yslot + 1)) continue;
+        for (int j = 0; j < nargs; ++j) {
+            // the other map column of the same output is the same dat by design
+            if (j == k || (args[j].dat == args[k].dat && args[j].access != OPF_READ)) continue;
+            rc = check_disjoint(ctx, args[k].dat, {args[j].dat},
+                                ("argument " + std::to_string(k)).c_str());
+            if (rc) return rc;
+        }
+    }
     auto it = ctx->plans.find(m);
     if (it == ctx->plans.end()) return ctx->fail(OPF_ESTATE, "no plan for this map: call opf_plan");
     PlanRec &pr = *it->second;
@@ -649,6 +744,11 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
         for (int j = 0; j < out0; ++j)
             if (args[k].dat == args[j].dat)
                 return ctx->fail(OPF_EINVAL, "an incremented argument aliases an input");
+    // by memory as well: every incremented dat against every other argument
+    for (int k = out0; k < nargs && !rc; ++k)
+        for (int j = 0; j < nargs && !rc; ++j)
+            if (j != k) rc = check_disjoint(ctx, args[k].dat, {args[j].dat}, "tet loop");
+    if (rc) return rc;
     const double period = *static_cast<const double *>(gbls[0].ptr);
     if (!(period >= 0.0)) return ctx->fail(OPF_EINVAL, "period must be >= 0");
     auto it = ctx->plans.find(eplan);
@@ -691,9 +791,13 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
         for (int d = 0; d < 3; ++d) ta.xbar[d] = (double *)comp(xb, d);
     }
     const int64_t T = ctx->sets[s].size;
+    if (gather) {
+        rc = scratch_begin(ctx, st);
+        if (rc) return rc;
+    }
     int e = opf::gpu::launch_geometry(adj, gather, (int)T, ta, period, st);
     if (e) return hip_fail(ctx, (hipError_t)e, "tet loop launch");
-    return OPF_OK;
+    return gather ? scratch_end(ctx, st) : OPF_OK;
 }
 
 int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args, int ngbl,
@@ -718,7 +822,18 @@ int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *a
         if (rc) return rc;
         if (args[0].dat == args[3].dat || args[1].dat == args[3].dat)
             return ctx->fail(OPF_EINVAL, "q must not alias q0 or res");
+        const opf_dat dtd = nargs == 5 ? args[4].dat : -1;
+        rc = check_disjoint(ctx, args[3].dat, {args[0].dat, args[1].dat, args[2].dat, dtd}, "RK stage q");
+        if (!rc && !keep_res)
+            rc = check_disjoint(ctx, args[1].dat, {args[0].dat, args[2].dat, dtd}, "RK stage res");
+        if (!rc)
+            rc = check_gbl_disjoint(ctx, gbls[1].ptr, 6 * sizeof(double),
+                                    {args[0].dat, args[1].dat, args[2].dat, args[3].dat, dtd},
+                                    "RK stage ss");
+        if (rc) return rc;
         rc = device_ready(ctx);
+        if (rc) return rc;
+        rc = scratch_begin(ctx, st);
         if (rc) return rc;
         opf::gpu::NodeArrays na;
         const DatRec &q0 = ctx->dats[args[0].dat], &res = ctx->dats[args[1].dat];
@@ -735,7 +850,7 @@ int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *a
                                           static_cast<double *>(gbls[1].ptr), ctx->scratch,
                                           keep_res, st);
         if (e) return hip_fail(ctx, (hipError_t)e, "RK stage launch");
-        return OPF_OK;
+        return scratch_end(ctx, st);
     }
     if (kernel == OPF_K_LOCAL_DT) {
         if (nargs != 3 || !args) return ctx->fail(OPF_EINVAL, "expected 3 arguments");
@@ -748,6 +863,8 @@ int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *a
         if (rc) return rc;
         if (args[2].dat == args[0].dat || args[2].dat == args[1].dat)
             return ctx->fail(OPF_EINVAL, "dt must not alias vol or lam");
+        rc = check_disjoint(ctx, args[2].dat, {args[0].dat, args[1].dat}, "local time step dt");
+        if (rc) return rc;
         rc = device_ready(ctx);
         if (rc) return rc;
         const double cfl = *static_cast<const double *>(gbls[0].ptr);
@@ -765,8 +882,12 @@ int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *a
     for (int k = 0; k < 2 && !rc; ++k) rc = check_arg(ctx, args[k], w[k], k);
     if (!rc) rc = check_gbl(ctx, gbls[0], 1, OPF_READ, 0, 0);
     if (!rc) rc = check_gbl(ctx, gbls[1], 1, OPF_MIN, 1, 1);
+    if (!rc)
+        rc = check_gbl_disjoint(ctx, gbls[1].ptr, sizeof(double), {args[0].dat, args[1].dat}, "time step");
     if (rc) return rc;
     rc = device_ready(ctx);
+    if (rc) return rc;
+    rc = scratch_begin(ctx, st);
     if (rc) return rc;
     const double cfl = *static_cast<const double *>(gbls[0].ptr);
     int e = opf::gpu::launch_dt_min((int)ctx->sets[s].size,
@@ -774,7 +895,7 @@ int direct_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *a
                                     static_cast<const double *>(ctx->dats[args[1].dat].ptr), cfl,
                                     static_cast<double *>(gbls[1].ptr), ctx->scratch, st);
     if (e) return hip_fail(ctx, (hipError_t)e, "time-step launch");
-    return OPF_OK;
+    return scratch_end(ctx, st);
 }
 
 }  // namespace
@@ -820,6 +941,7 @@ int opf_finalize(opf_ctx *ctx)
             ctx->dfree(kv.second.n2t);
         }
         ctx->dfree(ctx->scratch);
+        if (ctx->scratch_ev) (void)hipEventDestroy(ctx->scratch_ev);
     }
     delete ctx;
     return OPF_OK;
@@ -1218,6 +1340,11 @@ int opf_edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf
     if (rc) return rc;
     if (qout == q || qout == q0) return ctx->fail(OPF_EINVAL, "qout must not alias q or q0");
     if (!ss_dev) return ctx->fail(OPF_EINVAL, "ss must be device memory");
+    rc = check_disjoint(ctx, qout, {q, n, q0, vol, dt}, "fused stage qout");
+    if (!rc)
+        rc = check_gbl_disjoint(ctx, ss_dev, 6 * sizeof(double), {q, n, q0, vol, dt, qout},
+                                "fused stage ss");
+    if (rc) return rc;
     auto it = ctx->plans.find(e2n);
     if (it == ctx->plans.end()) return ctx->fail(OPF_ESTATE, "no plan for this map: call opf_plan");
     PlanRec &pr = *it->second;
@@ -1249,10 +1376,12 @@ int opf_edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf
     na.vol = static_cast<const double *>(ctx->dats[vol].ptr);
     if (dt >= 0) na.dt = static_cast<const double *>(ctx->dats[dt].ptr);
     opf::gpu::LaunchOpts lo;
-    int e = opf::gpu::launch_edge_stage(fp32, pr.dev, ea, na, gamma, alpha, ss_dev,
-                                        static_cast<hipStream_t>(stream), lo);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = scratch_begin(ctx, st);
+    if (rc) return rc;
+    int e = opf::gpu::launch_edge_stage(fp32, pr.dev, ea, na, gamma, alpha, ss_dev, st, lo);
     if (e) return hip_fail(ctx, (hipError_t)e, "fused loop launch");
-    return OPF_OK;
+    return scratch_end(ctx, st);
 }
 
 int opf_geometry(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x, double period,

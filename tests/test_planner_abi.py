@@ -453,6 +453,89 @@ def test_loop_argument_checks_without_device():
     assert flux(good) == pk.ESTATE
 
 
+def test_aliasing_is_checked_by_memory_without_device():
+    """Outputs are compared with every other argument by the bytes they cover,
+    not by handle: two handles declared over one buffer, or over overlapping
+    parts of it, are refused before anything runs (host-only context, fake
+    device addresses that are never dereferenced)."""
+    m = meshgen.build_mesh(3, 0, 0.0)
+    t2n = m.tets()
+    t2e = meshgen.tet_edges(m, t2n)
+    ctx = pk.Context(None)
+    N, E, T = m.N, m.E, len(t2n)
+    nodes, edges, tets = ctx.decl_set(N, "nodes"), ctx.decl_set(E, "edges"), ctx.decl_set(T, "tets")
+    mp = ctx.decl_map(edges, nodes, 2, m.e2n, 0, "e2n")
+    tn = ctx.decl_map(tets, nodes, 4, t2n, 0, "t2n")
+    te = ctx.decl_map(tets, edges, 6, t2e, 0, "t2e")
+    ctx.plan(mp, block_size=64, cluster_size=64)
+    lib, out = ctx.lib, ctypes.c_int32()
+    base = [1 << 40]
+
+    def dat(s, dim, size, addr=None, typ=pk.F64):
+        if addr is None:  # a fresh, disjoint fake region
+            addr = base[0]
+            base[0] += 1 << 24
+        assert lib.opf_decl_dat(ctx._ctx, s, dim, typ, ctypes.c_void_p(addr), size, b"d",
+                                ctypes.byref(out)) == 0
+        return out.value, addr
+
+    q, qa = dat(nodes, 6, N)
+    n, na = dat(edges, 3, E)
+    res, _ = dat(nodes, 6, N)
+    res_on_q, _ = dat(nodes, 6, N, addr=qa)              # another handle, same memory
+    res_tail_q, _ = dat(nodes, 6, N, addr=qa + 8 * (5 * N + N - 1))  # shares q's last value
+    res_after_q, _ = dat(nodes, 6, N, addr=qa + 8 * 6 * N)  # starts right after q: disjoint
+    V, C = pk.COLOURED, pk.OWNER
+    assert lib.opf_edge_flux(ctx._ctx, edges, mp, q, n, res, 1.4, V, pk.INC, None) == pk.EDEVICE
+    assert lib.opf_edge_flux(ctx._ctx, edges, mp, q, n, res_after_q, 1.4, V, pk.INC, None) == pk.EDEVICE
+    for bad in (res_on_q, res_tail_q):
+        assert lib.opf_edge_flux(ctx._ctx, edges, mp, q, n, bad, 1.4, V, pk.INC, None) == pk.EINVAL
+        assert "overlaps" in lib.opf_last_error(ctx._ctx).decode()
+    res_on_n, _ = dat(nodes, 6, N, addr=na)
+    assert lib.opf_edge_flux(ctx._ctx, edges, mp, q, n, res_on_n, 1.4, C, pk.WRITE, None) == pk.EINVAL
+    # adjoint: nbar must not share memory with n (nor with q, rbar or qbar)
+    rbar, _ = dat(nodes, 6, N)
+    qbar, qba = dat(nodes, 6, N)
+    nbar, _ = dat(edges, 3, E)
+    nbar_on_n, _ = dat(edges, 3, E, addr=na)
+    nbar_on_qbar, _ = dat(edges, 3, E, addr=qba)
+    adj = lib.opf_edge_flux_adjoint
+    assert adj(ctx._ctx, edges, mp, q, n, rbar, qbar, nbar, 1.4, C, pk.WRITE, None) == pk.EDEVICE
+    for bad in (nbar_on_n, nbar_on_qbar):
+        assert adj(ctx._ctx, edges, mp, q, n, rbar, qbar, bad, 1.4, C, pk.WRITE, None) == pk.EINVAL
+    # fused stage: qout against q0, vol and the device global ss
+    q0, q0a = dat(nodes, 6, N)
+    vol, vola = dat(nodes, 1, N)
+    qout, _ = dat(nodes, 6, N)
+    qout_on_q0, _ = dat(nodes, 6, N, addr=q0a)
+    ssb = base[0]
+    base[0] += 1 << 24
+    fs = lib.opf_edge_flux_stage
+    assert fs(ctx._ctx, edges, mp, q, n, q0, vol, -1, qout, 1.4, 0.1, ctypes.c_void_p(ssb),
+              None) == pk.EDEVICE
+    assert fs(ctx._ctx, edges, mp, q, n, q0, vol, -1, qout_on_q0, 1.4, 0.1, ctypes.c_void_p(ssb),
+              None) == pk.EINVAL
+    assert fs(ctx._ctx, edges, mp, q, n, q0, vol, -1, qout, 1.4, 0.1, ctypes.c_void_p(vola),
+              None) == pk.EINVAL  # ss inside vol
+    # RK stage: q against res; local dt: dt against vol
+    q_on_res, _ = dat(nodes, 6, N, addr=base[0])
+    res2, _ = dat(nodes, 6, N, addr=base[0])
+    base[0] += 1 << 24
+    assert lib.opf_rk_stage(ctx._ctx, nodes, q0, res2, vol, q_on_res, 0.1, ctypes.c_void_p(ssb),
+                            pk.RW, None) == pk.EINVAL
+    assert lib.opf_rk_stage(ctx._ctx, nodes, q0, res2, vol, qout, 0.1, ctypes.c_void_p(ssb),
+                            pk.RW, None) == pk.EDEVICE
+    lam, _ = dat(nodes, 1, N)
+    dt_on_vol, _ = dat(nodes, 1, N, addr=vola)
+    assert lib.opf_local_dt(ctx._ctx, nodes, vol, lam, 0.5, dt_on_vol, None) == pk.EINVAL
+    # geometry: the volumes must not share memory with the coordinates
+    x, xa = dat(nodes, 3, N)
+    w, _ = dat(edges, 3, E)
+    vol_on_x, _ = dat(nodes, 1, N, addr=xa + 8 * N)
+    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, vol, pk.OWNER, None) == pk.EDEVICE
+    assert lib.opf_geometry(ctx._ctx, tets, tn, te, x, 1.0, w, vol_on_x, pk.OWNER, None) == pk.EINVAL
+
+
 def test_tet_loop_checks_without_device():
     m = meshgen.build_mesh(4, 1, 0.25)
     t2n = m.tets()
