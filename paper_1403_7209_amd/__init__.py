@@ -48,7 +48,8 @@ SYMBOLS = ("opf_init", "opf_finalize", "opf_last_error", "opf_set_allocator", "o
            "opf_decl_map", "opf_plan", "opf_get_perm", "opf_plan_view_get", "opf_plan_verify",
            "opf_decl_dat", "opf_par_loop", "opf_edge_flux", "opf_edge_flux_adjoint",
            "opf_edge_specrad", "opf_edge_gradient", "opf_edge_flux2", "opf_rk_stage",
-           "opf_rk_stage_local", "opf_local_dt", "opf_dt_min", "opf_edge_flux_stage", "opf_geometry",
+           "opf_rk_stage_local", "opf_local_dt", "opf_dt_min", "opf_edge_flux_stage",
+           "opf_edge_flux_stage_noalloc", "opf_geometry",
            "opf_geometry_adjoint",
            "opf_sync", "opf_check_finite")
 
@@ -158,6 +159,8 @@ def load():
     lib.opf_local_dt.argtypes = [vp, i32, i32, i32, d, i32, vp]
     lib.opf_geometry.argtypes = [vp, i32, i32, i32, i32, d, i32, i32, vp]
     lib.opf_edge_flux_stage.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i32, d, d, vp, vp]
+    lib.opf_edge_flux_stage_noalloc.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i32, d, d,
+                                                vp, vp]
     lib.opf_geometry_adjoint.argtypes = [vp, i32, i32, i32, i32, d, i32, i32, i32, vp]
     lib.opf_sync.argtypes = [vp, vp]
     lib.opf_check_finite.argtypes = [vp, vp, ctypes.c_int, vp]
@@ -390,6 +393,16 @@ class Context:
                                                  gamma, float(alpha), self._gbl_ptr(ss, 6, "ss"),
                                                  _stream_ptr(stream, self.device)),
                     "opf_edge_flux_stage")
+
+    def edge_flux_stage_noalloc(self, edges, e2n, q, n, q0, vol, qout, alpha, ss, gamma=1.4,
+                                dt=-1, stream=None):
+        """edge_flux_stage through the allocation-free entry point (partial sums in
+        the library's static device scratch; calls overlapping on one GPU race)."""
+        self._check(self.lib.opf_edge_flux_stage_noalloc(self._ctx, edges, e2n, q, n, q0, vol, dt,
+                                                         qout, gamma, float(alpha),
+                                                         self._gbl_ptr(ss, 6, "ss"),
+                                                         _stream_ptr(stream, self.device)),
+                    "opf_edge_flux_stage_noalloc")
 
     def geometry(self, tets, t2n, t2e, x, w, vol, period=1.0, variant=OWNER, stream=None):
         """w (edge dat, 3) and vol (node dat) += median-dual weights and volumes of the

@@ -35,6 +35,12 @@
 
 #include "kernels.hpp"
 
+// Scratch of the fused stage for callers that cannot allocate: per-cluster
+// partial sums (6 doubles per cluster).  Host code must not pass this name to a
+// kernel -- on the host it is only a stand-in for the symbol; the device address
+// comes from static_scratch_address(), resolved once per device.
+static __device__ __align__(256) double scratch[6 * opf::gpu::kStaticMaxClusters];
+
 // Tuning of the owner kernel per (type, op): edges each thread resolves before
 // computing (B), and the waves per SIMD the register allocator must allow
 // (0: no constraint).  Occupancy, not bandwidth per wave, limits these loops.
@@ -1137,9 +1143,9 @@ int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t s
 
 template <typename T>
 int run_owner_stage(const DevPlan &P, const EdgeArrays &a, const NodeArrays &na, double gamma,
-                    double adt, double *ss, hipStream_t st, const LaunchOpts &lo)
+                    double adt, double *ss, double *partial, hipStream_t st, const LaunchOpts &lo)
 {
-    if (!P.owner_ok || P.ncl <= 0 || !P.stage_partial) return (int)hipErrorInvalidValue;
+    if (!P.owner_ok || P.ncl <= 0 || !partial) return (int)hipErrorInvalidValue;
     const size_t lds = owner_dyn_lds<T, OpFlux>(P.K);
     const OwnerPtrs op{P.oe2n ? P.oe2n : P.e2n, P.prim, P.sec_off, P.sec_eid, P.pmap, P.smap,
                        P.nbr_off, P.nbr};
@@ -1151,7 +1157,7 @@ int run_owner_stage(const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
     sp.vol = na.vol;
     sp.dt = na.dt;
     sp.adt = adt;
-    sp.partial = P.stage_partial;
+    sp.partial = partial;
     if (P.compact && lo.compact)
         hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, true, true>), dim3(P.ncl),
                            dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
@@ -1160,8 +1166,7 @@ int run_owner_stage(const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
         hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, false, true>), dim3(P.ncl),
                            dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
                            lo.xcd_remap, 0, sp);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSumThreads), 0, st, P.ncl, P.stage_partial,
-                       ss);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSumThreads), 0, st, P.ncl, partial, ss);
     return (int)hipGetLastError();
 }
 
@@ -1294,10 +1299,20 @@ int launch_edge(int op, bool fp32, int variant, const DevPlan &P, const EdgeArra
 }
 
 int launch_edge_stage(bool fp32, const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
-                      double gamma, double adt, double *ss, hipStream_t st, const LaunchOpts &lo)
+                      double gamma, double adt, double *ss, double *partial, hipStream_t st,
+                      const LaunchOpts &lo)
 {
-    return fp32 ? run_owner_stage<float>(P, a, na, gamma, adt, ss, st, lo)
-                : run_owner_stage<double>(P, a, na, gamma, adt, ss, st, lo);
+    return fp32 ? run_owner_stage<float>(P, a, na, gamma, adt, ss, partial, st, lo)
+                : run_owner_stage<double>(P, a, na, gamma, adt, ss, partial, st, lo);
+}
+
+int static_scratch_address(double **out)
+{
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    *out = static_cast<double *>(p);
+    return 0;
 }
 
 template <typename T>

@@ -96,9 +96,20 @@ int launch_rk_stage(bool fp32, int N, const NodeArrays &a, double alpha_dt, doub
 // The owner FP64/FP32 edge-flux loop with the stage update fused into it:
 // q = q0 - adt * res / vol (adt * dt_i when a.dt is set) for every node, and
 // ss[v] += sum res^2 (per-cluster partials, fixed-order second pass); the
-// residual is never written.  The plan must have owner clusters.
+// residual is never written.  The plan must have owner clusters.  `partial`
+// holds 6 * P.ncl doubles; every cluster writes its six before they are summed,
+// so it needs no clearing.
 int launch_edge_stage(bool fp32, const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
-                      double gamma, double adt, double *ss, hipStream_t stream, const LaunchOpts &lo);
+                      double gamma, double adt, double *ss, double *partial, hipStream_t stream,
+                      const LaunchOpts &lo);
+
+// Clusters whose partial sums fit the library's static device scratch (the
+// fused stage for callers that cannot allocate): 6 doubles each, 768 KiB.
+constexpr int kStaticMaxClusters = 16384;
+
+// Device address of that static scratch on the current device (each GPU holds
+// its own copy).  Returns 0 or a hipError_t value.
+int static_scratch_address(double **out);
 
 // dt = min(dt, cfl * min_i vol_i / lam_i); `partial` holds kRkBlocks doubles.
 int launch_dt_min(int N, const double *vol, const double *lam, double cfl, double *dt,

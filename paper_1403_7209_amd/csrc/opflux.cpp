@@ -14,6 +14,7 @@
 #include <initializer_list>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -341,6 +342,44 @@ int check_gbl(opf_ctx *ctx, const opf_gbl &g, int dim, int access, int on_device
 const void *comp(const DatRec &d, int c)
 {
     return static_cast<const char *>(d.ptr) + (size_t)c * (size_t)d.ld * type_size(d.type);
+}
+
+// Makes the context's device current; allocates nothing.
+int device_bind(opf_ctx *ctx)
+{
+    if (ctx->device < 0) return ctx->fail(OPF_EDEVICE, "host-only context cannot run loops");
+    const hipError_t e = hipSetDevice(ctx->device);
+    return e == hipSuccess ? OPF_OK : hip_fail(ctx, e, "hipSetDevice");
+}
+
+// Device address of the static scratch (the allocation-free fused loop), per
+// device, resolved by opf_init with that device current.
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+double *g_static_scratch[kMaxStaticDevices] = {};
+
+double *static_scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxStaticDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    return g_static_scratch[device];
+}
+
+// Resolves the static scratch of `device` once; restores the caller's device.
+int resolve_static_scratch(int device)
+{
+    if (device >= kMaxStaticDevices) return OPF_OK;  // the allocation-free loop then refuses
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_scratch[device]) return OPF_OK;
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (hipSetDevice(device) != hipSuccess) return OPF_EDEVICE;
+    double *p = nullptr;
+    const int e = opf::gpu::static_scratch_address(&p);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    if (e || !p) return OPF_EDEVICE;
+    g_static_scratch[device] = p;
+    return OPF_OK;
 }
 
 int device_ready(opf_ctx *ctx)
@@ -917,7 +956,9 @@ int opf_init(opf_ctx **out, int hip_device)
         ctx->max_lds = prop.sharedMemPerBlock;
         ctx->lds_limit = prop.sharedMemPerBlock;
         if (prop.sharedMemPerBlockOptin > ctx->max_lds) ctx->max_lds = prop.sharedMemPerBlockOptin;
+        if (resolve_static_scratch(hip_device) != OPF_OK) return OPF_EDEVICE;
     }
+    ctx->err.reserve(512);  // error messages of later calls need no allocation
     ctx->device = hip_device;
     *out = ctx.release();
     return OPF_OK;
@@ -1310,9 +1351,17 @@ int opf_edge_flux2(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat 
     return opf_par_loop(ctx, OPF_K_EDGE_FLUX2, edges, 10, a, 1, g, variant, stream);
 }
 
-int opf_edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
-                        opf_dat q0, opf_dat vol, opf_dat dt, opf_dat qout, double gamma,
-                        double alpha, double *ss_dev, void *stream)
+}  // extern "C"
+
+namespace {
+
+// The fused edge loop + stage.  noalloc: the per-cluster partials go to the
+// static device scratch of the current device instead of the plan's buffer, and
+// nothing is allocated (no context scratch, no event): the allocation-free entry
+// point.
+int edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n, opf_dat q0,
+                    opf_dat vol, opf_dat dt, opf_dat qout, double gamma, double alpha,
+                    double *ss_dev, void *stream, bool noalloc)
 {
     if (!ctx) return OPF_EINVAL;
     ctx->err.clear();
@@ -1350,8 +1399,19 @@ int opf_edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf
     PlanRec &pr = *it->second;
     if (pr.map_version != mr.version) return ctx->fail(OPF_ESTATE, "plan is stale: map re-declared");
     if (!pr.host.owner_ok) return ctx->fail(OPF_EINVAL, "the fused loop needs owner clusters");
-    rc = device_ready(ctx);
-    if (rc) return rc;
+    double *partial = pr.dev.stage_partial;
+    if (noalloc) {
+        rc = device_bind(ctx);
+        if (rc) return rc;
+        if (pr.on_device && pr.dev.ncl > opf::gpu::kStaticMaxClusters)
+            return ctx->fail(OPF_ESIZE, "the allocation-free fused loop holds at most 16384 "
+                                        "clusters; this plan has more");
+        partial = static_scratch_of(ctx->device);
+        if (!partial) return ctx->fail(OPF_ESTATE, "static scratch not resolved for this device");
+    } else {
+        rc = device_ready(ctx);
+        if (rc) return rc;
+    }
     if (!pr.on_device) return ctx->fail(OPF_ESTATE, "plan is not on the device");
     const bool fp32 = T == OPF_F32;
     const size_t lds = opf::gpu::edge_lds_bytes(opf::gpu::OP_FLUX, fp32, OPF_V_OWNER, pr.dev.umax,
@@ -1377,11 +1437,36 @@ int opf_edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf
     if (dt >= 0) na.dt = static_cast<const double *>(ctx->dats[dt].ptr);
     opf::gpu::LaunchOpts lo;
     const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (noalloc) {
+        const int e = opf::gpu::launch_edge_stage(fp32, pr.dev, ea, na, gamma, alpha, ss_dev,
+                                                  partial, st, lo);
+        return e ? hip_fail(ctx, (hipError_t)e, "fused loop launch") : OPF_OK;
+    }
     rc = scratch_begin(ctx, st);
     if (rc) return rc;
-    int e = opf::gpu::launch_edge_stage(fp32, pr.dev, ea, na, gamma, alpha, ss_dev, st, lo);
+    int e = opf::gpu::launch_edge_stage(fp32, pr.dev, ea, na, gamma, alpha, ss_dev, partial, st, lo);
     if (e) return hip_fail(ctx, (hipError_t)e, "fused loop launch");
     return scratch_end(ctx, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int opf_edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
+                        opf_dat q0, opf_dat vol, opf_dat dt, opf_dat qout, double gamma,
+                        double alpha, double *ss_dev, void *stream)
+{
+    return edge_flux_stage(ctx, edges, e2n, q, n, q0, vol, dt, qout, gamma, alpha, ss_dev, stream,
+                           false);
+}
+
+int opf_edge_flux_stage_noalloc(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,
+                                opf_dat q0, opf_dat vol, opf_dat dt, opf_dat qout, double gamma,
+                                double alpha, double *ss_dev, void *stream)
+{
+    return edge_flux_stage(ctx, edges, e2n, q, n, q0, vol, dt, qout, gamma, alpha, ss_dev, stream,
+                           true);
 }
 
 int opf_geometry(opf_ctx *ctx, opf_set tets, opf_map t2n, opf_map t2e, opf_dat x, double period,
