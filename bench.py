@@ -171,8 +171,6 @@ def main():
     ap.add_argument("--no-lane-groups", action="store_true")
     ap.add_argument("--no-bank-spread", action="store_true")
     ap.add_argument("--no-halo-order", action="store_true")
-    ap.add_argument("--owner-compact", action="store_true",
-                    help="owner variant reads 4-byte visit words instead of the 8-byte map")
     ap.add_argument("--renumber", choices=["rcm", "morton", "none"], default="morton")
     ap.add_argument("--block-size", type=int, default=512)
     ap.add_argument("--colour-sort", action="store_true")
@@ -220,8 +218,7 @@ def main():
                          block_size=args.block_size, colour_sort=args.colour_sort,
                          coords=mesh.xyz, cluster_size=args.cluster_size,
                          lane_groups=not args.no_lane_groups, tets=t2n, tet_edges=t2e,
-                         bank_spread=not args.no_bank_spread, halo_order=not args.no_halo_order,
-                         owner_compact=args.owner_compact)
+                         bank_spread=not args.no_bank_spread, halo_order=not args.no_halo_order)
     T = len(t2n)
     p32 = pk.FluxProblem(ctx, mesh.e2n, mesh.w, mesh.vol, q, fp32=True, like=p64)
     info = p64.info
@@ -429,8 +426,7 @@ def main():
     config_key = (f"n={mn} variant={args.variant} renumber={args.renumber} "
                   f"cluster={args.cluster_size} block={args.block_size} "
                   f"lane_groups={not args.no_lane_groups} colour_sort={bool(args.colour_sort)} "
-                  f"bank_spread={not args.no_bank_spread} halo_order={not args.no_halo_order}"
-                  + (" owner_compact=True" if args.owner_compact else ""))
+                  f"bank_spread={not args.no_bank_spread} halo_order={not args.no_halo_order}")
     out = {
         "metric": "edges/s of edge-flux residual loop (FP64, FP32, adjoint) + % HBM roofline",
         "value": round(value, 1),
@@ -456,7 +452,6 @@ def main():
             "lane_groups": not args.no_lane_groups,
             "bank_spread": not args.no_bank_spread,
             "halo_order": not args.no_halo_order,
-            "owner_compact": bool(args.owner_compact),
             "plan": {k: info[k] for k in ("nblocks", "nblock_colours", "sum_unique", "max_unique",
                                           "mean_elem_colours", "nclusters", "owner_edge_visits",
                                           "plan_seconds")},

@@ -173,10 +173,9 @@ typedef struct {
     int32_t lane_groups;   /* 1: inside each cluster-pair segment, order edges in
                               groups of 64 sharing no node, so the lanes of one
                               wavefront update distinct nodes (OWNER variant)     */
-    int32_t owner_compact; /* 1: the OWNER variant reads 4-byte visit words
-                              (when every cluster has <= 256 neighbour clusters
-                              and cluster_size <= 1024) instead of the 8-byte
-                              edge map: 7 % less traffic, no faster on MI355X  */
+    int32_t owner_compact; /* accepted and ignored: the OWNER variant always
+                              reads the edges inside a cluster through 4-byte
+                              words of two local offsets                     */
     int32_t bank_spread;   /* 1: place the visits of every 64-lane wavefront of
                               the OWNER variant so that their LDS words fall in
                               distinct banks as far as possible, and choose
@@ -205,8 +204,9 @@ typedef struct {
     int32_t max_cluster_segments; /* most cluster-pair segments of one cluster    */
     int32_t owner_ok;           /* 1 when the plan has owner clusters (the OWNER
                                    variant can run)                               */
-    int32_t owner_compact;      /* 1 when the OWNER variant uses 4-byte visit
-                                   words (device contexts, set at upload)         */
+    int32_t owner_compact;      /* 1 when the plan has owner clusters (the
+                                   OWNER kernel then reads interior edges
+                                   through 4-byte words of local offsets)         */
     int32_t flat_colours;       /* colours of the flat colouring                  */
     int32_t flat_ok;            /* 1 when the FLAT variant can run (<= 128)       */
 } opf_plan_info;
@@ -221,7 +221,7 @@ typedef struct {
  * again); the library's device copies of other maps in the old numbering (the
  * tet maps) are dropped and rebuilt on their next use.
  * `opts` NULL means RCM, block_size 512, no colour sort, cluster_size 512,
- * lane groups on, bank spreading on, halo order on, no compact visit words.
+ * lane groups on, bank spreading on, halo order on.
  * `info` may be NULL.
  * Errors: OPF_EINVAL (dim != 2, self-loop edge, bad options), OPF_ESTATE (a set
  * already renumbered by another plan), OPF_ENOMEM, OPF_EDEVICE, OPF_EPLAN. */
@@ -265,6 +265,16 @@ typedef struct {
     const int32_t *flat_edges;    /* [E]                                        */
     const uint8_t *owner_swap;    /* [E] 1: the OWNER kernel updates the edge's
                                      second end first; NULL without bank spreading */
+    /* The OWNER kernel's two loops: cluster c first runs the interior block,
+     * the first cluster_interior[c] edges of its cluster_range (both ends in
+     * c, read through local offsets), then its cut visits
+     * cluster_cut_edges[cluster_cut_offsets[c] .. [c+1]), one (edge, owned
+     * end) pair each: cluster_cut_ends 0 names the edge's first node, 1 its
+     * second.  Every end of every edge is covered exactly once. */
+    const int32_t *cluster_interior;     /* [nclusters]                     */
+    const int64_t *cluster_cut_offsets;  /* [nclusters+1]                   */
+    const int32_t *cluster_cut_edges;
+    const uint8_t *cluster_cut_ends;
 } opf_plan_view;
 
 int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out);

@@ -94,7 +94,9 @@ class PlanView(ctypes.Structure):
                 ("cluster_seg_len", ctypes.c_void_p), ("cluster_range", ctypes.c_void_p),
                 ("cluster_list_offsets", ctypes.c_void_p), ("cluster_list_edges", ctypes.c_void_p),
                 ("nflat_colours", ctypes.c_int64), ("flat_offsets", ctypes.c_void_p),
-                ("flat_edges", ctypes.c_void_p), ("owner_swap", ctypes.c_void_p)]
+                ("flat_edges", ctypes.c_void_p), ("owner_swap", ctypes.c_void_p),
+                ("cluster_interior", ctypes.c_void_p), ("cluster_cut_offsets", ctypes.c_void_p),
+                ("cluster_cut_edges", ctypes.c_void_p), ("cluster_cut_ends", ctypes.c_void_p)]
 
 
 class PlanReport(ctypes.Structure):
@@ -270,6 +272,8 @@ class Context:
         nseg = int(soff[-1])
         loff = arr(v.cluster_list_offsets, ctypes.c_int64, ncl + 1, np.int64) if ncl else \
             np.zeros(1, np.int64)
+        coff = arr(v.cluster_cut_offsets, ctypes.c_int64, ncl + 1, np.int64) if ncl else \
+            np.zeros(1, np.int64)
         return dict(nnodes=v.nnodes, nedges=E, nblocks=nb, nblock_colours=nc,
                     cluster_size=v.cluster_size, nclusters=ncl, cluster_seg_offsets=soff,
                     cluster_seg_start=arr(v.cluster_seg_start, ctypes.c_int32, nseg, np.int32),
@@ -296,7 +300,14 @@ class Context:
                     flat_edges=arr(v.flat_edges, ctypes.c_int32, E, np.int32)
                     if v.nflat_colours else None,
                     owner_swap=arr(v.owner_swap, ctypes.c_uint8, E, np.uint8)
-                    if v.owner_swap else None)
+                    if v.owner_swap else None,
+                    cluster_interior=arr(v.cluster_interior, ctypes.c_int32, ncl, np.int32)
+                    if ncl else np.zeros(0, np.int32),
+                    cluster_cut_offsets=coff,
+                    cluster_cut_edges=arr(v.cluster_cut_edges, ctypes.c_int32, int(coff[-1]),
+                                          np.int32),
+                    cluster_cut_ends=arr(v.cluster_cut_ends, ctypes.c_uint8, int(coff[-1]),
+                                         np.uint8))
 
     def plan_verify(self, m):
         rep = PlanReport()

@@ -47,14 +47,32 @@ static __device__ __align__(256) double scratch[6 * opf::gpu::kStaticMaxClusters
 #ifndef OPF_FLUX64_BATCH
 #define OPF_FLUX64_BATCH 2
 #endif
+#ifndef OPF_FLUX64_CUT_BATCH
+#define OPF_FLUX64_CUT_BATCH 1
+#endif
 #ifndef OPF_FLUX64_WAVES
-#define OPF_FLUX64_WAVES 4
+#define OPF_FLUX64_WAVES 6
+#endif
+#ifndef OPF_FLUX32_BATCH
+#define OPF_FLUX32_BATCH 2
+#endif
+#ifndef OPF_FLUX32_CUT_BATCH
+#define OPF_FLUX32_CUT_BATCH 2
+#endif
+#ifndef OPF_FLUX32_WAVES
+#define OPF_FLUX32_WAVES 8
 #endif
 #ifndef OPF_ADJ_BATCH
-#define OPF_ADJ_BATCH 2
+#define OPF_ADJ_BATCH 1
+#endif
+#ifndef OPF_ADJ_CUT_BATCH
+#define OPF_ADJ_CUT_BATCH 1
 #endif
 #ifndef OPF_ADJ_WAVES
 #define OPF_ADJ_WAVES 4
+#endif
+#ifndef OPF_FLUX2_CUT_BATCH
+#define OPF_FLUX2_CUT_BATCH 1
 #endif
 // The gradient and second-order loops hold 24 or more values per node in LDS:
 // one workgroup per CU, so their workgroups take more threads (NT) instead
@@ -99,6 +117,15 @@ __device__ __forceinline__ double tsqrt(double x)
 __device__ __forceinline__ float tsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double tabs(double x) { return fabs(x); }
 __device__ __forceinline__ float tabs(float x) { return fabsf(x); }
+// x with its sign flipped when s is set (one XOR of the sign bit).
+__device__ __forceinline__ double flip(double x, uint32_t s)
+{
+    return __hiloint2double(__double2hiint(x) ^ (int)(s << 31), __double2loint(x));
+}
+__device__ __forceinline__ float flip(float x, uint32_t s)
+{
+    return __uint_as_float(__float_as_uint(x) ^ (s << 31));
+}
 
 // ----------------------------------------------------------- edge math -- */
 
@@ -334,25 +361,35 @@ struct OpFlux2 {
     }
 };
 
+// B: edges each thread resolves before computing in the interior loop, BC in
+// the cut-visit loop (whose gathered records cost registers).
 template <typename T, class Op>
 struct OwnerTune {
-    static constexpr int B = 2, WAVES = 0, NT = kOwnerThreads;
+    static constexpr int B = 2, BC = 2, WAVES = 0, NT = kOwnerThreads;
+};
+template <>
+struct OwnerTune<float, OpFlux> {
+    static constexpr int B = OPF_FLUX32_BATCH, BC = OPF_FLUX32_CUT_BATCH, WAVES = OPF_FLUX32_WAVES,
+                         NT = kOwnerThreads;
 };
 template <>
 struct OwnerTune<double, OpFlux> {
-    static constexpr int B = OPF_FLUX64_BATCH, WAVES = OPF_FLUX64_WAVES, NT = kOwnerThreads;
+    static constexpr int B = OPF_FLUX64_BATCH, BC = OPF_FLUX64_CUT_BATCH, WAVES = OPF_FLUX64_WAVES,
+                         NT = kOwnerThreads;
 };
 template <>
 struct OwnerTune<double, OpAdjoint> {
-    static constexpr int B = OPF_ADJ_BATCH, WAVES = OPF_ADJ_WAVES, NT = kOwnerThreads;
+    static constexpr int B = OPF_ADJ_BATCH, BC = OPF_ADJ_CUT_BATCH, WAVES = OPF_ADJ_WAVES,
+                         NT = kOwnerThreads;
 };
 template <>
 struct OwnerTune<double, OpGrad> {
-    static constexpr int B = OPF_GRAD_BATCH, WAVES = 0, NT = OPF_GRAD_THREADS;
+    static constexpr int B = OPF_GRAD_BATCH, BC = OPF_GRAD_BATCH, WAVES = 0, NT = OPF_GRAD_THREADS;
 };
 template <>
 struct OwnerTune<double, OpFlux2> {
-    static constexpr int B = OPF_FLUX2_BATCH, WAVES = 0, NT = OPF_FLUX2_THREADS;
+    static constexpr int B = OPF_FLUX2_BATCH, BC = OPF_FLUX2_CUT_BATCH, WAVES = 0,
+                         NT = OPF_FLUX2_THREADS;
 };
 
 // ----------------------------------------------------------- plumbing -- */
@@ -369,25 +406,13 @@ struct PlanPtrs {
 };
 
 struct OwnerPtrs {
-    const int2 *e2n;
-    const int2 *prim;     // [ncl] (first edge, count) of the cluster's contiguous range
-    const int *sec_off;   // [ncl+1]
-    const int *sec_eid;   // the cluster's other edges
-    const uint32_t *pmap; // compact words of the contiguous range (by edge)
-    const int2 *smap;     // (edge, compact word) of the listed edges
-    const int *nb_off;    // [ncl+1] neighbour-cluster tables
-    const int *nb;
+    const int2 *iblk;       // [ncl] (first edge, count) of the interior block
+    const uint32_t *iw;     // interior words by edge (see DevPlan)
+    const int *cv_off;      // [ncl+1] cut visits of each cluster
+    const int *cv_eid;
+    const int *cv_oth;
+    const uint16_t *cv_own;
 };
-
-// Endpoints of an edge from its compact visit word (see DevPlan): the owned
-// end at v0 + offset, the other end in this cluster or in neighbour slot nb[s].
-__device__ __forceinline__ int2 visit_ends(uint32_t v, int v0, int K, const int *nb)
-{
-    const int go = v0 + (int)(v & 1023u);
-    const int off = (int)(v >> 20);
-    const int gx = (v & 0x800u) ? nb[(v >> 12) & 255u] * K + off : v0 + off;
-    return (v & 0x400u) ? make_int2(gx, go) : make_int2(go, gx);
-}
 
 template <typename T>
 struct Arrays {
@@ -745,11 +770,21 @@ __device__ __forceinline__ void lds_sum6(const double (&acc)[6], double *buf, do
 
 // ------------------------------------------------------- owner kernel -- */
 
-// One workgroup per cluster of K consecutive nodes.  It runs every edge with
-// an end in the cluster: first the contiguous range of edges whose smaller end
-// it owns, then the listed edges whose larger end it owns.  A cut edge thus
-// runs in both of its clusters; each adds only to its own end, in LDS, and
-// writes its nodes' totals once.
+// One workgroup per cluster of K consecutive nodes runs every edge with an
+// end in the cluster and adds only into its own nodes' LDS accumulators, then
+// writes each node's total once.  Two loops, each uniform across a wavefront:
+//   (1) the interior block: edges with both ends in the cluster, read through
+//       4-byte words of local offsets; both records come from LDS and both
+//       ends are updated (the word's flag picks which first: bank spreading);
+//   (2) the cut visits: one (edge, owned end) pair each; the owned end's
+//       record comes from LDS, the other end's state is gathered from memory
+//       and staged in registers.  The flux is evaluated with the owned end as
+//       the first node: F(a, b, w) = -F(b, a, -w) for every kernel here (the
+//       edge inputs flip sign with the orientation), so a visit whose owned
+//       end is the edge's second node negates its edge inputs and adds the
+//       first-node result.  An edge joining two clusters runs in both.
+// KC > 0 fixes the cluster size at compile time (LDS addresses become
+// immediate offsets); KC = 0 takes it from the launch.
 __host__ __device__ constexpr int owner_acc_rows(int K) { return K; }
 
 // The stage update fused into the owner loop: each workgroup turns its nodes'
@@ -766,112 +801,122 @@ struct StagePtrs {
     double *partial;   // [ncl][6]
 };
 
-template <typename T, class Op, int NT, bool COMPACT, bool STAGE = false>
+template <typename T, class Op, int NT, int KC, bool STAGE = false>
 __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>::WAVES : 1)) void k_edge_owner(
-    OwnerPtrs p, Arrays<T> a, T gamma, int N, int K, int ncl, int remap, int overwrite,
+    OwnerPtrs p, Arrays<T> a, T gamma, int N, int Kr, int ncl, int remap, int overwrite,
     StagePtrs<T> sp = {})
 {
     constexpr int B = OwnerTune<T, Op>::B;
+    const int K = KC > 0 ? KC : Kr;
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int NY = Op::MODE == GEN ? 2 * Op::NOUT : Op::NOUT;
     T *ss = reinterpret_cast<T *>(smem);
     double *sy = reinterpret_cast<double *>(smem + stage_bytes<T, Op>(K));
-    const int AR = owner_acc_rows(K);
 
     const int c = remap ? xcd_map((int)blockIdx.x, ncl) : (int)blockIdx.x;
     const int v0 = c * K, nown = min(K, N - v0);
-    const int2 pr = p.prim[c];
-    const int sb = p.sec_off[c];
-    const int total = pr.y + (p.sec_off[c + 1] - sb);
-    [[maybe_unused]] const int *nbt = nullptr;
-    if constexpr (COMPACT) {
-        __shared__ int s_nb[kCompactMaxNeighbours];
-        const int n0 = p.nb_off[c], nn = p.nb_off[c + 1] - n0;
-        for (int t = threadIdx.x; t < nn; t += NT) s_nb[t] = p.nb[n0 + t];
-        nbt = s_nb;
-    }
     // stage the owned nodes (contiguous ids: coalesced), clear the accumulator
     for (int v = threadIdx.x; v < nown; v += NT) {
         T rec[Op::NS];
         load_stage<Op>(a, v0 + v, gamma, rec);
         lds_put<T, Op::NS>(ss, K, v, rec);
 #pragma unroll
-        for (int k = 0; k < Op::NOUT; ++k) sy[k * AR + v] = 0.0;
+        for (int k = 0; k < Op::NOUT; ++k) sy[k * K + v] = 0.0;
     }
     __syncthreads();
 
-    for (int k0 = threadIdx.x; k0 < total; k0 += NT * B) {
-        // resolve B edges and issue all their global loads first
-        int eid[B];
-        int2 ij[B];
-        [[maybe_unused]] uint32_t wd[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const int k = k0 + b * NT;
-            eid[b] = -1;
-            if constexpr (COMPACT) {
-                if (k < pr.y) {
-                    eid[b] = pr.x + k;
-                    wd[b] = ld(p.pmap, eid[b]);
-                } else if (k < total) {
-                    const int2 sv = ld(p.smap, sb + (k - pr.y));
-                    eid[b] = sv.x;
-                    wd[b] = (uint32_t)sv.y;
-                }
-            } else {
-                if (k < pr.y)
-                    eid[b] = pr.x + k;
-                else if (k < total)
-                    eid[b] = ld(p.sec_eid, sb + (k - pr.y));
-            }
-        }
+    // (1) interior block
+    const int2 ib = p.iblk[c];
+    for (int k0 = threadIdx.x; k0 < ib.y; k0 += NT * B) {
+        uint32_t wd[B];
         T w[B][Op::NW];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            if (eid[b] >= 0) {
-                if constexpr (!COMPACT) ij[b] = ld(p.e2n, eid[b]);
+            const int k = k0 + b * NT;
+            if (k < ib.y) {
+                wd[b] = ld(p.iw, ib.x + k);
 #pragma unroll
-                for (int d = 0; d < Op::NW; ++d) w[b][d] = ld(a.w[d], eid[b]);
+                for (int d = 0; d < Op::NW; ++d) w[b][d] = ld(a.w[d], ib.x + k);
             }
-        }
-        if constexpr (COMPACT) {
-#pragma unroll
-            for (int b = 0; b < B; ++b)
-                if (eid[b] >= 0) ij[b] = visit_ends(wd[b], v0, K, nbt);
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            if (eid[b] < 0) continue;
-            // bit 31 of the second end: update that end first (bank spreading)
-            const bool swp = ij[b].y < 0;
-            ij[b].y &= 0x7fffffff;
-            const int li = ij[b].x - v0, lj = ij[b].y - v0;
-            const bool oi = (unsigned)li < (unsigned)nown, oj = (unsigned)lj < (unsigned)nown;
+            const int k = k0 + b * NT;
+            if (k >= ib.y) continue;
+            const int li = (int)(wd[b] & 0x1fffu), lj = (int)((wd[b] >> 16) & 0x1fffu);
+            const uint32_t swp = wd[b] >> 31;
             T si[Op::NS], sj[Op::NS];
-            if (oi)
-                lds_get<T, Op::NS>(ss, K, li, si);
-            else
-                load_stage<Op>(a, ij[b].x, gamma, si);
-            if (oj)
-                lds_get<T, Op::NS>(ss, K, lj, sj);
-            else
-                load_stage<Op>(a, ij[b].y, gamma, sj);
-            double y[NY];
+            lds_get<T, Op::NS>(ss, K, li, si);
+            lds_get<T, Op::NS>(ss, K, lj, sj);
+            double y[Op::NOUT], yj[Op::NOUT];
             double wo[3] = {0.0, 0.0, 0.0};
-            Op::edge(si, sj, w[b], gamma, y, y + (NY - Op::NOUT), wo);
+            Op::edge(si, sj, w[b], gamma, y, yj, wo);
             const int la = swp ? lj : li, lb = swp ? li : lj;
-            const bool oa = swp ? oj : oi, ob = swp ? oi : oj;
 #pragma unroll
             for (int v = 0; v < Op::NOUT; ++v) {
-                const double yi = y[v];
-                const double yj = Op::MODE == ANTI ? -yi : Op::MODE == SAME ? yi : y[Op::NOUT + v];
-                if (oa) lds_add(&sy[v * AR + la], swp ? yj : yi);
-                if (ob) lds_add(&sy[v * AR + lb], swp ? yi : yj);
+                if constexpr (Op::MODE == ANTI) {
+                    const double ya = flip(y[v], swp);
+                    lds_add(&sy[v * K + la], ya);
+                    lds_add(&sy[v * K + lb], -ya);
+                } else if constexpr (Op::MODE == SAME) {
+                    lds_add(&sy[v * K + la], y[v]);
+                    lds_add(&sy[v * K + lb], y[v]);
+                } else {
+                    lds_add(&sy[v * K + la], swp ? yj[v] : y[v]);
+                    lds_add(&sy[v * K + lb], swp ? y[v] : yj[v]);
+                }
             }
-            // a direct output is written by the cluster of the smaller end only
-            if (Op::NWOUT && (ij[b].x < ij[b].y ? oi : oj)) {
+            if constexpr (Op::NWOUT > 0) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) st(a.wo[d], eid[b], wo[d]);
+                for (int d = 0; d < 3; ++d) st(a.wo[d], ib.x + k, wo[d]);
+            }
+        }
+    }
+
+    // (2) cut visits
+    constexpr int BC = OwnerTune<T, Op>::BC;
+    const int s0 = p.cv_off[c], ns = p.cv_off[c + 1] - s0;
+    for (int k0 = threadIdx.x; k0 < ns; k0 += NT * BC) {
+        int eid[BC], oth[BC], own[BC];
+#pragma unroll
+        for (int b = 0; b < BC; ++b) {
+            const int k = k0 + b * NT;
+            eid[b] = -1;
+            if (k < ns) {
+                eid[b] = ld(p.cv_eid, s0 + k);
+                oth[b] = ld(p.cv_oth, s0 + k);
+                own[b] = (int)ld(p.cv_own, s0 + k);
+            }
+        }
+        T w[BC][Op::NW], xf[BC][Op::NIN];
+#pragma unroll
+        for (int b = 0; b < BC; ++b) {
+            if (eid[b] < 0) continue;
+            const int g = oth[b] & 0x7fffffff;
+#pragma unroll
+            for (int d = 0; d < Op::NW; ++d) w[b][d] = ld(a.w[d], eid[b]);
+#pragma unroll
+            for (int v = 0; v < Op::NIN; ++v) xf[b][v] = ld(a.x[v], g);
+        }
+#pragma unroll
+        for (int b = 0; b < BC; ++b) {
+            if (eid[b] < 0) continue;
+            const uint32_t second = (uint32_t)oth[b] >> 31;
+            T so[Op::NS], sf[Op::NS], wf[Op::NW];
+            lds_get<T, Op::NS>(ss, K, own[b], so);
+            Op::stage(xf[b], sf, gamma);
+#pragma unroll
+            for (int d = 0; d < Op::NW; ++d) wf[d] = flip(w[b][d], second);
+            double y[Op::NOUT], yj[Op::NOUT];
+            double wo[3] = {0.0, 0.0, 0.0};
+            Op::edge(so, sf, wf, gamma, y, yj, wo);
+#pragma unroll
+            for (int v = 0; v < Op::NOUT; ++v) lds_add(&sy[v * K + own[b]], y[v]);
+            // a direct output is written by the visit from the smaller end only
+            if constexpr (Op::NWOUT > 0) {
+                if (v0 + own[b] < (oth[b] & 0x7fffffff)) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) st(a.wo[d], eid[b], flip(wo[d], second));
+                }
             }
         }
     }
@@ -896,7 +941,7 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
             const double adt = sp.dt ? sp.adt * ld(sp.dt, g) : sp.adt;
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                const double r = sy[k * AR + v];
+                const double r = sy[k * K + v];
                 acc[k] += r * r;
                 const double base = pre ? pq0[k] : (double)ld(sp.q0[k], g);
                 st(sp.q[k], g, (T)(base - adt * r / vi));
@@ -914,7 +959,7 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
         for (int v = threadIdx.x; v < nown; v += NT) {
 #pragma unroll
             for (int k = 0; k < Op::NOUT; ++k) {
-                const double acc = sy[k * AR + v];
+                const double acc = sy[k * K + v];
                 st(a.y[k], v0 + v, overwrite ? acc : ld(a.y[k], v0 + v) + acc);
             }
         }
@@ -1123,20 +1168,27 @@ constexpr size_t owner_dyn_lds(int K)
     return stage_bytes<T, Op>(K) + (size_t)Op::NOUT * owner_acc_rows(K) * sizeof(double);
 }
 
+OwnerPtrs owner_ptrs(const DevPlan &P)
+{
+    return OwnerPtrs{P.iblk, P.iw, P.cv_off, P.cv_eid, P.cv_oth, P.cv_own};
+}
+
+// Cluster size fixed at compile time for the default plan.
+constexpr int kOwnerKC = 512;
+
 template <typename T, class Op>
 int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
               const LaunchOpts &lo)
 {
     if (!P.owner_ok || P.ncl <= 0) return (int)hipErrorInvalidValue;
     const size_t lds = owner_dyn_lds<T, Op>(P.K);
-    const OwnerPtrs op{P.oe2n ? P.oe2n : P.e2n, P.prim, P.sec_off, P.sec_eid, P.pmap, P.smap,
-                       P.nbr_off, P.nbr};
+    const OwnerPtrs op = owner_ptrs(P);
     constexpr int NT = OwnerTune<T, Op>::NT;
-    if (P.compact && lo.compact)
-        hipLaunchKernelGGL((k_edge_owner<T, Op, NT, true>), dim3(P.ncl), dim3(NT), lds, st, op,
+    if (P.K == kOwnerKC)
+        hipLaunchKernelGGL((k_edge_owner<T, Op, NT, kOwnerKC>), dim3(P.ncl), dim3(NT), lds, st, op,
                            typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
     else
-        hipLaunchKernelGGL((k_edge_owner<T, Op, NT, false>), dim3(P.ncl), dim3(NT), lds, st, op,
+        hipLaunchKernelGGL((k_edge_owner<T, Op, NT, 0>), dim3(P.ncl), dim3(NT), lds, st, op,
                            typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
     return (int)hipGetLastError();
 }
@@ -1147,8 +1199,7 @@ int run_owner_stage(const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
 {
     if (!P.owner_ok || P.ncl <= 0 || !partial) return (int)hipErrorInvalidValue;
     const size_t lds = owner_dyn_lds<T, OpFlux>(P.K);
-    const OwnerPtrs op{P.oe2n ? P.oe2n : P.e2n, P.prim, P.sec_off, P.sec_eid, P.pmap, P.smap,
-                       P.nbr_off, P.nbr};
+    const OwnerPtrs op = owner_ptrs(P);
     StagePtrs<T> sp;
     for (int k = 0; k < 6; ++k) {
         sp.q0[k] = static_cast<const T *>(na.q0[k]);
@@ -1158,12 +1209,12 @@ int run_owner_stage(const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
     sp.dt = na.dt;
     sp.adt = adt;
     sp.partial = partial;
-    if (P.compact && lo.compact)
-        hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, true, true>), dim3(P.ncl),
+    if (P.K == kOwnerKC)
+        hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, kOwnerKC, true>), dim3(P.ncl),
                            dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
                            lo.xcd_remap, 0, sp);
     else
-        hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, false, true>), dim3(P.ncl),
+        hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, 0, true>), dim3(P.ncl),
                            dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
                            lo.xcd_remap, 0, sp);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSumThreads), 0, st, P.ncl, partial, ss);
@@ -1219,15 +1270,16 @@ int raise_all(size_t bytes)
     int rc = raise_coloured<T, Op, false>(bytes);
     if (!rc) rc = raise_coloured<T, Op, true>(bytes);
     constexpr int NT = OwnerTune<T, Op>::NT;
-    if (!rc) rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, NT, false>), bytes);
-    if (!rc) rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, NT, true>), bytes);
+    if (!rc) rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, NT, 0>), bytes);
+    if (!rc) rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, NT, kOwnerKC>), bytes);
     if constexpr (std::is_same<Op, OpFlux>::value) {
         if (!rc)
             rc = raise_one(
-                reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, false, true>), bytes);
+                reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, 0, true>), bytes);
         if (!rc)
             rc = raise_one(
-                reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, true, true>), bytes);
+                reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, kOwnerKC, true>),
+                bytes);
     }
     return rc;
 }
@@ -1242,7 +1294,7 @@ size_t owner_dyn_lds_bytes(int op, bool fp32, int K)
 }
 
 // LDS of an owner workgroup: the dynamic part plus a static allowance for the
-// compact form's neighbour table and the fused stage's reduction.
+// fused stage's reduction.
 size_t owner_lds_bytes(int op, bool fp32, int K)
 {
     return owner_dyn_lds_bytes(op, fp32, K) + 2048;

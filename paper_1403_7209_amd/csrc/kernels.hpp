@@ -14,8 +14,6 @@ enum EdgeOpKind { OP_FLUX = 0, OP_ADJOINT = 1, OP_SPECRAD = 2, OP_GRAD = 3, OP_F
 constexpr int kMaxNodeIn = 25;   // node inputs of one edge loop (q, G, vol)
 constexpr int kMaxNodeOut = 18;  // node increments (Green-Gauss sums)
 constexpr int kMaxEdgeIn = 6;    // direct edge inputs (n, dx)
-constexpr int kCompactMaxK = 1024;       // cluster size limit of the compact visit words
-constexpr int kCompactMaxNeighbours = 256;
 
 // Execution variants of an edge loop (values match opf_variant).
 enum Variant { V_COLOURED = 0, V_ATOMIC = 1, V_OWNER = 2, V_COLOURED_LDS_ATOMIC = 3, V_FLAT = 4 };
@@ -34,23 +32,21 @@ struct DevPlan {
     const int *block_ncol = nullptr;     // [nb]
     const int *colour_blocks = nullptr;  // [nb]
     std::vector<int> colour_off;         // host copy [nc+1]
-    // owner clusters: cluster c runs edges [prim[c].x, prim[c].x + prim[c].y),
-    // then sec_eid[sec_off[c] .. sec_off[c+1])
+    // owner clusters (cluster c owns internal nodes [c K, (c+1) K)), two loops
+    // per cluster: the interior block, edges iblk[c].x .. iblk[c].x + iblk[c].y
+    // with both ends in c, read through iw; then the cut visits
+    // cv_off[c] .. cv_off[c+1], one (edge, owned end) pair each
     int K = 0, ncl = 0;
     bool owner_ok = false;
-    const int2 *prim = nullptr;    // [ncl]
-    const int *sec_off = nullptr;  // [ncl+1]
-    const int *sec_eid = nullptr;  // [sec_off[ncl]]
-    const int2 *oe2n = nullptr;    // [E] the map with bit 31 of .y set where the owner
-                                   // kernel updates the second end first (bank spreading)
-    // Compact visit words (K <= 1024, at most 256 neighbour clusters each):
-    // own offset (10 bits) | own is the second end (1) | other end foreign (1)
-    // | neighbour slot (8) | other end's offset in its cluster (10).
-    bool compact = false;
-    const uint32_t *pmap = nullptr;  // [E] word of each edge for the cluster of its smaller end
-    const int2 *smap = nullptr;      // [sec_off[ncl]] (edge, word) of the listed visits
-    const int *nbr_off = nullptr;    // [ncl+1]
-    const int *nbr = nullptr;        // neighbour clusters of each cluster, by slot
+    const int2 *iblk = nullptr;      // [ncl] (first edge, count)
+    const uint32_t *iw = nullptr;    // [E] interior edges: offsets of the first (bits
+                                     // 0-12) and second (bits 16-28) end in the
+                                     // cluster; bit 31: update the second end first
+    const int *cv_off = nullptr;     // [ncl+1]
+    const int *cv_eid = nullptr;     // edge of each cut visit
+    const int *cv_oth = nullptr;     // its other end (internal node), bit 31 set when
+                                     // the owned end is the edge's second node
+    const uint16_t *cv_own = nullptr; // offset of the owned end in the cluster
     // flat colouring: colour c runs edges flat_eid[flat_off[c] .. flat_off[c+1])
     double *stage_partial = nullptr;  // [ncl][6] partial sums of the fused stage
     int nflat = 0;
@@ -70,7 +66,6 @@ struct EdgeArrays {
 struct LaunchOpts {
     int xcd_remap = 1;  // give each XCD a contiguous range of partitions/clusters
     int overwrite = 0;  // owner variant: res = sum instead of res += sum
-    int compact = 1;    // owner variant: compact visit words when the plan has them
 };
 
 // Returns 0 or a hipError_t value.

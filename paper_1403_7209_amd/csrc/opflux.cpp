@@ -54,7 +54,6 @@ struct PlanRec {
     uint64_t map_version = 0;
     int64_t device_bytes = 0;
     bool on_device = false;
-    bool compact = false;  // build the owner variant's compact visit words
 };
 
 size_t type_size(int t) { return t == OPF_F32 ? 4 : 8; }
@@ -156,68 +155,43 @@ int upload(opf_ctx *ctx, PlanRec &p, const std::vector<T> &v, const T *&out)
     return OPF_OK;
 }
 
-// Compact 4-byte visit words of the owner variant (see DevPlan): per cluster a
-// table of neighbour clusters, per edge the word seen from the cluster of its
-// smaller end, per listed visit (edge, word).  Left off (the kernel reads the
-// int2 map instead) when K > 1024 or a cluster has more than 256 neighbours.
-int upload_compact(opf_ctx *ctx, PlanRec &pr)
+// The owner kernel's arrays (see DevPlan): per cluster the interior block and
+// the cut visits; per interior edge a word of the two ends' offsets in the
+// cluster and the bank-spreading flag.
+int upload_owner(opf_ctx *ctx, PlanRec &pr)
 {
     const opf::Plan &P = pr.host;
     opf::gpu::DevPlan &D = pr.dev;
     const int K = P.cluster_size;
     const int64_t ncl = P.nclusters();
-    if (K > opf::gpu::kCompactMaxK) return OPF_OK;
-    std::vector<int> nb_off(ncl + 1, 0), nb;
-    std::vector<std::vector<int32_t>> lists(ncl);
-    auto add_nb = [&](int64_t c, int32_t other) {
-        if (other != c) lists[c].push_back(other);
-    };
+    std::vector<int2> iblk(ncl);
+    std::vector<uint32_t> iw(P.E, 0);
     for (int64_t c = 0; c < ncl; ++c) {
-        const int64_t p0 = P.cl_prim[2 * c], pn = P.cl_prim[2 * c + 1];
-        for (int64_t e = p0; e < p0 + pn; ++e) {
-            add_nb(c, P.e2n[2 * e] / K);
-            add_nb(c, P.e2n[2 * e + 1] / K);
+        const int32_t p0 = P.cl_prim[2 * c], ni = P.cl_nint[c];
+        iblk[c] = make_int2(p0, ni);
+        for (int64_t e = p0; e < p0 + ni; ++e) {
+            const uint32_t sw = P.owner_swap.empty() ? 0u : (uint32_t)P.owner_swap[e];
+            iw[e] = (uint32_t)(P.e2n[2 * e] - c * K) | ((uint32_t)(P.e2n[2 * e + 1] - c * K) << 16) |
+                    (sw << 31);
         }
-        for (int64_t s = P.cl_sec_off[c]; s < P.cl_sec_off[c + 1]; ++s) {
-            const int64_t e = P.cl_sec_eid[s];
-            add_nb(c, P.e2n[2 * e] / K);
-            add_nb(c, P.e2n[2 * e + 1] / K);
-        }
-        std::vector<int32_t> &L = lists[c];
-        std::sort(L.begin(), L.end());
-        L.erase(std::unique(L.begin(), L.end()), L.end());
-        if ((int)L.size() > opf::gpu::kCompactMaxNeighbours) return OPF_OK;
-        nb_off[c + 1] = nb_off[c] + (int)L.size();
     }
-    nb.reserve(nb_off[ncl]);
-    for (int64_t c = 0; c < ncl; ++c) nb.insert(nb.end(), lists[c].begin(), lists[c].end());
-    auto word = [&](int64_t c, int64_t e) -> uint32_t {
-        const int32_t i = P.e2n[2 * e], j = P.e2n[2 * e + 1];
-        const bool second = i / K != c;  // the owned end is the edge's second node
-        const int32_t own = second ? j : i, other = second ? i : j;
-        const int64_t oc = other / K;
-        uint32_t slot = 0;
-        if (oc != c) {
-            const std::vector<int32_t> &L = lists[c];
-            slot = (uint32_t)(std::lower_bound(L.begin(), L.end(), (int32_t)oc) - L.begin());
-        }
-        return (uint32_t)(own % K) | ((uint32_t)second << 10) | ((uint32_t)(oc != c) << 11) |
-               (slot << 12) | ((uint32_t)(other % K) << 20);
-    };
-    std::vector<uint32_t> pmap(P.E, 0);
-    for (int64_t c = 0; c < ncl; ++c) {
-        const int64_t p0 = P.cl_prim[2 * c], pn = P.cl_prim[2 * c + 1];
-        for (int64_t e = p0; e < p0 + pn; ++e) pmap[e] = word(c, e);
-    }
-    std::vector<int2> smap(P.cl_sec_eid.size());
+    const size_t nv = P.cl_cut_eid.size();
+    std::vector<int> cv_off(ncl + 1), cv_oth(nv);
+    std::vector<uint16_t> cv_own(nv);
+    for (int64_t c = 0; c <= ncl; ++c) cv_off[c] = (int)P.cl_cut_off[c];
     for (int64_t c = 0; c < ncl; ++c)
-        for (int64_t s = P.cl_sec_off[c]; s < P.cl_sec_off[c + 1]; ++s)
-            smap[s] = make_int2(P.cl_sec_eid[s], (int)word(c, P.cl_sec_eid[s]));
-    int rc = upload(ctx, pr, pmap, D.pmap);
-    if (!rc) rc = upload(ctx, pr, smap, D.smap);
-    if (!rc) rc = upload(ctx, pr, nb_off, D.nbr_off);
-    if (!rc) rc = upload(ctx, pr, nb, D.nbr);
-    if (!rc) D.compact = true;
+        for (int64_t s = P.cl_cut_off[c]; s < P.cl_cut_off[c + 1]; ++s) {
+            const int64_t e = P.cl_cut_eid[s];
+            const int h = P.cl_cut_end[s];
+            cv_oth[s] = (int)((uint32_t)P.e2n[2 * e + 1 - h] | ((uint32_t)h << 31));
+            cv_own[s] = (uint16_t)(P.e2n[2 * e + h] - c * K);
+        }
+    int rc = upload(ctx, pr, iblk, D.iblk);
+    if (!rc) rc = upload(ctx, pr, iw, D.iw);
+    if (!rc) rc = upload(ctx, pr, cv_off, D.cv_off);
+    if (!rc) rc = upload(ctx, pr, P.cl_cut_eid, D.cv_eid);
+    if (!rc) rc = upload(ctx, pr, cv_oth, D.cv_oth);
+    if (!rc) rc = upload(ctx, pr, cv_own, D.cv_own);
     return rc;
 }
 
@@ -252,25 +226,9 @@ int upload_plan(opf_ctx *ctx, PlanRec &pr)
     D.K = P.cluster_size;
     D.ncl = (int)P.nclusters();
     D.owner_ok = P.owner_ok && D.ncl > 0;
-    std::vector<int2> prim;
-    std::vector<int> sec_off;
     if (D.owner_ok) {
-        prim.resize(D.ncl);
-        sec_off.resize(D.ncl + 1);
-        for (int c = 0; c < D.ncl; ++c) prim[c] = make_int2(P.cl_prim[2 * c], P.cl_prim[2 * c + 1]);
-        for (int c = 0; c <= D.ncl; ++c) sec_off[c] = (int)P.cl_sec_off[c];
-        if (!rc) rc = upload(ctx, pr, prim, D.prim);
-        if (!rc) rc = upload(ctx, pr, sec_off, D.sec_off);
-        if (!rc) rc = upload(ctx, pr, P.cl_sec_eid, D.sec_eid);
-        if (!rc && !P.owner_swap.empty()) {
-            std::vector<int2> oe2n(P.E);
-            for (int64_t k = 0; k < P.E; ++k)
-                oe2n[k] = make_int2(P.e2n[2 * k],
-                                    (int)((uint32_t)P.e2n[2 * k + 1] |
-                                          ((uint32_t)P.owner_swap[k] << 31)));
-            rc = upload(ctx, pr, oe2n, D.oe2n);
-        }
-        if (!rc && pr.compact) rc = upload_compact(ctx, pr);
+        if (P.cluster_size > 8192) return ctx->fail(OPF_EINVAL, "cluster_size above 8192");
+        rc = upload_owner(ctx, pr);
         if (!rc) {
             D.stage_partial = static_cast<double *>(ctx->dalloc(sizeof(double) * 6 * D.ncl));
             if (!D.stage_partial)
@@ -1084,7 +1042,6 @@ int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info
     auto t0 = std::chrono::steady_clock::now();
     auto pr = std::unique_ptr<PlanRec>(new (std::nothrow) PlanRec());
     if (!pr) return ctx->fail(OPF_ENOMEM, "out of host memory");
-    pr->compact = opts && opts->owner_compact;
     int rc;
     try {
         rc = opf::build_plan(ctx->sets[m.to].size, ctx->sets[m.from].size, m.idx.data(), po,
@@ -1142,7 +1099,7 @@ int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info
         info->owner_edge_visits = P.owner_edge_visits;
         info->max_cluster_segments = P.max_cluster_segments;
         info->owner_ok = P.owner_ok ? 1 : 0;
-        info->owner_compact = pr->dev.compact ? 1 : 0;
+        info->owner_compact = P.owner_ok ? 1 : 0;
         info->flat_colours = P.flat_colours;
         info->flat_ok = P.flat_ok ? 1 : 0;
     }
@@ -1199,6 +1156,10 @@ int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out)
     out->flat_offsets = P.flat_ok ? P.flat_off.data() : nullptr;
     out->flat_edges = P.flat_ok ? P.flat_eid.data() : nullptr;
     out->owner_swap = P.owner_swap.empty() ? nullptr : P.owner_swap.data();
+    out->cluster_interior = P.cl_nint.data();
+    out->cluster_cut_offsets = P.cl_cut_off.data();
+    out->cluster_cut_edges = P.cl_cut_eid.data();
+    out->cluster_cut_ends = P.cl_cut_end.data();
     return OPF_OK;
 }
 

@@ -694,6 +694,68 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
                 }
             });
         }
+        // the owner kernel's two loops: the interior block of each cluster
+        // (leading edges of its range with both ends in it), then its cut
+        // visits, one (edge, owned end) pair each: the rest of its range, then
+        // its listed edges, one neighbour cluster at a time, each run spread
+        // over LDS banks by its owned ends
+        P.cl_nint.assign(ncl, 0);
+        for (int64_t c = 0; c < ncl; ++c) {
+            const int64_t p0 = P.cl_prim[2 * c], pn = P.cl_prim[2 * c + 1];
+            int64_t t = 0;
+            while (t < pn && P.e2n[2 * (p0 + t)] / K == c && P.e2n[2 * (p0 + t) + 1] / K == c) ++t;
+            P.cl_nint[c] = (int32_t)t;
+        }
+        std::vector<std::vector<int32_t>> cut_eid(ncl);
+        std::vector<std::vector<uint8_t>> cut_end(ncl);
+        parallel_for(ncl, [&](int64_t c) {
+            std::vector<int64_t> src;
+            const int64_t p0 = P.cl_prim[2 * c], pn = P.cl_prim[2 * c + 1];
+            for (int64_t e = p0 + P.cl_nint[c]; e < p0 + pn; ++e) src.push_back(e);
+            for (int64_t s = P.cl_sec_off[c]; s < P.cl_sec_off[c + 1]; ++s) src.push_back(P.cl_sec_eid[s]);
+            std::vector<int32_t> &ve = cut_eid[c];
+            std::vector<uint8_t> &vh = cut_end[c];
+            for (int64_t e : src)
+                for (int h = 0; h < 2; ++h)
+                    if (P.e2n[2 * e + h] / K == c) {
+                        ve.push_back((int32_t)e);
+                        vh.push_back((uint8_t)h);
+                    }
+            if (!opt.bank_spread) return;
+            std::vector<int32_t> ends, te;
+            std::vector<uint8_t> th;
+            std::vector<int8_t> fixed;
+            std::vector<int> perm;
+            std::vector<uint8_t> sw;
+            const int64_t n = (int64_t)ve.size();
+            for (int64_t a = 0; a < n;) {
+                auto other = [&](int64_t t) { return P.e2n[2 * ve[t] + (1 - vh[t])] / K; };
+                int64_t b = a + 1;
+                while (b < n && other(b) == other(a)) ++b;
+                const int64_t m = b - a;
+                ends.assign(2 * m, -1);
+                fixed.assign(m, 0);
+                for (int64_t t = 0; t < m; ++t)
+                    ends[2 * t] = (int32_t)(P.e2n[2 * ve[a + t] + vh[a + t]] - c * K);
+                const int lead = (int)((16 - a % 16) % 16);
+                quarter_groups((int)m, ends.data(), fixed.data(), lead, perm, sw);
+                te.assign(ve.begin() + a, ve.begin() + b);
+                th.assign(vh.begin() + a, vh.begin() + b);
+                for (int64_t t = 0; t < m; ++t) {
+                    ve[a + t] = te[perm[t]];
+                    vh[a + t] = th[perm[t]];
+                }
+                a = b;
+            }
+        });
+        P.cl_cut_off.assign(ncl + 1, 0);
+        for (int64_t c = 0; c < ncl; ++c) P.cl_cut_off[c + 1] = P.cl_cut_off[c] + (int64_t)cut_eid[c].size();
+        P.cl_cut_eid.resize(P.cl_cut_off[ncl]);
+        P.cl_cut_end.resize(P.cl_cut_off[ncl]);
+        for (int64_t c = 0; c < ncl; ++c) {
+            std::copy(cut_eid[c].begin(), cut_eid[c].end(), P.cl_cut_eid.begin() + P.cl_cut_off[c]);
+            std::copy(cut_end[c].begin(), cut_end[c].end(), P.cl_cut_end.begin() + P.cl_cut_off[c]);
+        }
         P.owner_ok = true;
     }
 
@@ -949,6 +1011,33 @@ VerifyResult verify_plan(const Plan &P, const int32_t *e2n_user)
             const int want = (P.e2n[2 * k] / K == P.e2n[2 * k + 1] / K) ? 1 : 2;
             if (seen[k] != want) return fail(8, k, "edge missing from its clusters' visit lists");
         }
+        // the two loops of the owner kernel cover every end of every edge exactly
+        // once: interior blocks both ends, each cut visit the end it names
+        if ((int64_t)P.cl_nint.size() != ncl || (int64_t)P.cl_cut_off.size() != ncl + 1 ||
+            P.cl_cut_off[0] != 0 || P.cl_cut_off[ncl] != (int64_t)P.cl_cut_eid.size() ||
+            P.cl_cut_eid.size() != P.cl_cut_end.size())
+            return fail(8, -1, "interior blocks or cut visits are inconsistent");
+        std::vector<uint8_t> ends(E, 0);  // bit h: end h covered
+        for (int64_t c = 0; c < ncl; ++c) {
+            const int64_t p0 = P.cl_prim[2 * c], ni = P.cl_nint[c];
+            if (ni < 0 || ni > P.cl_prim[2 * c + 1]) return fail(8, c, "interior block outside the range");
+            for (int64_t k = p0; k < p0 + ni; ++k) {
+                if (P.e2n[2 * k] / K != c || P.e2n[2 * k + 1] / K != c)
+                    return fail(8, k, "interior block holds an edge with an end outside the cluster");
+                if (ends[k]) return fail(8, k, "edge end covered twice");
+                ends[k] = 3;
+            }
+            for (int64_t s = P.cl_cut_off[c]; s < P.cl_cut_off[c + 1]; ++s) {
+                const int64_t k = P.cl_cut_eid[s];
+                const int h = P.cl_cut_end[s];
+                if (k < 0 || k >= E || h > 1) return fail(8, s, "cut visit out of range");
+                if (P.e2n[2 * k + h] / K != c) return fail(8, s, "cut visit names an end outside the cluster");
+                if (ends[k] & (1 << h)) return fail(8, k, "edge end covered twice");
+                ends[k] |= (uint8_t)(1 << h);
+            }
+        }
+        for (int64_t k = 0; k < E; ++k)
+            if (ends[k] != 3) return fail(8, k, "edge end missing from the owner kernel's loops");
     }
     // (9) flat colouring: every edge in exactly one colour; edges of one colour
     // share no node

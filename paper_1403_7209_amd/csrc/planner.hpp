@@ -73,6 +73,17 @@ struct Plan {
     // Per internal edge: 1 when the owner kernel should issue the second end's
     // LDS update first (bank spreading); empty when not computed.
     std::vector<uint8_t> owner_swap;
+    // The same work as the owner kernel runs it, in two loops.  Cluster c first
+    // runs its interior block [cl_prim[2c], cl_prim[2c] + cl_nint[c]): the
+    // leading edges of its range with both ends in c, read through local
+    // offsets.  Then its cut visits cl_cut_eid[cl_cut_off[c] .. [c+1]): every
+    // other (edge, end in c) pair, the end given by cl_cut_end (0: the edge's
+    // first node, 1: its second), one owned end per visit, ordered so that the
+    // owned ends of 16 consecutive visits fall in distinct LDS banks.
+    std::vector<int32_t> cl_nint;
+    std::vector<int64_t> cl_cut_off;
+    std::vector<int32_t> cl_cut_eid;
+    std::vector<uint8_t> cl_cut_end;
     // Flat colouring (one level over all edges; no partitions): edges
     // flat_eid[flat_off[c] .. flat_off[c+1]) have colour c and share no node.
     bool flat_ok = false;  // false when more than 128 colours would be needed

@@ -34,7 +34,7 @@ def test_traffic_profile_applies_only_to_its_sources_and_configuration():
         assert 1.0 < t / float(kv["algorithmic_bytes_per_launch"]) < 2.0
     else:
         assert t is None  # kernels changed since the counters were taken
-    assert bench.measured_traffic(DEFAULT_KEY + " owner_compact=True") is None
+    assert bench.measured_traffic(DEFAULT_KEY.replace("bank_spread=True", "bank_spread=False")) is None
     assert bench.measured_traffic(DEFAULT_KEY.replace("n=160", "n=100")) is None
 
 

@@ -124,6 +124,24 @@ def check_plan_properties(m, ctx, nodes, edges, mp):
             assert np.all((cl[:, 0] == c) | (cl[:, 1] == c))
             cnt[ks] += 1
         assert np.array_equal(cnt, want)
+        # the owner kernel's two loops: the interior block (leading edges of the
+        # range with both ends in the cluster), then one cut visit per other
+        # (edge, owned end) pair; together every end of every edge exactly once
+        ni, co = v["cluster_interior"], v["cluster_cut_offsets"]
+        ce, ch = v["cluster_cut_edges"].astype(np.int64), v["cluster_cut_ends"].astype(np.int64)
+        assert co[0] == 0 and co[-1] == len(ce) == len(ch) and np.all(np.diff(co) >= 0)
+        assert np.all(ch <= 1)
+        cover = np.zeros((m.E, 2), np.int64)
+        for c in range(v["nclusters"]):
+            r0, rn = rng[c]
+            assert 0 <= ni[c] <= rn
+            blk = np.arange(r0, r0 + ni[c])
+            assert np.all(e2n[blk] // K == c)
+            cover[blk] += 1
+            es, hs = ce[co[c]:co[c + 1]], ch[co[c]:co[c + 1]]
+            assert np.all(e2n[es, hs] // K == c)
+            np.add.at(cover, (es, hs), 1)
+        assert np.all(cover == 1)
         return contiguous / v["nclusters"]
 
 
@@ -186,30 +204,35 @@ def test_lane_groups_make_wavefront_endpoints_distinct():
 
 
 def owner_bank_conflicts(v):
-    """Excess same-bank LDS words over the owner kernel's wavefronts: lanes run
-    the cluster's visits in order; per lane the first and second owned end (the
-    swap flag reverses them) each form one LDS instruction; the LDS serves a
-    quarter-wave per pass with 16 banks of 8-byte words, so count equal offsets
-    mod 16 per quarter-wave beyond the first."""
+    """Excess same-bank LDS words over the owner kernel's wavefronts.  Interior
+    loop: lanes run the cluster's interior block in order, each updating its
+    edge's first and second end (the swap flag reverses them) with one LDS
+    instruction each; cut loop: lanes run the cut visits in order, one owned end
+    each.  The LDS serves a quarter-wave per pass with 16 banks of 8-byte words,
+    so count equal offsets mod 16 per quarter-wave beyond the first."""
     K, e2n = v["cluster_size"], v["e2n"].astype(np.int64)
-    rng, loff, led = v["cluster_range"], v["cluster_list_offsets"], v["cluster_list_edges"]
+    rng, ni = v["cluster_range"], v["cluster_interior"]
+    co, ce, ch = v["cluster_cut_offsets"], v["cluster_cut_edges"], v["cluster_cut_ends"]
     swap = v["owner_swap"]
+
+    def excess(offsets):
+        lane = np.arange(len(offsets)) % 64
+        chunk = np.arange(len(offsets)) // 64
+        key = (chunk * 4 + lane // 16) * 16 + offsets % 16
+        _, cnt = np.unique(key, return_counts=True)
+        return int((cnt - 1).sum())
+
     total = 0
     for c in range(v["nclusters"]):
-        vis = np.concatenate([np.arange(rng[c, 0], rng[c, 0] + rng[c, 1]), led[loff[c]:loff[c + 1]]])
+        vis = np.arange(rng[c, 0], rng[c, 0] + ni[c])
         ends = e2n[vis].copy()
         if swap is not None:
             s = swap[vis].astype(bool)
             ends[s] = ends[s][:, ::-1]
-        own = np.where(ends // K == c, ends - c * K, -1)
-        lane = np.arange(len(vis)) % 64
-        chunk = np.arange(len(vis)) // 64
         for slot in range(2):
-            o = own[:, slot]
-            m = o >= 0
-            key = (chunk[m] * 4 + lane[m] // 16) * 16 + o[m] % 16
-            _, cnt = np.unique(key, return_counts=True)
-            total += int((cnt - 1).sum())
+            total += excess(ends[:, slot] - c * K)
+        es, hs = ce[co[c]:co[c + 1]], ch[co[c]:co[c + 1]]
+        total += excess(e2n[es, hs] - c * K)
     return total
 
 
