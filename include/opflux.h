@@ -209,6 +209,11 @@ typedef struct {
                                    through 4-byte words of local offsets)         */
     int32_t flat_colours;       /* colours of the flat colouring                  */
     int32_t flat_ok;            /* 1 when the FLAT variant can run (<= 128)       */
+    int32_t coloured_ok;        /* 1 when the plan has the two-level colouring;
+                                   0 when it could not be built (more than 1024
+                                   partition colours, as in an unrenumbered
+                                   mesh): the COLOURED variants then refuse to
+                                   run (OPF_EINVAL), the others are unaffected   */
 } opf_plan_info;
 
 /* Builds the execution plan of an arity-2 map (edges -> nodes) on the host
@@ -233,7 +238,10 @@ int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info
 int opf_get_perm(const opf_ctx *ctx, opf_set s, int32_t *new_of_old);
 
 /* Read-only view of a plan's host arrays (valid until opf_finalize or the next
- * opf_plan on the same map).  Internal numbering throughout. */
+ * opf_plan on the same map).  Internal numbering throughout.  Without the
+ * two-level colouring (opf_plan_info.coloured_ok == 0) the colouring arrays
+ * (block_colour, colour_blocks, colour_offsets, elem_colour, block_ncolours,
+ * unique_offsets, unique_nodes, local_idx) are NULL and nblock_colours is 0. */
 typedef struct {
     int64_t nnodes, nedges, nblocks;
     int32_t nblock_colours, block_size;

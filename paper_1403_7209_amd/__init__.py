@@ -78,7 +78,7 @@ class PlanInfo(ctypes.Structure):
                 ("owner_edge_visits", ctypes.c_int64), ("max_cluster_segments", ctypes.c_int32),
                 ("owner_ok", ctypes.c_int32), ("owner_compact", ctypes.c_int32),
                 ("flat_colours", ctypes.c_int32),
-                ("flat_ok", ctypes.c_int32)]
+                ("flat_ok", ctypes.c_int32), ("coloured_ok", ctypes.c_int32)]
 
 
 class PlanView(ctypes.Structure):
@@ -262,6 +262,8 @@ class Context:
         def arr(ptr, ctype, n, dtype):
             if n == 0:
                 return np.empty(0, dtype=dtype)
+            if not ptr:  # an array the plan does not have (no two-level colouring)
+                return None
             buf = (ctype * n).from_address(ptr)
             return np.frombuffer(buf, dtype=dtype).copy()
 
@@ -292,8 +294,10 @@ class Context:
                     elem_colour=arr(v.elem_colour, ctypes.c_uint8, E, np.uint8),
                     block_ncolours=arr(v.block_ncolours, ctypes.c_int32, nb, np.int32),
                     unique_offsets=uoff,
-                    unique_nodes=arr(v.unique_nodes, ctypes.c_int32, int(uoff[-1]), np.int32),
-                    local_idx=arr(v.local_idx, ctypes.c_uint16, 2 * E, np.uint16).reshape(E, 2),
+                    unique_nodes=None if uoff is None else
+                    arr(v.unique_nodes, ctypes.c_int32, int(uoff[-1]), np.int32),
+                    local_idx=None if not v.local_idx else
+                    arr(v.local_idx, ctypes.c_uint16, 2 * E, np.uint16).reshape(E, 2),
                     nflat_colours=v.nflat_colours,
                     flat_offsets=arr(v.flat_offsets, ctypes.c_int64, v.nflat_colours + 1,
                                      np.int64) if v.nflat_colours else None,

@@ -243,13 +243,18 @@ int upload_plan(opf_ctx *ctx, PlanRec &pr)
         if (!rc) rc = upload(ctx, pr, P.flat_eid, D.flat_eid);
     }
     if (!rc) rc = upload(ctx, pr, e2n, D.e2n);
-    if (!rc) rc = upload(ctx, pr, block_off, D.block_off);
-    if (!rc) rc = upload(ctx, pr, uniq_off, D.uniq_off);
-    if (!rc) rc = upload(ctx, pr, P.uniq, D.uniq);
-    if (!rc) rc = upload(ctx, pr, lidx, D.lidx);
-    if (!rc) rc = upload(ctx, pr, P.ecol, D.ecol);
-    if (!rc) rc = upload(ctx, pr, P.block_ncol, D.block_ncol);
-    if (!rc) rc = upload(ctx, pr, P.colour_blocks, D.colour_blocks);
+    if (P.coloured_ok) {
+        if (!rc) rc = upload(ctx, pr, block_off, D.block_off);
+        if (!rc) rc = upload(ctx, pr, uniq_off, D.uniq_off);
+        if (!rc) rc = upload(ctx, pr, P.uniq, D.uniq);
+        if (!rc) rc = upload(ctx, pr, lidx, D.lidx);
+        if (!rc) rc = upload(ctx, pr, P.ecol, D.ecol);
+        if (!rc) rc = upload(ctx, pr, P.block_ncol, D.block_ncol);
+        if (!rc) rc = upload(ctx, pr, P.colour_blocks, D.colour_blocks);
+    } else {
+        D.nc = 0;
+        D.colour_off.assign(1, 0);
+    }
     if (rc) {
         free_plan(ctx, pr);
         return rc;
@@ -541,6 +546,9 @@ int edge_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *arg
         return ctx->fail(OPF_EINVAL, "the plan has no owner clusters (cluster_size 0)");
     if (variant == OPF_V_FLAT && pr.dev.nflat <= 0)
         return ctx->fail(OPF_EINVAL, "the map needs more than 128 flat colours");
+    if ((variant == OPF_V_COLOURED || variant == OPF_V_COLOURED_LDS_ATOMIC) && !pr.host.coloured_ok)
+        return ctx->fail(OPF_EINVAL, "the plan has no two-level colouring (" + pr.host.coloured_why +
+                                         "): use the OWNER or ATOMIC variant");
     if (variant != OPF_V_ATOMIC && variant != OPF_V_FLAT) {
         const size_t lds = opf::gpu::edge_lds_bytes(op, fp32, variant, pr.dev.umax, pr.dev.K);
         if (lds > ctx->max_lds)
@@ -1102,6 +1110,7 @@ int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info
         info->owner_compact = P.owner_ok ? 1 : 0;
         info->flat_colours = P.flat_colours;
         info->flat_ok = P.flat_ok ? 1 : 0;
+        info->coloured_ok = P.coloured_ok ? 1 : 0;
     }
     ctx->plans[map] = std::move(pr);
     return OPF_OK;
@@ -1156,6 +1165,16 @@ int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out)
     out->flat_offsets = P.flat_ok ? P.flat_off.data() : nullptr;
     out->flat_edges = P.flat_ok ? P.flat_eid.data() : nullptr;
     out->owner_swap = P.owner_swap.empty() ? nullptr : P.owner_swap.data();
+    if (!P.coloured_ok) {  // no two-level colouring: its arrays are absent
+        out->block_colour = nullptr;
+        out->colour_blocks = nullptr;
+        out->colour_offsets = nullptr;
+        out->elem_colour = nullptr;
+        out->block_ncolours = nullptr;
+        out->unique_offsets = nullptr;
+        out->unique_nodes = nullptr;
+        out->local_idx = nullptr;
+    }
     out->cluster_interior = P.cl_nint.data();
     out->cluster_cut_offsets = P.cl_cut_off.data();
     out->cluster_cut_edges = P.cl_cut_eid.data();

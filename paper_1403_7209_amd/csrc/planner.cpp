@@ -521,8 +521,9 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
             P.lidx[2 * k + 1] = (uint16_t)lj;
             int c = lowest_free(lmask[li] | lmask[lj]);
             if (c < 0 || c > 255) {
-                err = "more than 64 edge colours in partition " + std::to_string(b);
-                return OPF_EPLAN;
+                P.coloured_ok = false;
+                P.coloured_why = "more than 64 edge colours in partition " + std::to_string(b);
+                break;
             }
             lmask[li] |= 1ULL << c;
             lmask[lj] |= 1ULL << c;
@@ -536,15 +537,16 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
         P.uniq.insert(P.uniq.end(), nodes.begin(), nodes.end());
         P.uniq_off[b + 1] = (int64_t)P.uniq.size();
         P.max_unique = std::max<int32_t>(P.max_unique, (int32_t)nodes.size());
-        if (nodes.size() > 65535) {
-            err = "partition with more than 65535 distinct nodes";
-            return OPF_EPLAN;
+        if (nodes.size() > 65535 && P.coloured_ok) {
+            P.coloured_ok = false;
+            P.coloured_why = "partition with more than 65535 distinct nodes";
         }
+        if (!P.coloured_ok) break;
     }
     P.mean_elem_colours = (double)ncol_sum / (double)nb;
 
     // (7) optional: order each partition's edges by colour (stable)
-    if (opt.colour_sort) {
+    if (opt.colour_sort && P.coloured_ok) {
         std::vector<int32_t> idx;
         std::vector<int32_t> t_e2n, t_order;
         std::vector<uint16_t> t_lidx;
@@ -799,16 +801,17 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
     // already sharing one of its nodes.  Colours are handed out in rounds of 64
     // (one bit mask per node per round); a partition that finds all 64 colours
     // of a round taken waits for the next round.
-    {
+    if (P.coloured_ok) {
         std::vector<uint64_t> nmask(N, 0);
         P.block_colour.assign(nb, -1);
         std::vector<int32_t> todo(nb), next;
         std::iota(todo.begin(), todo.end(), 0);
-        int base = 0, nc = 0;
+        int base = 0;
         while (!todo.empty()) {
             if (base >= kMaxBlockColours) {
-                err = "more than " + std::to_string(kMaxBlockColours) + " partition colours";
-                return OPF_EPLAN;
+                P.coloured_ok = false;
+                P.coloured_why = "more than " + std::to_string(kMaxBlockColours) + " partition colours";
+                break;
             }
             std::fill(nmask.begin(), nmask.end(), 0);
             next.clear();
@@ -823,11 +826,17 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
                 for (int64_t u = P.uniq_off[b]; u < P.uniq_off[b + 1]; ++u)
                     nmask[P.uniq[u]] |= 1ULL << c;
                 P.block_colour[b] = base + c;
-                nc = std::max(nc, base + c + 1);
             }
             todo.swap(next);
             base += 64;
         }
+    }
+    if (P.coloured_ok) {
+        const int nc = [&] {
+            int m = 0;
+            for (int32_t c : P.block_colour) m = std::max(m, c + 1);
+            return m;
+        }();
         P.nblock_colours = nc;
         P.colour_off.assign(nc + 1, 0);
         for (int64_t b = 0; b < nb; ++b) ++P.colour_off[P.block_colour[b] + 1];
@@ -846,11 +855,26 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
         for (int64_t b = 0; b < nb; ++b) P.block_colour[b] = remap[P.block_colour[b]];
         P.colour_off.swap(off2);
         P.nblock_colours = (int32_t)P.colour_off.size() - 1;
-        nc = P.nblock_colours;
         P.min_blocks_per_colour = (int32_t)nb;
-        for (int c = 0; c < nc; ++c)
+        for (int c = 0; c < P.nblock_colours; ++c)
             P.min_blocks_per_colour = std::min<int32_t>(
                 P.min_blocks_per_colour, (int32_t)(P.colour_off[c + 1] - P.colour_off[c]));
+    }
+    if (!P.coloured_ok) {
+        // the coloured variants are unavailable: drop their partial arrays
+        P.block_colour.clear();
+        P.colour_blocks.clear();
+        P.colour_off.assign(1, 0);
+        P.nblock_colours = 0;
+        P.min_blocks_per_colour = 0;
+        P.ecol.assign(E, 0);
+        P.block_ncol.assign(nb, 0);
+        P.uniq.clear();
+        P.uniq_off.assign(nb + 1, 0);
+        P.lidx.assign(2 * E, 0);
+        P.max_elem_colours = 0;
+        P.mean_elem_colours = 0.0;
+        P.max_unique = 0;
     }
     lap(3);
     return OPF_OK;
@@ -898,68 +922,71 @@ VerifyResult verify_plan(const Plan &P, const int32_t *e2n_user)
         int64_t n = P.block_off[b + 1] - P.block_off[b];
         if (n <= 0 || n > P.block_size) return fail(5, b, "partition size out of range");
     }
-    if ((int64_t)P.colour_off.size() != P.nblock_colours + 1 || P.colour_off[0] != 0 ||
-        P.colour_off[P.nblock_colours] != nb || (int64_t)P.colour_blocks.size() != nb)
-        return fail(5, -1, "colour offsets do not cover the partitions");
-    {
-        std::vector<char> seen(nb, 0);
-        for (int c = 0; c < P.nblock_colours; ++c) {
-            if (P.colour_off[c + 1] <= P.colour_off[c]) return fail(5, c, "empty partition colour");
-            for (int64_t k = P.colour_off[c]; k < P.colour_off[c + 1]; ++k) {
-                int32_t b = P.colour_blocks[k];
-                if (b < 0 || b >= nb || seen[b] || P.block_colour[b] != c)
-                    return fail(5, k, "partition listed under the wrong colour or twice");
-                seen[b] = 1;
-            }
-        }
-    }
-    // (7) colour counts fit their types
-    if (P.nblock_colours < 1 || P.nblock_colours > kMaxBlockColours)
-        return fail(7, -1, "partition colour count");
-    for (int64_t b = 0; b < nb; ++b)
-        if (P.block_ncol[b] < 1 || P.block_ncol[b] > 64) return fail(7, b, "edge colour count");
-    // (6) local indices resolve to the map's nodes; unique lists sorted and distinct
-    if ((int64_t)P.uniq_off.size() != nb + 1 || P.uniq_off[nb] != (int64_t)P.uniq.size())
-        return fail(6, -1, "distinct-node offsets do not match the lists");
-    for (int64_t b = 0; b < nb; ++b) {
-        const int64_t u0 = P.uniq_off[b], nu = P.uniq_off[b + 1] - u0;
-        if (nu < 1 || nu > 65535) return fail(7, b, "distinct-node count out of range");
-        for (int64_t u = 1; u < nu; ++u)
-            if (P.uniq[u0 + u] <= P.uniq[u0 + u - 1]) return fail(6, b, "distinct nodes not sorted");
-        for (int64_t k = P.block_off[b]; k < P.block_off[b + 1]; ++k)
-            for (int s = 0; s < 2; ++s) {
-                int64_t l = P.lidx[2 * k + s];
-                if (l >= nu || P.uniq[u0 + l] != P.e2n[2 * k + s])
-                    return fail(6, k, "local index does not resolve to the map's node");
-            }
-        for (int64_t k = P.block_off[b]; k < P.block_off[b + 1]; ++k)
-            if (P.ecol[k] >= P.block_ncol[b]) return fail(7, k, "edge colour above the count");
-    }
-    // (3) partitions of one colour share no node
-    {
-        std::vector<int32_t> stamp(N, -1);
-        for (int c = 0; c < P.nblock_colours; ++c)
-            for (int64_t k = P.colour_off[c]; k < P.colour_off[c + 1]; ++k) {
-                const int32_t b = P.colour_blocks[k];
-                for (int64_t u = P.uniq_off[b]; u < P.uniq_off[b + 1]; ++u) {
-                    const int32_t v = P.uniq[u];
-                    if (stamp[v] == c) return fail(3, b, "two partitions of one colour share a node");
-                    stamp[v] = c;
+    // properties 3-7 hold for the two-level colouring, when the plan has one
+    if (P.coloured_ok) {
+        if ((int64_t)P.colour_off.size() != P.nblock_colours + 1 || P.colour_off[0] != 0 ||
+            P.colour_off[P.nblock_colours] != nb || (int64_t)P.colour_blocks.size() != nb)
+            return fail(5, -1, "colour offsets do not cover the partitions");
+        {
+            std::vector<char> seen(nb, 0);
+            for (int c = 0; c < P.nblock_colours; ++c) {
+                if (P.colour_off[c + 1] <= P.colour_off[c]) return fail(5, c, "empty partition colour");
+                for (int64_t k = P.colour_off[c]; k < P.colour_off[c + 1]; ++k) {
+                    int32_t b = P.colour_blocks[k];
+                    if (b < 0 || b >= nb || seen[b] || P.block_colour[b] != c)
+                        return fail(5, k, "partition listed under the wrong colour or twice");
+                    seen[b] = 1;
                 }
             }
-    }
-    // (4) inside a partition, edges of one colour share no node
-    {
-        std::vector<uint64_t> lm;
+        }
+        // (7) colour counts fit their types
+        if (P.nblock_colours < 1 || P.nblock_colours > kMaxBlockColours)
+            return fail(7, -1, "partition colour count");
+        for (int64_t b = 0; b < nb; ++b)
+            if (P.block_ncol[b] < 1 || P.block_ncol[b] > 64) return fail(7, b, "edge colour count");
+        // (6) local indices resolve to the map's nodes; unique lists sorted and distinct
+        if ((int64_t)P.uniq_off.size() != nb + 1 || P.uniq_off[nb] != (int64_t)P.uniq.size())
+            return fail(6, -1, "distinct-node offsets do not match the lists");
         for (int64_t b = 0; b < nb; ++b) {
-            lm.assign(P.uniq_off[b + 1] - P.uniq_off[b], 0);
-            for (int64_t k = P.block_off[b]; k < P.block_off[b + 1]; ++k) {
-                uint64_t bit = 1ULL << P.ecol[k];
-                int li = P.lidx[2 * k], lj = P.lidx[2 * k + 1];
-                if ((lm[li] & bit) || (lm[lj] & bit) || li == lj)
-                    return fail(4, k, "two edges of one colour share a node");
-                lm[li] |= bit;
-                lm[lj] |= bit;
+            const int64_t u0 = P.uniq_off[b], nu = P.uniq_off[b + 1] - u0;
+            if (nu < 1 || nu > 65535) return fail(7, b, "distinct-node count out of range");
+            for (int64_t u = 1; u < nu; ++u)
+                if (P.uniq[u0 + u] <= P.uniq[u0 + u - 1]) return fail(6, b, "distinct nodes not sorted");
+            for (int64_t k = P.block_off[b]; k < P.block_off[b + 1]; ++k)
+                for (int s = 0; s < 2; ++s) {
+                    int64_t l = P.lidx[2 * k + s];
+                    if (l >= nu || P.uniq[u0 + l] != P.e2n[2 * k + s])
+                        return fail(6, k, "local index does not resolve to the map's node");
+                }
+            for (int64_t k = P.block_off[b]; k < P.block_off[b + 1]; ++k)
+                if (P.ecol[k] >= P.block_ncol[b]) return fail(7, k, "edge colour above the count");
+        }
+        // (3) partitions of one colour share no node
+        {
+            std::vector<int32_t> stamp(N, -1);
+            for (int c = 0; c < P.nblock_colours; ++c)
+                for (int64_t k = P.colour_off[c]; k < P.colour_off[c + 1]; ++k) {
+                    const int32_t b = P.colour_blocks[k];
+                    for (int64_t u = P.uniq_off[b]; u < P.uniq_off[b + 1]; ++u) {
+                        const int32_t v = P.uniq[u];
+                        if (stamp[v] == c) return fail(3, b, "two partitions of one colour share a node");
+                        stamp[v] = c;
+                    }
+                }
+        }
+        // (4) inside a partition, edges of one colour share no node
+        {
+            std::vector<uint64_t> lm;
+            for (int64_t b = 0; b < nb; ++b) {
+                lm.assign(P.uniq_off[b + 1] - P.uniq_off[b], 0);
+                for (int64_t k = P.block_off[b]; k < P.block_off[b + 1]; ++k) {
+                    uint64_t bit = 1ULL << P.ecol[k];
+                    int li = P.lidx[2 * k], lj = P.lidx[2 * k + 1];
+                    if ((lm[li] & bit) || (lm[lj] & bit) || li == lj)
+                        return fail(4, k, "two edges of one colour share a node");
+                    lm[li] |= bit;
+                    lm[lj] |= bit;
+                }
             }
         }
     }

@@ -45,6 +45,13 @@ struct Plan {
     std::vector<int64_t> uniq_off;   // [nb+1]
     std::vector<int32_t> uniq;       // sum U_b
     std::vector<uint16_t> lidx;      // [2E]
+    // false when the two-level colouring of Sec. 4.1 could not be built (more
+    // than kMaxBlockColours partition colours, more than 64 edge colours or
+    // 65535 distinct nodes in a partition): the coloured variants are then
+    // unavailable and their arrays empty, while the rest of the plan (owner
+    // clusters, flat colouring) stays valid
+    bool coloured_ok = true;
+    std::string coloured_why;
     int32_t nblock_colours = 0;
     int32_t max_elem_colours = 0;
     double mean_elem_colours = 0.0;
@@ -91,7 +98,7 @@ struct Plan {
     std::vector<int64_t> flat_off;
     std::vector<int32_t> flat_eid;
     int64_t nclusters() const { return cluster_size ? (N + cluster_size - 1) / cluster_size : 0; }
-    int64_t nblocks() const { return (int64_t)block_colour.size(); }
+    int64_t nblocks() const { return block_off.empty() ? 0 : (int64_t)block_off.size() - 1; }
 };
 
 // Builds a plan of the map e2n (2E entries, 0-based, user numbering).

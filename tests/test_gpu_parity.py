@@ -37,8 +37,10 @@ def problem(m, q, fp32=False, renumber="rcm", block_size=512, colour_sort=False,
 
 
 def variants(p):
+    coloured = (pk.COLOURED, pk.COLOURED_LDS_ATOMIC)
     return [v for v in ALL_VARIANTS
-            if (v != pk.OWNER or p.info["owner_ok"]) and (v != pk.FLAT or p.info["flat_ok"])]
+            if (v != pk.OWNER or p.info["owner_ok"]) and (v != pk.FLAT or p.info["flat_ok"])
+            and (v not in coloured or p.info["coloured_ok"])]
 
 
 def gpu_residual(p, variant):
@@ -433,4 +435,33 @@ def test_geometry_after_replanning():
                           normwise(w.cpu().numpy()[:, edge_new], w_ref), TOL64)
             assert report(f"geometry vol after plan {tag}",
                           normwise(vol.cpu().numpy()[:, node_new], vol_ref[None]), TOL64)
+    ctx.close()
+
+
+def test_owner_and_atomic_without_colouring():
+    """A map whose partitions cannot be coloured (a hub node in every
+    partition): the plan keeps its owner clusters, the owner and atomic edge
+    loops and the fused stage match the oracle, and the coloured variants
+    refuse to run."""
+    from tests.test_planner_abi import hub_map
+    N, e2n = hub_map()
+    print(f"[hub map: N={N} E={len(e2n)}]", flush=True)
+    rng = np.random.default_rng(71)
+    w = rng.normal(size=(3, len(e2n))) * 1e-2
+    vol = np.full(N, 1e-3)
+    q = meshgen.state(N)
+    ctx = pk.Context(DEV)
+    p = pk.FluxProblem(ctx, e2n, w, vol, q, renumber="none", cluster_size=512)
+    assert p.info["coloured_ok"] == 0 and p.info["owner_ok"] == 1
+    ref = oracle.residual(e2n, q, w)
+    for variant in (pk.OWNER, pk.ATOMIC):
+        assert report(f"hub residual v{variant}", normwise(gpu_residual(p, variant), ref), TOL64)
+    for variant in (pk.COLOURED, pk.COLOURED_LDS_ATOMIC):
+        with pytest.raises(pk.OpfError):
+            gpu_residual(p, variant)
+    dt = 1e-6  # the hub's 1100 edges: a small step keeps its state physical
+    q1, ss = oracle.rk_iteration(e2n, q, w, vol, dt)
+    p.rk_iteration(dt, pk.OWNER)
+    ctx.sync()
+    assert report("hub fused iteration", normwise(p.nodes_out(p.qa), q1), TOL64)
     ctx.close()

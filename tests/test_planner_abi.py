@@ -169,6 +169,43 @@ def test_plan_properties(renumber, bs, K, lg, csort, spread, halo):
         assert csort or contiguous == 1.0
 
 
+def hub_map(parts=1100, per=511):
+    """A matching of 2 * per * parts nodes plus one hub node joined to one node
+    of every run of `per` pairs: every partition holds a hub edge, so the
+    partitions all conflict and need more colours than a plan allows."""
+    M = 2 * per * parts
+    pairs = np.stack([np.arange(0, M, 2), np.arange(1, M, 2)], 1)
+    hub = np.stack([np.arange(0, M, 2 * per), np.full(parts, M)], 1)
+    return M + 1, np.ascontiguousarray(np.concatenate([pairs, hub]).astype(np.int32))
+
+
+def test_plan_degrades_per_variant():
+    """When the two-level colouring cannot be built the plan stays valid for
+    the owner clusters: coloured_ok is 0, the colouring arrays are absent, the
+    owner kernel's work covers every edge end once, and the verifier passes."""
+    N, e2n = hub_map()
+    ctx = pk.Context(None)
+    nodes = ctx.decl_set(N)
+    edges = ctx.decl_set(len(e2n))
+    mp = ctx.decl_map(edges, nodes, 2, e2n)
+    info = ctx.plan(mp, renumber="none", cluster_size=512)
+    assert info["coloured_ok"] == 0 and info["nblock_colours"] == 0
+    assert info["owner_ok"] == 1
+    assert ctx.plan_verify(mp)["ok"]
+    v = ctx.plan_view(mp)
+    assert v["block_colour"] is None and v["local_idx"] is None and v["unique_nodes"] is None
+    K, ie = v["cluster_size"], v["e2n"].astype(np.int64)
+    cover = np.zeros((len(e2n), 2), np.int64)
+    rng, ni = v["cluster_range"], v["cluster_interior"]
+    co, ce, ch = v["cluster_cut_offsets"], v["cluster_cut_edges"], v["cluster_cut_ends"]
+    for c in range(v["nclusters"]):
+        cover[rng[c, 0]:rng[c, 0] + ni[c]] += 1
+        es, hs = ce[co[c]:co[c + 1]].astype(np.int64), ch[co[c]:co[c + 1]].astype(np.int64)
+        assert np.all(ie[es, hs] // K == c)
+        np.add.at(cover, (es, hs), 1)
+    assert np.all(cover == 1)
+
+
 def test_renumbering_reduces_bandwidth_and_verifier_on_config_a():
     m = meshgen.config_mesh("A")
     _, _, _, _, info = host_problem(m, renumber="rcm")
