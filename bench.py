@@ -101,9 +101,25 @@ def measured_traffic(config_key):
         return None
 
 
+def host_cpu():
+    """The host's CPU model name (from /proc/cpuinfo) and its logical CPU count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
 def cpu_baseline(mesh, q, seconds=12.0):
     """The oracle (single thread) on a bounded sample of the same workload:
-    repeated FP64 residual passes over the full mesh until ~`seconds` elapse."""
+    repeated FP64 residual passes over the full mesh until ~`seconds` elapse,
+    in the input's own (randomly permuted) node numbering, which is what the
+    oracle is given; it does not renumber."""
     import oracle
     passes, t0 = 0, time.perf_counter()
     res = np.zeros_like(q)
@@ -113,9 +129,12 @@ def cpu_baseline(mesh, q, seconds=12.0):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
+    model, nproc = host_cpu()
     return {"value": passes * mesh.E / el, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "host_nproc": nproc,
             "sample": f"{passes} sequential FP64 residual passes over all {mesh.E} edges "
-                      f"of the same mesh ({el:.1f} s, one thread)"}
+                      f"of the same mesh in its input (randomly permuted) numbering "
+                      f"({el:.1f} s, one thread of {nproc})"}
 
 
 def cpu_baseline_sweep():

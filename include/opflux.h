@@ -140,8 +140,10 @@ int opf_finalize(opf_ctx *ctx);
 const char *opf_last_error(const opf_ctx *ctx);
 
 /* Optional device allocator for plan arrays and scratch: alloc(user, bytes)
- * returns device memory or NULL; free(user, ptr) releases it.  Must be set
- * before the first opf_plan.  NULL functions restore hipMalloc / hipFree.
+ * returns device memory aligned to at least 16 bytes (the kernels read plan
+ * arrays and partial sums as 8- and 16-byte words), or NULL; free(user, ptr)
+ * releases it.  Must be set before the first opf_plan.  NULL functions restore
+ * hipMalloc / hipFree.
  * Errors: OPF_ESTATE (a plan already exists). */
 int opf_set_allocator(opf_ctx *ctx, void *(*alloc_fn)(void *user, size_t bytes),
                       void (*free_fn)(void *user, void *ptr), void *user);

@@ -939,12 +939,13 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
             const bool pre = K <= NT;
             const double vi = pre ? pvol : ld(sp.vol, g);
             const double adt = sp.dt ? sp.adt * ld(sp.dt, g) : sp.adt;
+            const double step = adt / vi;  // one division per node
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
                 const double r = sy[k * K + v];
                 acc[k] += r * r;
                 const double base = pre ? pq0[k] : (double)ld(sp.q0[k], g);
-                st(sp.q[k], g, (T)(base - adt * r / vi));
+                st(sp.q[k], g, (T)(base - step * r));
             }
         }
         bool done = false;
@@ -986,11 +987,12 @@ __global__ __launch_bounds__(kRkThreads) void k_rk_stage(int N, RkPtrs<T> a, dou
     for (int i = (int)blockIdx.x * kRkThreads + (int)threadIdx.x; i < N; i += stride) {
         const double vi = a.vol[i];
         const double adt = a.dt ? alpha_dt * a.dt[i] : alpha_dt;
+        const double step = adt / vi;  // one division per node
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
             const double r = a.res[v][i];
             acc[v] += r * r;
-            a.q[v][i] = (T)((double)a.q0[v][i] - adt * r / vi);
+            a.q[v][i] = (T)((double)a.q0[v][i] - step * r);
             if (!keep_res) a.res[v][i] = 0.0;
         }
     }
@@ -1007,26 +1009,31 @@ __global__ __launch_bounds__(kRkThreads) void k_local_dt(int N, const double *__
 }
 
 // ss[0..5] += the sum of nparts rows of 6 partial sums.  One workgroup; each
-// thread owns a fixed set of rows and issues the loads of kSumUnroll rows at
-// once (the kernel is latency-bound), so the order of the additions is fixed.
-constexpr int kSumThreads = 1024, kSumUnroll = 4;
+// thread owns a fixed set of rows and issues the loads of kSumRows rows at once
+// as 16-byte words (the kernel is latency-bound: one round trip for up to
+// 8192 rows), so the order of the additions is fixed.
+constexpr int kSumThreads = 1024, kSumRows = 8;
 
 __global__ __launch_bounds__(kSumThreads) void k_sum_partials(int nparts, const double *partial,
                                                               double *ss)
 {
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int k0 = threadIdx.x; k0 < nparts; k0 += kSumThreads * kSumUnroll) {
-        double r[kSumUnroll][6];
+    const double2 *p2 = reinterpret_cast<const double2 *>(partial);  // a row is 3 words
+    for (int r0 = threadIdx.x; r0 < nparts; r0 += kSumThreads * kSumRows) {
+        double2 r[kSumRows][3];
 #pragma unroll
-        for (int u = 0; u < kSumUnroll; ++u) {
-            const int k = k0 + u * kSumThreads;
+        for (int u = 0; u < kSumRows; ++u) {
+            const int k = r0 + u * kSumThreads;
 #pragma unroll
-            for (int v = 0; v < 6; ++v) r[u][v] = k < nparts ? partial[6 * k + v] : 0.0;
+            for (int w = 0; w < 3; ++w) r[u][w] = k < nparts ? p2[3 * k + w] : make_double2(0.0, 0.0);
         }
 #pragma unroll
-        for (int u = 0; u < kSumUnroll; ++u)
+        for (int u = 0; u < kSumRows; ++u)
 #pragma unroll
-            for (int v = 0; v < 6; ++v) acc[v] += r[u][v];
+            for (int w = 0; w < 3; ++w) {
+                acc[2 * w] += r[u][w].x;
+                acc[2 * w + 1] += r[u][w].y;
+            }
     }
     // fixed tree through LDS: 64 lanes x 16 per component, then 8 x 8, then 8
     __shared__ double buf[6 * kSumThreads];

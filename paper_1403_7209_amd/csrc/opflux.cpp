@@ -108,7 +108,14 @@ struct opf_ctx {
     void *dalloc(size_t bytes)
     {
         if (bytes == 0) bytes = 256;
-        if (alloc_fn) return alloc_fn(alloc_user, bytes);
+        if (alloc_fn) {
+            void *p = alloc_fn(alloc_user, bytes);
+            if (p && (reinterpret_cast<uintptr_t>(p) & 15u)) {  // the kernels need 16-byte words
+                if (free_fn) free_fn(alloc_user, p);
+                return nullptr;
+            }
+            return p;
+        }
         void *p = nullptr;
         return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
     }
