@@ -4,7 +4,8 @@ Workload: the periodic 160^3 box (4,096,000 nodes) split into a layered mix of
 5- and 6-tet cubes (26,624,000 edges), nodes jittered by U(-0.25h, 0.25h) and
 randomly relabelled, then renumbered by the planner.  All inputs are seeded
 and synthetic.  `--mesh B` runs the same step on the 1,000,000-node 100^3 box
-of 6-tet cubes jittered by U(-0.2h, 0.2h).
+of 6-tet cubes jittered by U(-0.2h, 0.2h), `--mesh A` on the 8,000-node 20^3
+box of 6-tet cubes without jitter.
 
 One step = one 5-stage Runge-Kutta iteration in FP64 (5 edge-flux loops + 5
 stage updates with residual norms), the same iteration in the FP32-storage
@@ -68,6 +69,7 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "edge_flux_fp64_owner_E_traffic
 MESHES = {  # name: (nodes per axis, split, jitter / h, description)
     "E": (160, 1, 0.25, "layered 5/6-tet mix"),
     "B": (100, 0, 0.2, "6 tets per cube"),
+    "A": (20, 0, 0.0, "6 tets per cube"),
 }
 
 
@@ -194,7 +196,8 @@ def main():
     ap.add_argument("--block-size", type=int, default=512)
     ap.add_argument("--colour-sort", action="store_true")
     ap.add_argument("--mesh", choices=sorted(MESHES), default="E",
-                    help="E: 160^3 layered 5/6-tet box (4.1M nodes); B: 100^3 6-tet box (1M nodes)")
+                    help="E: 160^3 layered 5/6-tet box (4.1M nodes); B: 100^3 6-tet box (1M nodes); "
+                         "A: 20^3 6-tet box (8,000 nodes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device copy first (calibrates profiler byte counters)")

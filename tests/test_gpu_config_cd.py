@@ -1,6 +1,10 @@
-"""The FP32-storage trajectory (config C) and the adjoint (config D) on the
-1M-node jittered box, against the FP64 oracle, in the launch configuration
-bench.py times (owner variant, Morton renumbering, clusters of 512 nodes).
+"""The FP64 loops (config B), the FP32-storage trajectory (config C) and the
+adjoint (config D) on the 1M-node jittered box, against the FP64 oracle, in
+the launch configuration bench.py times (owner variant, Morton renumbering,
+clusters of 512 nodes).
+
+B: the residual of every variant and one fused 5-stage iteration, bound at
+1e-12 normwise.
 
 C: 100 iterations of 5 stages with the stage update fused into the FP32
 edge loop, each stage compared with the oracle's FP64 stage (the oracle fed
@@ -112,6 +116,30 @@ def test_fp32_trajectory_vs_oracle_config_c(traj_c, part):
     assert traj_c["it"] == 20 * part, "the parts run in order on one trajectory"
     _advance(traj_c, 20, identical_first=2 if part == 0 else 0)
     assert torch.isfinite(traj_c["p"].qa).all()
+
+
+def test_fp64_residual_and_iteration_config_b():
+    """Config B (the same 1M-node box, FP64): the residual of every variant and
+    one 5-stage iteration with the stage update fused into the owner loop,
+    against the oracle."""
+    print("[config B: 1M-node jittered box, FP64]", flush=True)
+    m = meshgen.config_mesh("B")
+    q = meshgen.state(m.N, m.perm)
+    ctx = pk.Context(DEV)
+    p = pk.FluxProblem(ctx, m.e2n, m.w, m.vol, q, coords=m.xyz, **BENCH)
+    ref = oracle.residual(m.e2n, q, m.w)
+    for variant in (pk.OWNER, pk.COLOURED, pk.COLOURED_LDS_ATOMIC, pk.ATOMIC, pk.FLAT):
+        res = torch.zeros((6, m.N), dtype=torch.float64, device=DEV)
+        p.residual(p.qa, res, variant)
+        ctx.sync()
+        assert report(f"B residual v{variant}", normwise(p.nodes_out(res), ref), 1e-12)
+    dt = oracle.dt(m.e2n, q, m.w, m.vol)
+    q1, ss = oracle.rk_iteration(m.e2n, q, m.w, m.vol, dt)
+    p.rk_iteration(dt, pk.OWNER)
+    ctx.sync()
+    assert report("B fused iteration state", normwise(p.nodes_out(p.qa), q1), 1e-12)
+    assert report("B fused iteration rms", normwise(p.rms(), np.sqrt(ss / m.N)), 1e-12)
+    ctx.close()
 
 
 @pytest.fixture(scope="module")
