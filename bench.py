@@ -432,11 +432,13 @@ def main():
         gbs = (be * E + bn * N + bt * T) / (ms * 1e-3) / 1e9
         per[k] = {"ms": round(ms, 4), "ms_median": round(float(np.median(times)), 4),
                   "ms_min": round(float(np.min(times)), 4), "launches": len(times),
-                  "algorithmic_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+                  "algorithmic_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                  "frac_of_device_copy": round(gbs / copy_gbs, 4)}
         if be:
             per[k]["edges_per_s"] = round(E / (ms * 1e-3), 1)
         log(f"{k:8s} {ms * 1e3:9.1f} us  {gbs:8.1f} GB/s algorithmic  "
-            f"({100 * gbs / HBM_PEAK_GBS:.1f} % of 8 TB/s)")
+            f"({100 * gbs / HBM_PEAK_GBS:.1f} % of 8 TB/s, "
+            f"{100 * gbs / copy_gbs:.1f} % of the device copy)")
     main64, main32 = ("fp64_fused", "fp32_fused") if fused else ("fp64", "fp32")
     speedup32 = per[main64]["ms"] / per[main32]["ms"]
     value = 11 * E / (ms_step * 1e-3)
@@ -492,6 +494,7 @@ def main():
             "bytes_per_launch": be * E + bn * N,
             "traffic": measured_traffic(config_key),
             "device_copy_GBs": round(copy_gbs, 1),
+            "frac_of_device_copy": dom["frac_of_device_copy"],
         },
     }
     if not args.no_cpu_baseline:
