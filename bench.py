@@ -396,11 +396,14 @@ def main():
     for rec in (False, True):
         for _ in range(3 if rec else 1):
             for variant, tag in ((pk.OWNER, ""), (pk.ATOMIC, "_atomic")):
-                wg.zero_()
-                volg.zero_()
+                # the gather form writes its results; the scatter form adds into zeros
+                if variant == pk.ATOMIC:
+                    wg.zero_()
+                    volg.zero_()
                 xbar.zero_()
                 a = ev()
-                p64.geometry(x, wg, volg, variant=variant)
+                p64.geometry(x, wg, volg, variant=variant,
+                             access=pk.WRITE if variant == pk.OWNER else pk.INC)
                 b = ev()
                 p64.geometry_adjoint(x, nbar, volg, xbar, variant=variant)
                 c = ev()

@@ -373,14 +373,22 @@ typedef struct {
  *   dx_e = x_j - x_i; WRITE increments with the OWNER variant as above.
  *  In every edge loop the increment target must not be one of the inputs.
  *  GEOMETRY over tets (variant ATOMIC: one thread per tet scattering with
- *  FP64 atomics, summation order varies; variant OWNER: each tet's results
- *  go to a library-owned device scratch buffer of 152 bytes per tet, then
- *  each edge and node sums over its incident tets in a fixed order: no
- *  atomics, deterministic.  The first OWNER call on a pair of tet maps
- *  builds the incidence lists and the buffer, kept until the maps are
- *  declared again or opf_finalize; any other variant is OPF_EINVAL):
+ *  FP64 atomics, summation order varies; variant OWNER: no atomics, fixed
+ *  summation orders, the same bits on every run.  OWNER walks the tets around
+ *  each edge, as a chain of vertices, from node coordinates staged per chunk
+ *  of nodes (the plan's owner clusters, else 512 nodes) in LDS, writes the
+ *  weights and a per-edge volume sum, then sums those per node.  Where a mesh
+ *  does not fit that form (a chunk's edges not contiguous in the plan's edge
+ *  order, more than 4096 chunk and halo nodes, the tets around an edge not
+ *  one fan), each tet's results go to a per-tet buffer that every edge and
+ *  node then sums over its incident tets.  The first OWNER call on a pair of
+ *  tet maps builds these lists and buffers on the device (about 40 bytes
+ *  per edge and 176 per tet; 232 per tet when the forward uses the per-tet
+ *  buffer), kept until the maps are declared again or opf_finalize; any
+ *  other variant is OPF_EINVAL):
  *     (x, ALL, t2n, 3, F64, READ) (w, ALL, t2e, 3, F64, INC)
  *     (vol, ALL, t2n, 1, F64, INC) gbl (period, 1, F64, READ, host)
+ *   With OWNER, w and vol may each be WRITE instead of INC (overwritten).
  *   t2n (tets -> nodes, arity 4) lists positively oriented tets; t2e (tets ->
  *   edges, arity 6) lists their edges in the local order (0,1) (0,2) (0,3)
  *   (1,2) (1,3) (2,3).  The edge set must have been planned (its edge->node

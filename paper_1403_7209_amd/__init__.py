@@ -419,12 +419,22 @@ class Context:
                                                          _stream_ptr(stream, self.device)),
                     "opf_edge_flux_stage_noalloc")
 
-    def geometry(self, tets, t2n, t2e, x, w, vol, period=1.0, variant=OWNER, stream=None):
+    def geometry(self, tets, t2n, t2e, x, w, vol, period=1.0, variant=OWNER, stream=None,
+                 access=INC):
         """w (edge dat, 3) and vol (node dat) += median-dual weights and volumes of the
-        tets (OWNER: gather over incident tets, deterministic; ATOMIC: scatter)."""
-        self._check(self.lib.opf_geometry(self._ctx, tets, t2n, t2e, x, float(period), w, vol,
-                                          variant, _stream_ptr(stream, self.device)),
-                    "opf_geometry")
+        tets (OWNER: gather over incident tets, deterministic; ATOMIC: scatter).
+        access=WRITE (OWNER only) overwrites them instead."""
+        if access == INC:
+            self._check(self.lib.opf_geometry(self._ctx, tets, t2n, t2e, x, float(period), w, vol,
+                                              variant, _stream_ptr(stream, self.device)),
+                        "opf_geometry")
+            return
+        per = ctypes.c_double(period)
+        self.par_loop(K_GEOMETRY, tets,
+                      [(x, ALL, t2n, 3, F64, READ), (w, ALL, t2e, 3, F64, access),
+                       (vol, ALL, t2n, 1, F64, access)],
+                      [(ctypes.addressof(per), 1, F64, READ, 0)],
+                      variant, stream)
 
     def geometry_adjoint(self, tets, t2n, t2e, x, wbar, volbar, xbar, period=1.0, variant=OWNER,
                          stream=None):
@@ -594,12 +604,13 @@ class FluxProblem:
                               self.ss[k], rk, stream)
         self.qa, self.qb = self.qb, self.qa
 
-    def geometry(self, x_t, w_t, vol_t, period=1.0, variant=OWNER, stream=None):
+    def geometry(self, x_t, w_t, vol_t, period=1.0, variant=OWNER, stream=None, access=INC):
         """w_t (3, E) and vol_t (N,) += weights and volumes of the tets at node
-        coordinates x_t (3, N); all internal numbering, FP64."""
+        coordinates x_t (3, N); all internal numbering, FP64.  access=WRITE
+        (OWNER only) overwrites them."""
         self.ctx.geometry(self.tets, self.t2n, self.t2e, self.dat(x_t, "x"),
                           self.dat(w_t, "w", edges=True), self.dat(vol_t[None], "vol_out"),
-                          period, variant, stream)
+                          period, variant, stream, access)
 
     def geometry_adjoint(self, x_t, wbar_t, volbar_t, xbar_t, period=1.0, variant=OWNER,
                          stream=None):

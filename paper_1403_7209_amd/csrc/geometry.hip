@@ -12,10 +12,12 @@
 //
 // Two forms.  Scatter: one thread per tet adds its six face vectors and four
 // volume quarters (or, in reverse, its four x-bar shares) to HBM with FP64
-// atomics.  Gather: one thread per tet writes those results to a scratch
-// buffer, then one thread per edge or node sums its incident tets' entries in
-// a fixed order: no atomics, the same bits on every run.  The loop runs once
-// per mesh (or once per design step for the reverse).
+// atomics.  Gather: no atomics, fixed summation orders, the same bits on every
+// run.  The forward gather walks the tets around each edge from coordinates
+// staged in LDS (ring form, below); the reverse (and the forward, where a
+// mesh does not fit the ring form) writes per-tet results to a scratch buffer
+// that one thread per edge or node then sums over its incident tets.  The
+// loop runs once per mesh (or once per design step for the reverse).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(256) void k_edge_sum_faces(TetArrays a)
                 if (j + u < end) acc[d] += r[u][d];
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) a.w[d][e] += acc[d];
+    for (int d = 0; d < 3; ++d) a.w[d][e] = (a.write_w ? 0.0 : a.w[d][e]) + acc[d];
 }
 
 // vol[i] += sum over the tets around i of a quarter of their volume
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(256) void k_node_sum_vol(int T, TetArrays a)
         for (int u = 0; u < kSumAhead; ++u)
             if (j + u < end) acc += r[u];
     }
-    a.vol[i] += acc;
+    a.vol[i] = (a.write_vol ? 0.0 : a.vol[i]) + acc;
 }
 
 // record of tet t (12 doubles at t * 12): its share of x-bar at local vertex v
@@ -343,6 +345,164 @@ __global__ __launch_bounds__(256) void k_node_sum_xbar(TetArrays a)
     for (int d = 0; d < 3; ++d) a.xbar[d][i] += acc[d];
 }
 
+// ------------------------------------------------------------ ring form -- */
+//
+// The forward gather without per-tet records.  One workgroup per chunk of KG
+// consecutive nodes stages the coordinates of its nodes and of its halo (the
+// other vertices of the tets around its edges) in LDS; then one thread per
+// edge of the chunk walks the tets around its edge in list order.  Around edge
+// (a, b), tet (a, b, r, s) gives the face (x_r + x_s - x_a - x_b) x (x_s - x_r)
+// / 24 (the formula above with p = a, q = b) and the determinant
+// (x_b - x_a) . ((x_r - x_a) x (x_s - x_a)), six times the tet's volume; every
+// difference is taken from x_a (wrapped to its nearest image in a periodic
+// box).  The edge's weight gets the sum of its faces, and the sum of its
+// determinants goes to edge_det; a node's volume is then the sum over its
+// edges of edge_det / 72: a tet lies around three of its edges at each vertex,
+// and each vertex owns a quarter of its volume.  Fixed orders throughout: the
+// same bits on every run.
+
+// LDS rows: plane of (x, y) pairs, then plane of z (L rows each).
+__device__ __forceinline__ void geo_get(const double *X, int L, uint32_t l, double *x)
+{
+    const double2 xy = reinterpret_cast<const double2 *>(X)[l];
+    x[0] = xy.x;
+    x[1] = xy.y;
+    x[2] = X[2 * L + l];
+}
+
+__device__ __forceinline__ void geo_diff(const double *x, const double *a, bool wrap, double period,
+                                         double ip, double *d)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        d[k] = x[k] - a[k];
+        if (wrap) d[k] -= period * rint(d[k] * ip);
+    }
+}
+
+// The edges of a chunk go in batches of kGeoThreads, one per thread; each
+// batch's ring entries (one contiguous run) are first copied to LDS by the
+// whole workgroup, so that the walks read LDS only.  Around edge (a, b) with
+// chain c_0 .. c_k and d_i = x_(c_i) - x_a, tet i contributes
+// (d_(i-1) + d_i - d_b) x (d_i - d_(i-1)) / 24 = (2 d_(i-1) x d_i
+// - d_b x (d_i - d_(i-1))) / 24 to the face and d_b . (d_(i-1) x d_i) to the
+// determinant sum; summed over the chain, the d_b terms telescope to
+// d_b x (d_k - d_0), zero on a closed ring.  One vertex and one cross product
+// per tet.
+__global__ __launch_bounds__(kGeoThreads) void k_geo_rings(TetArrays a, double period)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *X = reinterpret_cast<double *>(smem);
+    uint32_t *R32 = reinterpret_cast<uint32_t *>(smem + (size_t)a.L * 24);
+    const uint16_t *R16 = reinterpret_cast<const uint16_t *>(R32);
+    const uint32_t *ring32 = reinterpret_cast<const uint32_t *>(a.ring);
+    const int L = a.L, KG = a.KG, c = (int)blockIdx.x, t = (int)threadIdx.x;
+    const int v0 = c * KG, nown = min(KG, a.N - v0);
+    const int h0 = a.halo_off[c], nh = a.halo_off[c + 1] - h0;
+    const int2 ce = a.chunk_e[c];
+    // the words of a batch: whole 4-byte words covering its entries, kGeoPre
+    // per thread at most; the next batch's are loaded while this one computes
+    uint32_t pre[kGeoPre];
+    auto fetch = [&](int b0, int &q0, int &nq) {
+        const int eb = ce.x + b0, nb = min(kGeoThreads, ce.y - b0);
+        const int wb = a.ring_off[eb], we = a.ring_off[eb + nb];
+        q0 = wb >> 1;
+        nq = ((we + 1) >> 1) - q0;
+#pragma unroll
+        for (int u = 0; u < kGeoPre; ++u) {
+            const int j = t + u * kGeoThreads;
+            if (j < nq) pre[u] = ring32[q0 + j];
+        }
+    };
+    int q0 = 0, nq = 0;
+    if (ce.y > 0) fetch(0, q0, nq);
+    for (int l = t; l < nown + nh; l += kGeoThreads) {
+        const bool own = l < nown;
+        const int g = own ? v0 + l : a.halo[h0 + l - nown];
+        const int row = own ? l : KG + l - nown;
+        reinterpret_cast<double2 *>(X)[row] = make_double2(a.x[0][g], a.x[1][g]);
+        X[2 * L + row] = a.x[2][g];
+    }
+    const bool wrap = period > 0.0;
+    const double ip = wrap ? 1.0 / period : 0.0;
+    for (int b0 = 0; b0 < ce.y; b0 += kGeoThreads) {
+        const int nb = min(kGeoThreads, ce.y - b0), eb = ce.x + b0;
+        const int sh = 2 * q0;  // entry o of this batch sits at R16[o - sh]
+        const bool act = t < nb;
+        const int e = eb + t;
+        int o0 = 0, o1 = 0;
+        double w0[3] = {0.0, 0.0, 0.0};
+        if (act) {
+            o0 = a.ring_off[e] - sh;
+            o1 = a.ring_off[e + 1] - sh;
+            if (!a.write_w)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) w0[d] = a.w[d][e];
+        }
+        __syncthreads();  // coordinates staged; the last batch's entries read
+#pragma unroll
+        for (int u = 0; u < kGeoPre; ++u) {
+            const int j = t + u * kGeoThreads;
+            if (j < nq) R32[j] = pre[u];
+        }
+        __syncthreads();
+        if (b0 + kGeoThreads < ce.y) fetch(b0 + kGeoThreads, q0, nq);
+        if (!act) continue;
+        double xa[3], xb[3], db[3], d0[3], dp[3];
+        geo_get(X, L, R16[o0], xa);
+        geo_get(X, L, R16[o0 + 1], xb);
+        geo_diff(xb, xa, wrap, period, ip, db);
+        geo_get(X, L, R16[o0 + 2], d0);
+        geo_diff(d0, xa, wrap, period, ip, d0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dp[d] = d0[d];
+        double C[3] = {0.0, 0.0, 0.0};
+        for (int j = o0 + 3; j < o1; ++j) {
+            double xn[3], dn[3], cr[3];
+            geo_get(X, L, R16[j], xn);
+            geo_diff(xn, xa, wrap, period, ip, dn);
+            cross3(dp, dn, cr);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                C[d] += cr[d];
+                dp[d] = dn[d];
+            }
+        }
+        double ds[3], corr[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ds[d] = dp[d] - d0[d];
+        cross3(db, ds, corr);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.w[d][e] = w0[d] + (2.0 * C[d] - corr[d]) * (1.0 / 24.0);
+        a.edge_det[e] = db[0] * C[0] + db[1] * C[1] + db[2] * C[2];
+    }
+}
+
+// Volumes, one workgroup per chunk: the determinant sums of the edges at its
+// nodes go to LDS (its own edge range, coalesced, then the edges it shares
+// with lower chunks, vsec), and each node adds those of its edges in the
+// order of its slot list vloc: vol (+)= sum / 72.
+__global__ __launch_bounds__(kGeoVolThreads) void k_geo_vol(TetArrays a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *D = reinterpret_cast<double *>(smem);
+    const int c = (int)blockIdx.x, t = (int)threadIdx.x;
+    const int v0 = c * a.KG, nown = min(a.KG, a.N - v0);
+    const int2 ce = a.chunk_e[c];
+    const int s0 = a.vsec_off[c], ns = a.vsec_off[c + 1] - s0;
+    for (int j = t; j < ce.y; j += kGeoVolThreads) D[j] = a.edge_det[ce.x + j];
+    for (int j = t; j < ns; j += kGeoVolThreads) D[ce.y + j] = a.edge_det[a.vsec[s0 + j]];
+    __syncthreads();
+    for (int l = t; l < nown; l += kGeoVolThreads) {
+        const int i = v0 + l;
+        const double vi = a.write_vol ? 0.0 : a.vol[i];
+        double acc = 0.0;
+        const int end = a.vloc_off[i + 1];
+        for (int j = a.vloc_off[i]; j < end; ++j) acc += D[a.vloc[j]];
+        a.vol[i] = vi + acc * (1.0 / 72.0);
+    }
+}
+
 }  // namespace
 
 int launch_geometry(bool adjoint, bool gather, int T, const TetArrays &a, double period,
@@ -354,6 +514,17 @@ int launch_geometry(bool adjoint, bool gather, int T, const TetArrays &a, double
         if (adjoint) {
             hipLaunchKernelGGL(k_tet_reverse, gt, dim3(256), 0, st, T, a, period);
             hipLaunchKernelGGL(k_node_sum_xbar, gn, dim3(256), 0, st, a);
+        } else if (a.ring) {
+            const size_t lds = geo_ring_lds(a.L, a.RB);
+            if (lds > 65536) {
+                const hipError_t e = hipFuncSetAttribute(
+                    reinterpret_cast<const void *>(k_geo_rings),
+                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (e != hipSuccess) return (int)e;
+            }
+            hipLaunchKernelGGL(k_geo_rings, dim3(a.nchunk), dim3(kGeoThreads), lds, st, a, period);
+            hipLaunchKernelGGL(k_geo_vol, dim3(a.nchunk), dim3(kGeoVolThreads),
+                               (size_t)a.DV * sizeof(double), st, a);
         } else {
             hipLaunchKernelGGL(k_tet_forward, gt, dim3(256), 0, st, T, a, period);
             hipLaunchKernelGGL(k_edge_sum_faces, ge, dim3(256), 0, st, a);

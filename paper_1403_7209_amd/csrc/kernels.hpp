@@ -121,6 +121,32 @@ struct TetArrays {
     const int *e2t_off = nullptr, *e2t = nullptr;
     const int *n2t_off = nullptr, *n2t = nullptr;
     double *scratch = nullptr;  // gather form: kTetScratch x T doubles
+    // ring form of the forward gather (ring != nullptr): node chunks of KG
+    // consecutive internal nodes; chunk c owns the edges chunk_e[c] = (first,
+    // count) whose smaller end it holds.  Edge e's entries are
+    // ring[ring_off[e] .. ring_off[e+1]): a and b (a -> b the edge's
+    // orientation), then the chain c_0 .. c_k of the k tets around it, tet i
+    // being (a, b, c_(i-1), c_i), an even permutation of its vertices (a
+    // closed ring ends with c_k = c_0); all in the chunk's local numbering: its
+    // own nodes at 0 .. KG-1, then its halo nodes halo[halo_off[c] ..] at KG,
+    // KG + 1, ...  L = KG + the largest halo.  The array has two spare entries
+    // at its end.
+    const int *ring_off = nullptr;
+    const uint16_t *ring = nullptr;
+    const int2 *chunk_e = nullptr;
+    const int *halo_off = nullptr, *halo = nullptr;
+    // volumes: per chunk the edges with their larger end in it and smaller end
+    // in a lower chunk (vsec[vsec_off[c] ..], ascending); per node i its edges'
+    // slots vloc[vloc_off[i] .. vloc_off[i+1]) in ascending edge order, slot j
+    // < count being the chunk's edge first + j, slot count + m its m-th vsec
+    // edge.  DV: the most slots of a chunk.
+    const int *vsec_off = nullptr, *vsec = nullptr, *vloc_off = nullptr;
+    const uint16_t *vloc = nullptr;
+    double *edge_det = nullptr;  // per edge: sum of 6 vol over its tets
+    int nchunk = 0, KG = 0, L = 0;
+    int RB = 0;  // ring entries of the largest batch of kGeoThreads edges of a chunk
+    int DV = 0;
+    int write_w = 0, write_vol = 0;  // gather forward: WRITE instead of INC
     int N = 0, E = 0;
     const double *x[3] = {};
     double *w[3] = {};      // GEOMETRY: weights (INC); ADJ: wbar (read)
@@ -137,6 +163,21 @@ constexpr int kTetScratch = 19;
 // sums them over the incident tets in a fixed order (deterministic, no atomics).
 int launch_geometry(bool adjoint, bool gather, int T, const TetArrays &a, double period,
                     hipStream_t stream);
+// The largest L (chunk nodes + halo) the ring kernel takes (24 B of LDS per
+// node).
+constexpr int kGeoMaxRows = 4096;
+// The ring kernel's workgroup: one edge per thread per batch.
+constexpr int kGeoThreads = 512;
+// Ring words (4 bytes) each thread of the ring kernel prefetches for the next
+// batch, and so the most ring entries of one batch.
+constexpr int kGeoPre = 8;
+constexpr int kGeoMaxBatch = 2 * (kGeoPre * kGeoThreads - 2);
+// The volume kernel's workgroup and its most slots per chunk (LDS: 8 B each).
+constexpr int kGeoVolThreads = 512;
+constexpr int kGeoMaxSlots = 8192;
+// LDS bytes of one ring-kernel workgroup: coordinates, then the batch's
+// entries (whole 4-byte words, one spare at each end).
+inline size_t geo_ring_lds(int L, int RB) { return (size_t)L * 24 + ((size_t)RB / 2 + 2) * 4; }
 
 // dt[i] = cfl * vol[i] / lam[i].
 int launch_local_dt(int N, const double *vol, const double *lam, double cfl, double *dt,

@@ -16,6 +16,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -73,6 +74,13 @@ struct DevTetInverse {
     int32_t *t2n = nullptr, *t2e = nullptr;  // tets in the gather order
     int32_t *e2t_off = nullptr, *e2t = nullptr, *n2t_off = nullptr, *n2t = nullptr;
     double *scratch = nullptr;  // kTetScratch values per tet
+    // ring form of the forward (see opf::gpu::TetArrays); ring == nullptr when
+    // the mesh does not fit it
+    int32_t *ring_off = nullptr, *chunk_e = nullptr, *halo_off = nullptr, *halo = nullptr;
+    int32_t *vsec_off = nullptr, *vsec = nullptr, *vloc_off = nullptr;
+    uint16_t *ring = nullptr, *vloc = nullptr;
+    double *edge_det = nullptr;
+    int nchunk = 0, KG = 0, L = 0, RB = 0, DV = 0;
 };
 
 struct opf_ctx {
@@ -638,13 +646,207 @@ int device_map(opf_ctx *ctx, opf_map m, const int32_t *&out)
     return OPF_OK;
 }
 
+void free_tinv(opf_ctx *ctx, DevTetInverse &d)
+{
+    for (int32_t *p : {d.t2n, d.t2e, d.e2t_off, d.e2t, d.n2t_off, d.n2t, d.ring_off, d.chunk_e,
+                       d.halo_off, d.halo, d.vsec_off, d.vsec, d.vloc_off})
+        ctx->dfree(p);
+    ctx->dfree(d.ring);
+    ctx->dfree(d.vloc);
+    ctx->dfree(d.scratch);
+    ctx->dfree(d.edge_det);
+    d = DevTetInverse();
+}
+
+// Host arrays of the ring form (layout in opf::gpu::TetArrays).
+struct Rings {
+    int KG = 0, nchunk = 0, L = 0, RB = 0, DV = 0;
+    std::vector<int32_t> ring_off, chunk_e, halo_off, halo, vsec_off, vsec, vloc_off;
+    std::vector<uint16_t> ring, vloc;
+};
+
+// Builds the ring form from the plan's internal edge->node map (e2n), the tets
+// in internal numbering (tn, 4 per tet) and the CSR list of the tets around
+// every edge (eo, el: tet * 8 + local edge, ascending tet order).  Chunks are
+// the plan's owner clusters (512 nodes without them).  Returns false, and the
+// record form serves, when a chunk's edges are not one contiguous range of
+// the edge order, a chunk's nodes and halo exceed kGeoMaxRows, a batch of
+// kGeoThreads edges has more than kGeoMaxBatch entries, the edges at a chunk's
+// nodes exceed kGeoMaxSlots, or the tets around an edge are not one fan (each
+// next tet sharing a face with the last).
+bool build_rings(const std::vector<int32_t> &e2n, int64_t N, int64_t E, int KG,
+                 const std::vector<int32_t> &tn, const std::vector<int32_t> &eo,
+                 const std::vector<int32_t> &el, Rings &R)
+{
+    // local edge k: vertices (p, q) and the completing pair (r, s) such that
+    // (p, q, r, s) is an even permutation of (0, 1, 2, 3)
+    static const int kLocal[6][4] = {{0, 1, 2, 3}, {0, 2, 3, 1}, {0, 3, 1, 2},
+                                     {1, 2, 0, 3}, {1, 3, 2, 0}, {2, 3, 0, 1}};
+    if (KG <= 0 || N <= 0 || (int64_t)eo.size() != E + 1) return false;
+    if (E + (int64_t)el.size() >= ((int64_t)1 << 31)) return false;
+    const int64_t nch = (N + KG - 1) / KG;
+    R.KG = KG;
+    R.nchunk = (int)nch;
+    R.chunk_e.assign(2 * nch, 0);
+    std::vector<int64_t> last(nch, -1);
+    for (int64_t e = 0; e < E; ++e) {
+        const int64_t c = std::min(e2n[2 * e], e2n[2 * e + 1]) / KG;
+        if (last[c] < 0) R.chunk_e[2 * c] = (int32_t)e;
+        else if (last[c] != e - 1) return false;  // not one contiguous range
+        last[c] = e;
+        ++R.chunk_e[2 * c + 1];
+    }
+    // halo of every chunk: the other vertices of its edges' tets, ascending
+    std::vector<std::vector<int32_t>> halo(nch);
+    std::vector<int32_t> mark(N, -1), loc(N, -1);
+    for (int64_t c = 0; c < nch; ++c) {
+        const int64_t v0 = c * KG, v1 = std::min<int64_t>(N, v0 + KG);
+        std::vector<int32_t> &h = halo[c];
+        auto see = [&](int32_t v) {
+            if ((v < v0 || v >= v1) && mark[v] != (int32_t)c) {
+                mark[v] = (int32_t)c;
+                h.push_back(v);
+            }
+        };
+        for (int64_t e = R.chunk_e[2 * c]; e < R.chunk_e[2 * c] + R.chunk_e[2 * c + 1]; ++e) {
+            see(e2n[2 * e]);
+            see(e2n[2 * e + 1]);
+            for (int32_t j = eo[e]; j < eo[e + 1]; ++j) {
+                const int32_t t = el[j] >> 3;
+                for (int v = 0; v < 4; ++v) see(tn[4 * (int64_t)t + v]);
+            }
+        }
+        std::sort(h.begin(), h.end());
+        if (KG + (int64_t)h.size() > opf::gpu::kGeoMaxRows) return false;
+        R.L = std::max<int>(R.L, KG + (int)h.size());
+    }
+    R.halo_off.assign(nch + 1, 0);
+    for (int64_t c = 0; c < nch; ++c) R.halo_off[c + 1] = R.halo_off[c] + (int32_t)halo[c].size();
+    R.halo.resize(R.halo_off[nch]);
+    for (int64_t c = 0; c < nch; ++c)
+        std::copy(halo[c].begin(), halo[c].end(), R.halo.begin() + R.halo_off[c]);
+    // per edge: a and b, then the chain of the tets around it: vertices
+    // c_0 .. c_k such that tet i is (a, b, c_(i-1), c_i), an even permutation of
+    // its vertices; a closed ring repeats c_0 at the end (k tets, k + 1 entries)
+    R.ring_off.assign(E + 1, 0);
+    for (int64_t e = 0; e < E; ++e) R.ring_off[e + 1] = R.ring_off[e] + 3 + (eo[e + 1] - eo[e]);
+    R.ring.assign((size_t)R.ring_off[E] + 2, 0);  // +2: the kernel copies whole 4-byte words
+    // the ring kernel stages the entries of kGeoThreads edges at a time in LDS
+    for (int64_t c = 0; c < nch; ++c) {
+        const int64_t e0 = R.chunk_e[2 * c], e1 = e0 + R.chunk_e[2 * c + 1];
+        for (int64_t b = e0; b < e1; b += opf::gpu::kGeoThreads) {
+            const int64_t n = R.ring_off[std::min<int64_t>(e1, b + opf::gpu::kGeoThreads)] - R.ring_off[b];
+            if (n > opf::gpu::kGeoMaxBatch) return false;
+            R.RB = std::max<int>(R.RB, (int)n);
+        }
+    }
+    std::vector<int32_t> pr, ps;
+    std::vector<uint8_t> used;
+    for (int64_t c = 0; c < nch; ++c) {
+        const int64_t v0 = c * KG;
+        const std::vector<int32_t> &h = halo[c];
+        for (size_t i = 0; i < h.size(); ++i) loc[h[i]] = KG + (int32_t)i;
+        auto local = [&](int32_t v) -> uint16_t {
+            return (uint16_t)(v >= v0 && v < v0 + KG ? v - v0 : loc[v]);
+        };
+        for (int64_t e = R.chunk_e[2 * c]; e < R.chunk_e[2 * c] + R.chunk_e[2 * c + 1]; ++e) {
+            const int32_t a = e2n[2 * e], b = e2n[2 * e + 1];
+            const int k = eo[e + 1] - eo[e];
+            pr.assign(k, 0);
+            ps.assign(k, 0);
+            for (int i = 0; i < k; ++i) {
+                const int64_t t = el[eo[e] + i] >> 3;
+                const int l = el[eo[e] + i] & 7;
+                const int32_t *g = &tn[4 * t];
+                // (a, b, r, s) even: as listed when a is the local edge's first
+                // vertex, else (q, p, s, r)
+                const int32_t gp = g[kLocal[l][0]], gq = g[kLocal[l][1]];
+                const bool fwd = gp == a;
+                if (!(fwd ? gq == b : gq == a && gp == b)) return false;  // t2e disagrees with e2n
+                pr[i] = g[kLocal[l][fwd ? 2 : 3]];
+                ps[i] = g[kLocal[l][fwd ? 3 : 2]];
+            }
+            int64_t o = R.ring_off[e];
+            R.ring[o++] = local(a);
+            R.ring[o++] = local(b);
+            if (k == 0) {
+                R.ring[o++] = local(a);  // no tets: an empty chain (c_0 only)
+                continue;
+            }
+            // start: the tet whose r is no tet's s (an open fan), else the first
+            int start = 0;
+            for (int i = 0; i < k; ++i)
+                if (std::find(ps.begin(), ps.end(), pr[i]) == ps.end()) {
+                    start = i;
+                    break;
+                }
+            used.assign(k, 0);
+            used[start] = 1;
+            R.ring[o++] = local(pr[start]);
+            R.ring[o++] = local(ps[start]);
+            int32_t last = ps[start];
+            for (int n = 1; n < k; ++n) {
+                int next = -1;
+                for (int i = 0; i < k && next < 0; ++i)
+                    if (!used[i] && pr[i] == last) next = i;
+                if (next < 0) return false;  // not one fan of tets around the edge
+                used[next] = 1;
+                last = ps[next];
+                R.ring[o++] = local(last);
+            }
+        }
+    }
+    // incident edges of every node, ascending edge order
+    std::vector<int32_t> n2e_off(N + 1, 0), n2e(2 * E);
+    for (int64_t e = 0; e < E; ++e) {
+        ++n2e_off[e2n[2 * e] + 1];
+        ++n2e_off[e2n[2 * e + 1] + 1];
+    }
+    for (int64_t i = 0; i < N; ++i) n2e_off[i + 1] += n2e_off[i];
+    {
+        std::vector<int32_t> fill(n2e_off.begin(), n2e_off.end() - 1);
+        for (int64_t e = 0; e < E; ++e) {
+            n2e[fill[e2n[2 * e]]++] = (int32_t)e;
+            n2e[fill[e2n[2 * e + 1]]++] = (int32_t)e;
+        }
+    }
+    // the volume kernel's slots: per chunk its own edge range, then the edges
+    // it shares with lower chunks (vsec)
+    R.vsec_off.assign(nch + 1, 0);
+    R.vloc_off = n2e_off;
+    R.vloc.resize(2 * E);
+    std::vector<int32_t> sec;
+    for (int64_t c = 0; c < nch; ++c) {
+        const int64_t v0 = c * KG, v1 = std::min<int64_t>(N, v0 + KG);
+        const int64_t first = R.chunk_e[2 * c], count = R.chunk_e[2 * c + 1];
+        sec.clear();
+        for (int64_t i = v0; i < v1; ++i)
+            for (int32_t j = n2e_off[i]; j < n2e_off[i + 1]; ++j)
+                if (n2e[j] < first || n2e[j] >= first + count) sec.push_back(n2e[j]);
+        std::sort(sec.begin(), sec.end());
+        sec.erase(std::unique(sec.begin(), sec.end()), sec.end());
+        if (count + (int64_t)sec.size() > opf::gpu::kGeoMaxSlots) return false;
+        R.DV = std::max<int>(R.DV, (int)(count + sec.size()));
+        for (int64_t i = v0; i < v1; ++i)
+            for (int32_t j = n2e_off[i]; j < n2e_off[i + 1]; ++j) {
+                const int64_t e = n2e[j];
+                R.vloc[j] = (uint16_t)(e >= first && e < first + count
+                                           ? e - first
+                                           : count + (std::lower_bound(sec.begin(), sec.end(), (int32_t)e) - sec.begin()));
+            }
+        R.vsec_off[c + 1] = R.vsec_off[c] + (int32_t)sec.size();
+        R.vsec.insert(R.vsec.end(), sec.begin(), sec.end());
+    }
+    return true;
+}
+
 // The gather form's copies of the tet maps: tets reordered by their lowest
 // internal vertex (so that the tets around a node or an edge sit close
 // together), both maps in internal numbering, and the CSR lists of the
 // (tet, local index) pairs of every edge and node in that tet order,
 // packed as tet * 8 + local edge and tet * 4 + local vertex; plus the scratch
 // buffer of the per-tet results (kTetScratch doubles per tet).
-int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, DevTetInverse *&out)
+int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, const opf::Plan &P, DevTetInverse *&out)
 {
     DevTetInverse &d = ctx->tinv[std::make_pair((int)t2n, (int)t2e)];
     const MapRec &mn = ctx->maps[t2n], &me = ctx->maps[t2e];
@@ -698,13 +900,15 @@ int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, DevTetInverse *&out)
     std::vector<int32_t> eo, el, no, nl;
     invert(te, 6, 8, E, eo, el);
     invert(tn, 4, 4, N, no, nl);
-    for (int32_t *p : {d.t2n, d.t2e, d.e2t_off, d.e2t, d.n2t_off, d.n2t}) ctx->dfree(p);
-    ctx->dfree(d.scratch);
-    d = DevTetInverse();
-    auto up = [&](const std::vector<int32_t> &v, int32_t *&dst) {
-        dst = static_cast<int32_t *>(ctx->dalloc(v.size() * sizeof(int32_t)));
+    Rings R;
+    const bool rings = (int64_t)P.e2n.size() == 2 * E &&
+                       build_rings(P.e2n, N, E, P.owner_ok ? P.cluster_size : 512, tn, eo, el, R);
+    free_tinv(ctx, d);
+    auto up = [&](const auto &v, auto *&dst) {
+        using V = std::remove_const_t<std::remove_reference_t<decltype(v[0])>>;
+        dst = static_cast<V *>(ctx->dalloc(v.size() * sizeof(V)));
         if (!dst) return ctx->fail(OPF_ENOMEM, "device allocation of tet incidence failed");
-        hipError_t e = hipMemcpy(dst, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        hipError_t e = hipMemcpy(dst, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice);
         return e == hipSuccess ? OPF_OK : hip_fail(ctx, e, "tet incidence upload");
     };
     int rc = up(tn, d.t2n);
@@ -713,10 +917,38 @@ int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, DevTetInverse *&out)
     if (!rc) rc = up(el, d.e2t);
     if (!rc) rc = up(no, d.n2t_off);
     if (!rc) rc = up(nl, d.n2t);
-    if (rc) return rc;
-    d.scratch = static_cast<double *>(
-        ctx->dalloc((size_t)T * opf::gpu::kTetScratch * sizeof(double)));
-    if (!d.scratch) return ctx->fail(OPF_ENOMEM, "device allocation of the tet scratch failed");
+    if (!rc && rings) {
+        rc = up(R.ring_off, d.ring_off);
+        if (!rc) rc = up(R.ring, d.ring);
+        if (!rc) rc = up(R.chunk_e, d.chunk_e);
+        if (!rc) rc = up(R.halo_off, d.halo_off);
+        if (!rc) rc = up(R.halo.empty() ? std::vector<int32_t>(1, 0) : R.halo, d.halo);
+        if (!rc) rc = up(R.vsec_off, d.vsec_off);
+        if (!rc) rc = up(R.vsec.empty() ? std::vector<int32_t>(1, 0) : R.vsec, d.vsec);
+        if (!rc) rc = up(R.vloc_off, d.vloc_off);
+        if (!rc) rc = up(R.vloc.empty() ? std::vector<uint16_t>(1, 0) : R.vloc, d.vloc);
+        if (!rc) {
+            d.edge_det = static_cast<double *>(ctx->dalloc((size_t)std::max<int64_t>(E, 1) * sizeof(double)));
+            if (!d.edge_det) rc = ctx->fail(OPF_ENOMEM, "device allocation of the edge sums failed");
+        }
+        d.nchunk = R.nchunk;
+        d.KG = R.KG;
+        d.L = R.L;
+        d.RB = R.RB;
+        d.DV = R.DV;
+    }
+    if (rc) {
+        free_tinv(ctx, d);
+        return rc;
+    }
+    // per-tet records: the reverse's 12 values, and the forward's 19 when the
+    // ring form does not serve it
+    const size_t per_tet = rings ? 12 : opf::gpu::kTetScratch;
+    d.scratch = static_cast<double *>(ctx->dalloc((size_t)T * per_tet * sizeof(double)));
+    if (!d.scratch) {
+        free_tinv(ctx, d);
+        return ctx->fail(OPF_ENOMEM, "device allocation of the tet scratch failed");
+    }
     d.vn = mn.version;
     d.ve = me.version;
     out = &d;
@@ -743,9 +975,15 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
     const int eplan = ctx->sets[edges].plan_map;
     if (eplan < 0 || ctx->maps[eplan].from != edges || ctx->maps[eplan].to != nodes)
         return ctx->fail(OPF_ESTATE, "the edge set needs a plan of its edge->node map");
+    // the forward gather completes every weight and volume in one thread:
+    // it may WRITE them instead of incrementing
+    auto out_access = [&](int k) {
+        if (adj) return (int)OPF_READ;
+        return gather && args[k].access == OPF_WRITE ? (int)OPF_WRITE : (int)OPF_INC;
+    };
     std::vector<Want> w = {{nodes, OPF_ALL, t2n, 3, OPF_F64, OPF_READ},
-                           {edges, OPF_ALL, t2e, 3, OPF_F64, adj ? OPF_READ : OPF_INC},
-                           {nodes, OPF_ALL, t2n, 1, OPF_F64, adj ? OPF_READ : OPF_INC}};
+                           {edges, OPF_ALL, t2e, 3, OPF_F64, out_access(1)},
+                           {nodes, OPF_ALL, t2n, 1, OPF_F64, out_access(2)}};
     if (adj) w.push_back({nodes, OPF_ALL, t2n, 3, OPF_F64, OPF_INC});
     int rc = OPF_OK;
     for (int k = 0; k < nargs && !rc; ++k) rc = check_arg(ctx, args[k], w[k], k);
@@ -773,7 +1011,7 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
     opf::gpu::TetArrays ta;
     if (gather) {
         DevTetInverse *inv = nullptr;
-        rc = tet_inverse(ctx, t2n, t2e, inv);
+        rc = tet_inverse(ctx, t2n, t2e, it->second->host, inv);
         if (!rc) {
             ta.t2n = inv->t2n;
             ta.t2e = inv->t2e;
@@ -782,6 +1020,21 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
             ta.n2t_off = inv->n2t_off;
             ta.n2t = inv->n2t;
             ta.scratch = inv->scratch;
+            ta.ring_off = inv->ring_off;
+            ta.ring = inv->ring;
+            ta.chunk_e = reinterpret_cast<const int2 *>(inv->chunk_e);
+            ta.halo_off = inv->halo_off;
+            ta.halo = inv->halo;
+            ta.vsec_off = inv->vsec_off;
+            ta.vsec = inv->vsec;
+            ta.vloc_off = inv->vloc_off;
+            ta.vloc = inv->vloc;
+            ta.DV = inv->DV;
+            ta.edge_det = inv->edge_det;
+            ta.nchunk = inv->nchunk;
+            ta.KG = inv->KG;
+            ta.L = inv->L;
+            ta.RB = inv->RB;
         }
     } else {
         rc = device_map(ctx, t2n, ta.t2n);
@@ -798,6 +1051,10 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
         ta.w[d] = (double *)comp(wd, d);
     }
     ta.vol = (double *)comp(vd, 0);
+    if (!adj) {
+        ta.write_w = args[1].access == OPF_WRITE ? 1 : 0;
+        ta.write_vol = args[2].access == OPF_WRITE ? 1 : 0;
+    }
     if (adj) {
         const DatRec &xb = ctx->dats[args[3].dat];
         for (int d = 0; d < 3; ++d) ta.xbar[d] = (double *)comp(xb, d);
@@ -945,15 +1202,7 @@ int opf_finalize(opf_ctx *ctx)
         (void)hipDeviceSynchronize();
         for (auto &kv : ctx->plans) free_plan(ctx, *kv.second);
         for (auto &kv : ctx->dmaps) ctx->dfree(kv.second.ptr);
-        for (auto &kv : ctx->tinv) {
-            ctx->dfree(kv.second.scratch);
-            ctx->dfree(kv.second.t2n);
-            ctx->dfree(kv.second.t2e);
-            ctx->dfree(kv.second.e2t_off);
-            ctx->dfree(kv.second.e2t);
-            ctx->dfree(kv.second.n2t_off);
-            ctx->dfree(kv.second.n2t);
-        }
+        for (auto &kv : ctx->tinv) free_tinv(ctx, kv.second);
         ctx->dfree(ctx->scratch);
         if (ctx->scratch_ev) (void)hipEventDestroy(ctx->scratch_ev);
     }
@@ -1079,11 +1328,7 @@ int opf_plan(opf_ctx *ctx, opf_map map, const opf_plan_opts *opts, opf_plan_info
         // plan is about to change: drop them (rebuilt on their next use)
         for (auto &kv : ctx->dmaps) ctx->dfree(kv.second.ptr);
         ctx->dmaps.clear();
-        for (auto &kv : ctx->tinv) {
-            DevTetInverse &d = kv.second;
-            for (int32_t *q : {d.t2n, d.t2e, d.e2t_off, d.e2t, d.n2t_off, d.n2t}) ctx->dfree(q);
-            ctx->dfree(d.scratch);
-        }
+        for (auto &kv : ctx->tinv) free_tinv(ctx, kv.second);
         ctx->tinv.clear();
     }
     if (old != ctx->plans.end()) {

@@ -149,9 +149,11 @@ def test_geometry_full(mesh_e):
     xb_ref = oracle.geometry_adjoint(m.e2n, t2n, t2e, m.xyz, wbar, np.zeros(m.N))
     wbar_d = p.nodes_in(wbar, edges=True)
     for variant in (pk.OWNER, pk.ATOMIC):
-        w = torch.zeros((3, m.E), dtype=torch.float64, device=DEV)
-        vol = torch.zeros(m.N, dtype=torch.float64, device=DEV)
-        p.geometry(x, w, vol, variant=variant)
+        # the gather form overwrites (WRITE); the scatter form adds into zeros
+        fill = 1e30 if variant == pk.OWNER else 0.0
+        w = torch.full((3, m.E), fill, dtype=torch.float64, device=DEV)
+        vol = torch.full((m.N,), fill, dtype=torch.float64, device=DEV)
+        p.geometry(x, w, vol, variant=variant, access=pk.WRITE if variant == pk.OWNER else pk.INC)
         p.ctx.sync()
         assert report(f"E geometry w v{variant}", normwise(p.nodes_out(w, edges=True), w_ref),
                       1e-12)

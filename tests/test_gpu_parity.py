@@ -260,15 +260,18 @@ def test_geometry_and_shape_gradient(small):
                            p.nodes_in(volbar[None])[0].contiguous(), xbar, variant=variant)
         p.ctx.sync()
         assert report(f"geometry xbar v{variant}", normwise(p.nodes_out(xbar), xb_ref), TOL64)
-    # the gather form sums in a fixed order: repeated calls agree bit for bit
+    # the gather form sums in a fixed order: repeated calls agree bit for bit;
+    # with WRITE access it overwrites whatever the outputs held
     w1 = torch.zeros((3, m.E), dtype=torch.float64, device=DEV)
-    w2 = torch.zeros((3, m.E), dtype=torch.float64, device=DEV)
+    w2 = torch.full((3, m.E), 7.0e30, dtype=torch.float64, device=DEV)
     v1 = torch.zeros(m.N, dtype=torch.float64, device=DEV)
-    v2 = torch.zeros(m.N, dtype=torch.float64, device=DEV)
+    v2 = torch.full((m.N,), -3.0e30, dtype=torch.float64, device=DEV)
     p.geometry(x, w1, v1)
-    p.geometry(x, w2, v2)
+    p.geometry(x, w2, v2, access=pk.WRITE)
     p.ctx.sync()
     assert torch.equal(w1, w2) and torch.equal(v1, v2)
+    with pytest.raises(pk.OpfError):
+        p.geometry(x, w2, v2, variant=pk.ATOMIC, access=pk.WRITE)
     # shape sensitivities of rbar . R(q, w(x))
     rbar = rng.normal(size=(6, m.N))
     _, nbar = oracle.adjoint(m.e2n, q, m.w, rbar)
@@ -404,8 +407,9 @@ def test_argument_checks_on_device():
 
 def test_geometry_after_replanning():
     """A new plan renumbers the nodes and edges: the tet loops must follow it
-    (their device copies of the tet maps are rebuilt, not reused)."""
-    m = meshgen.build_mesh(8, 1, 0.25)
+    (their device copies of the tet maps are rebuilt, not reused).  1728 nodes:
+    several chunks of the forward gather's ring form."""
+    m = meshgen.build_mesh(12, 1, 0.25)
     t2n = m.tets()
     t2e = meshgen.tet_edges(m, t2n)
     w_ref, vol_ref = oracle.geometry(m.e2n, t2n, t2e, m.xyz)
@@ -416,8 +420,12 @@ def test_geometry_after_replanning():
     mp = ctx.decl_map(edges, nodes, 2, m.e2n, 0, "e2n")
     tn = ctx.decl_map(tets, nodes, 4, t2n, 0, "t2n")
     te = ctx.decl_map(tets, edges, 6, t2e, 0, "t2e")
-    for renumber in ("rcm", "morton", "none"):
-        ctx.plan(mp, renumber=renumber, coords=m.xyz, block_size=256, cluster_size=128)
+    # the last plan has no owner clusters and colour-sorted partitions: its edges
+    # are not grouped by chunks of nodes, and the forward gather uses per-tet records
+    for renumber, K, cs in (("rcm", 128, False), ("morton", 128, False), ("none", 128, False),
+                            ("morton", 0, True)):
+        ctx.plan(mp, renumber=renumber, coords=m.xyz, block_size=256, cluster_size=K,
+                 colour_sort=cs)
         node_new = ctx.get_perm(nodes, m.N)
         edge_new = ctx.get_perm(edges, m.E)
         x = np.empty((3, m.N))
@@ -430,7 +438,7 @@ def test_geometry_after_replanning():
                          ctx.decl_dat(edges, w, "w"), ctx.decl_dat(nodes, vol, "vol"),
                          variant=variant)
             ctx.sync()
-            tag = f"{renumber} v{variant}"
+            tag = f"{renumber} K={K} v{variant}"
             assert report(f"geometry w after plan {tag}",
                           normwise(w.cpu().numpy()[:, edge_new], w_ref), TOL64)
             assert report(f"geometry vol after plan {tag}",
