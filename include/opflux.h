@@ -382,8 +382,8 @@ typedef struct {
  *  order, more than 4096 chunk and halo nodes, the tets around an edge not
  *  one fan), each tet's results go to a per-tet buffer that every edge and
  *  node then sums over its incident tets.  The first OWNER call on a pair of
- *  tet maps builds these lists and buffers on the device (about 40 bytes
- *  per edge and 176 per tet; 232 per tet when the forward uses the per-tet
+ *  tet maps builds these lists and buffers on the device (about 60 bytes
+ *  per edge and 192 per tet; 248 per tet when the forward uses the per-tet
  *  buffer), kept until the maps are declared again or opf_finalize; any
  *  other variant is OPF_EINVAL):
  *     (x, ALL, t2n, 3, F64, READ) (w, ALL, t2e, 3, F64, INC)
@@ -398,7 +398,9 @@ typedef struct {
  *   (signed from the edge's first to its second node) and a quarter of its
  *   volume to each vertex.  period > 0: vertices are unwrapped to the image
  *   nearest vertex 0 in a periodic box of that side.
- *  GEOMETRY_ADJ over tets (ATOMIC or OWNER as above): (x, ALL, t2n, 3, READ)
+ *  GEOMETRY_ADJ over tets (ATOMIC, or OWNER: one thread per tet writes its
+ *  four vertex shares to the per-tet buffer, ordered node by node, and each
+ *  node sums its run in a fixed order): (x, ALL, t2n, 3, READ)
  *     (wbar, ALL, t2e, 3, READ) (volbar, ALL, t2n, 1, READ)
  *     (xbar, ALL, t2n, 3, INC) gbl period
  *   xbar += (dw/dx)^T wbar + (dvol/dx)^T volbar (shape sensitivities when

@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_tet_forward(int T, TetArrays a, double 
             v[d] = x[s][d] - x[r][d];
         }
         cross3(u, v, c);
-        const double sg = orient(a.e2n, a.t2e[6 * t + k], g[p]) * (1.0 / 24.0);
+        const double sg = (a.t2e[6 * t + k] < 0 ? -1.0 : 1.0) * (1.0 / 24.0);
 #pragma unroll
         for (int d = 0; d < 3; ++d) rec[3 * k + d] = sg * c[d];
     }
@@ -258,17 +258,24 @@ __global__ __launch_bounds__(256) void k_node_sum_vol(int T, TetArrays a)
     a.vol[i] = (a.write_vol ? 0.0 : a.vol[i]) + acc;
 }
 
-// record of tet t (12 doubles at t * 12): its share of x-bar at local vertex v
-// at 3v + d
-__global__ __launch_bounds__(256) void k_tet_reverse(int T, TetArrays a, double period)
+// the share of x-bar of tet t at its local vertex v: 3 doubles at the
+// (tet, vertex) pair's slot in the node-major list n2t
+// LDS rows: plane of (x, y) pairs, then plane of z (L rows each).
+__device__ __forceinline__ void geo_get(const double *X, int L, uint32_t l, double *x)
 {
-    const int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
-    if (t >= T) return;
-    int g[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) g[v] = a.t2n[4 * t + v];
-    double x[4][3], xb[4][3];
-    tet_x(a, g, period, x);
+    const double2 xy = reinterpret_cast<const double2 *>(X)[l];
+    x[0] = xy.x;
+    x[1] = xy.y;
+    x[2] = X[2 * L + l];
+}
+
+// The reverse of one tet at coordinates x (unwrapped): its x-bar shares xb
+// from the signed weight adjoints cb[k] = +-wbar / 24 of its six local edges
+// and the sum vbs of its vertices' volume adjoints (a quarter of the volume
+// to each vertex).  Face c = u x v / 24: ubar = v x cbar, vbar = cbar x u.
+__device__ __forceinline__ void tet_shares(const double (&x)[4][3], const double (&cb)[6][3],
+                                           double vbs, double (&xb)[4][3])
+{
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -276,17 +283,14 @@ __global__ __launch_bounds__(256) void k_tet_reverse(int T, TetArrays a, double 
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const int p = kTetEdge[k][0], q = kTetEdge[k][1], r = kTetEdge[k][2], s = kTetEdge[k][3];
-        const int ed = a.t2e[6 * t + k];
-        const double sg = orient(a.e2n, ed, g[p]) * (1.0 / 24.0);
-        double u[3], v[3], cb[3], ub[3], vb[3];
+        double u[3], v[3], ub[3], vb[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             u[d] = x[r][d] + x[s][d] - x[p][d] - x[q][d];
             v[d] = x[s][d] - x[r][d];
-            cb[d] = sg * a.w[d][ed];
         }
-        cross3(v, cb, ub);
-        cross3(cb, u, vb);
+        cross3(v, cb[k], ub);
+        cross3(cb[k], u, vb);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             xb[p][d] -= ub[d];
@@ -295,7 +299,8 @@ __global__ __launch_bounds__(256) void k_tet_reverse(int T, TetArrays a, double 
             xb[s][d] += ub[d] + vb[d];
         }
     }
-    const double Vb = 0.25 * (a.vol[g[0]] + a.vol[g[1]] + a.vol[g[2]] + a.vol[g[3]]) * (1.0 / 6.0);
+    // volume V = e1 . (e2 x e3) / 6 with e_k = x_k - x_0
+    const double Vb = 0.25 * vbs * (1.0 / 6.0);
     double e1[3], e2[3], e3[3], c1[3], c2[3], c3[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -313,13 +318,55 @@ __global__ __launch_bounds__(256) void k_tet_reverse(int T, TetArrays a, double 
         xb[3][d] += Vb * c3[d];
         xb[0][d] -= Vb * (c1[d] + c2[d] + c3[d]);
     }
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) a.scratch[(size_t)t * 12 + 3 * v + d] = xb[v][d];
 }
 
-// xbar[i] += sum over the tets around i of their share at i
+// the six weight adjoints of tet t, read from their interleaved copy wT
+__device__ __forceinline__ void tet_wbar(const TetArrays &a, int t, double (&cb)[6][3])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int ew = a.t2e[6 * t + k], ed = ew & 0x7fffffff;
+        const double sg = (ew < 0 ? -1.0 : 1.0) * (1.0 / 24.0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cb[k][d] = sg * a.wT[3 * (size_t)ed + d];
+    }
+}
+
+// wT[3 e + d] = wbar[d][e]: one 24-byte record per edge for the tets' gathers
+__global__ __launch_bounds__(256) void k_interleave_w(TetArrays a)
+{
+    const int e = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (e >= a.E) return;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.wT[3 * (size_t)e + d] = a.w[d][e];
+}
+
+__device__ __forceinline__ void put_shares(const TetArrays &a, int t, const double (&xb)[4][3])
+{
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        double *rec = a.scratch + (size_t)3 * a.n2t_pos[4 * t + v];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) rec[d] = xb[v][d];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tet_reverse(int T, TetArrays a, double period)
+{
+    const int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (t >= T) return;
+    int g[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) g[v] = a.t2n[4 * t + v];
+    double x[4][3], xb[4][3], cb[6][3];
+    tet_x(a, g, period, x);
+    tet_wbar(a, t, cb);
+    tet_shares(x, cb, a.vol[g[0]] + a.vol[g[1]] + a.vol[g[2]] + a.vol[g[3]], xb);
+    put_shares(a, t, xb);
+}
+
+// xbar[i] += sum over the tets around i of their share at i: one contiguous
+// run of records per node
 __global__ __launch_bounds__(256) void k_node_sum_xbar(TetArrays a)
 {
     const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
@@ -330,8 +377,7 @@ __global__ __launch_bounds__(256) void k_node_sum_xbar(TetArrays a)
         double r[kSumAhead][3];
 #pragma unroll
         for (int u = 0; u < kSumAhead; ++u) {
-            const int tv = a.n2t[j + u < end ? j + u : j];
-            const double *rec = a.scratch + (size_t)(tv >> 2) * 12 + 3 * (tv & 3);
+            const double *rec = a.scratch + (size_t)3 * (j + u < end ? j + u : j);
 #pragma unroll
             for (int d = 0; d < 3; ++d) r[u][d] = rec[d];
         }
@@ -360,15 +406,6 @@ __global__ __launch_bounds__(256) void k_node_sum_xbar(TetArrays a)
 // edges of edge_det / 72: a tet lies around three of its edges at each vertex,
 // and each vertex owns a quarter of its volume.  Fixed orders throughout: the
 // same bits on every run.
-
-// LDS rows: plane of (x, y) pairs, then plane of z (L rows each).
-__device__ __forceinline__ void geo_get(const double *X, int L, uint32_t l, double *x)
-{
-    const double2 xy = reinterpret_cast<const double2 *>(X)[l];
-    x[0] = xy.x;
-    x[1] = xy.y;
-    x[2] = X[2 * L + l];
-}
 
 __device__ __forceinline__ void geo_diff(const double *x, const double *a, bool wrap, double period,
                                          double ip, double *d)
@@ -512,6 +549,7 @@ int launch_geometry(bool adjoint, bool gather, int T, const TetArrays &a, double
     if (gather) {
         const dim3 gt((T + 255) / 256), ge((a.E + 255) / 256), gn((a.N + 255) / 256);
         if (adjoint) {
+            hipLaunchKernelGGL(k_interleave_w, ge, dim3(256), 0, st, a);
             hipLaunchKernelGGL(k_tet_reverse, gt, dim3(256), 0, st, T, a, period);
             hipLaunchKernelGGL(k_node_sum_xbar, gn, dim3(256), 0, st, a);
         } else if (a.ring) {

@@ -117,10 +117,14 @@ struct TetArrays {
     const int *t2e = nullptr;
     const int2 *e2n = nullptr;
     // gather form: incident tets of every edge (tet * 8 + local edge) and of
-    // every node (tet * 4 + local vertex), CSR in internal numbering
+    // every node (tet * 4 + local vertex), CSR in internal numbering; n2t_pos:
+    // the index in n2t of every (tet, vertex) pair (tet * 4 + vertex).  In the
+    // gather form's t2e, bit 31 marks an edge that runs from the local edge's
+    // second vertex to its first.
     const int *e2t_off = nullptr, *e2t = nullptr;
-    const int *n2t_off = nullptr, *n2t = nullptr;
+    const int *n2t_off = nullptr, *n2t = nullptr, *n2t_pos = nullptr;
     double *scratch = nullptr;  // gather form: kTetScratch x T doubles
+    double *wT = nullptr;       // gather reverse: wbar interleaved, 3 x E doubles
     // ring form of the forward gather (ring != nullptr): node chunks of KG
     // consecutive internal nodes; chunk c owns the edges chunk_e[c] = (first,
     // count) whose smaller end it holds.  Edge e's entries are
@@ -154,8 +158,8 @@ struct TetArrays {
     double *xbar[3] = {};   // ADJ only
 };
 // Per-tet results of the gather form: 6 signed face vectors (18 values at
-// 18 t) + 1 volume determinant (at 18 T + t) forward, or 4 vertex shares of
-// x-bar (12 values at 12 t) in reverse.
+// 18 t) + 1 volume determinant (at 18 T + t) forward, or in reverse the 4
+// vertex shares of x-bar, each 3 values at 3 n2t_pos[4 t + v] (node-major).
 constexpr int kTetScratch = 19;
 // gather = false: one thread per tet, FP64 atomics (summation order varies);
 // gather = true: one thread per tet writes its results to the scratch

@@ -73,7 +73,9 @@ struct DevTetInverse {
     uint64_t vn = 0, ve = 0;
     int32_t *t2n = nullptr, *t2e = nullptr;  // tets in the gather order
     int32_t *e2t_off = nullptr, *e2t = nullptr, *n2t_off = nullptr, *n2t = nullptr;
+    int32_t *n2t_pos = nullptr;
     double *scratch = nullptr;  // kTetScratch values per tet
+    double *wT = nullptr;       // the reverse's interleaved copy of wbar
     // ring form of the forward (see opf::gpu::TetArrays); ring == nullptr when
     // the mesh does not fit it
     int32_t *ring_off = nullptr, *chunk_e = nullptr, *halo_off = nullptr, *halo = nullptr;
@@ -648,15 +650,21 @@ int device_map(opf_ctx *ctx, opf_map m, const int32_t *&out)
 
 void free_tinv(opf_ctx *ctx, DevTetInverse &d)
 {
-    for (int32_t *p : {d.t2n, d.t2e, d.e2t_off, d.e2t, d.n2t_off, d.n2t, d.ring_off, d.chunk_e,
+    for (int32_t *p : {d.t2n, d.t2e, d.e2t_off, d.e2t, d.n2t_off, d.n2t, d.n2t_pos, d.ring_off, d.chunk_e,
                        d.halo_off, d.halo, d.vsec_off, d.vsec, d.vloc_off})
         ctx->dfree(p);
     ctx->dfree(d.ring);
     ctx->dfree(d.vloc);
     ctx->dfree(d.scratch);
+    ctx->dfree(d.wT);
     ctx->dfree(d.edge_det);
     d = DevTetInverse();
 }
+
+// Local edge k of a tet: vertices (p, q) and the completing pair (r, s) such
+// that (p, q, r, s) is an even permutation of (0, 1, 2, 3).
+const int kLocal[6][4] = {{0, 1, 2, 3}, {0, 2, 3, 1}, {0, 3, 1, 2},
+                          {1, 2, 0, 3}, {1, 3, 2, 0}, {2, 3, 0, 1}};
 
 // Host arrays of the ring form (layout in opf::gpu::TetArrays).
 struct Rings {
@@ -678,10 +686,6 @@ bool build_rings(const std::vector<int32_t> &e2n, int64_t N, int64_t E, int KG,
                  const std::vector<int32_t> &tn, const std::vector<int32_t> &eo,
                  const std::vector<int32_t> &el, Rings &R)
 {
-    // local edge k: vertices (p, q) and the completing pair (r, s) such that
-    // (p, q, r, s) is an even permutation of (0, 1, 2, 3)
-    static const int kLocal[6][4] = {{0, 1, 2, 3}, {0, 2, 3, 1}, {0, 3, 1, 2},
-                                     {1, 2, 0, 3}, {1, 3, 2, 0}, {2, 3, 0, 1}};
     if (KG <= 0 || N <= 0 || (int64_t)eo.size() != E + 1) return false;
     if (E + (int64_t)el.size() >= ((int64_t)1 << 31)) return false;
     const int64_t nch = (N + KG - 1) / KG;
@@ -900,9 +904,23 @@ int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, const opf::Plan &P, DevT
     std::vector<int32_t> eo, el, no, nl;
     invert(te, 6, 8, E, eo, el);
     invert(tn, 4, 4, N, no, nl);
+    // the slot of every (tet, vertex) pair in its node's list: the per-tet
+    // records of the reverse are written there, so that each node sums a
+    // contiguous run
+    std::vector<int32_t> npos(4 * T);
+    for (size_t j = 0; j < nl.size(); ++j) npos[nl[j]] = (int32_t)j;
+    // bit 31 of each local edge: the edge runs from the local edge's second
+    // vertex to its first (the map orients it the other way round)
+    if ((int64_t)P.e2n.size() != 2 * E) return ctx->fail(OPF_ESTATE, "the edge plan has no map");
+    for (int64_t t = 0; t < T; ++t)
+        for (int k = 0; k < 6; ++k) {
+            const int32_t e = te[6 * t + k];
+            if (P.e2n[2 * (int64_t)e] != tn[4 * t + kLocal[k][0]]) te[6 * t + k] = (int32_t)((uint32_t)e | 0x80000000u);
+        }
+    const int KG = P.owner_ok ? P.cluster_size : 512;
     Rings R;
-    const bool rings = (int64_t)P.e2n.size() == 2 * E &&
-                       build_rings(P.e2n, N, E, P.owner_ok ? P.cluster_size : 512, tn, eo, el, R);
+    const bool rings = build_rings(P.e2n, N, E, KG, tn, eo, el, R);
+
     free_tinv(ctx, d);
     auto up = [&](const auto &v, auto *&dst) {
         using V = std::remove_const_t<std::remove_reference_t<decltype(v[0])>>;
@@ -917,6 +935,7 @@ int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, const opf::Plan &P, DevT
     if (!rc) rc = up(el, d.e2t);
     if (!rc) rc = up(no, d.n2t_off);
     if (!rc) rc = up(nl, d.n2t);
+    if (!rc) rc = up(npos, d.n2t_pos);
     if (!rc && rings) {
         rc = up(R.ring_off, d.ring_off);
         if (!rc) rc = up(R.ring, d.ring);
@@ -945,7 +964,8 @@ int tet_inverse(opf_ctx *ctx, opf_map t2n, opf_map t2e, const opf::Plan &P, DevT
     // ring form does not serve it
     const size_t per_tet = rings ? 12 : opf::gpu::kTetScratch;
     d.scratch = static_cast<double *>(ctx->dalloc((size_t)T * per_tet * sizeof(double)));
-    if (!d.scratch) {
+    d.wT = static_cast<double *>(ctx->dalloc((size_t)std::max<int64_t>(E, 1) * 3 * sizeof(double)));
+    if (!d.scratch || !d.wT) {
         free_tinv(ctx, d);
         return ctx->fail(OPF_ENOMEM, "device allocation of the tet scratch failed");
     }
@@ -1019,7 +1039,9 @@ int tet_loop(opf_ctx *ctx, int kernel, opf_set s, int nargs, const opf_arg *args
             ta.e2t = inv->e2t;
             ta.n2t_off = inv->n2t_off;
             ta.n2t = inv->n2t;
+            ta.n2t_pos = inv->n2t_pos;
             ta.scratch = inv->scratch;
+            ta.wT = inv->wT;
             ta.ring_off = inv->ring_off;
             ta.ring = inv->ring;
             ta.chunk_e = reinterpret_cast<const int2 *>(inv->chunk_e);
