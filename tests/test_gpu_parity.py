@@ -473,3 +473,61 @@ def test_owner_and_atomic_without_colouring():
     ctx.sync()
     assert report("hub fused iteration", normwise(p.nodes_out(p.qa), q1), TOL64)
     ctx.close()
+
+
+def test_geometry_bounded_mesh():
+    """A mesh with a boundary (the tets of a periodic box that do not cross its
+    seam, period 0): edges on the boundary have open fans of tets, whose chains
+    do not close.  Both forms of the geometry loop and its reverse against the
+    oracle, for chunks of 128 and 512 nodes."""
+    m = meshgen.build_mesh(12, 1, 0.25)
+    t_all = m.tets()
+    x = m.xyz[:, t_all]  # (3, T, 4)
+    keep = np.all(np.abs(x - x[:, :, :1]).max(axis=2) < 0.5, axis=0)
+    t_old = t_all[keep]
+    used = np.unique(t_old)
+    new_id = np.full(m.N, -1, np.int64)
+    new_id[used] = np.arange(len(used))
+    t2n = new_id[t_old].astype(np.int32)
+    xyz = np.ascontiguousarray(m.xyz[:, used])
+    rng = np.random.default_rng(77)
+    pairs = {tuple(sorted((int(a), int(b)))) for t in t2n
+             for a, b in ((t[0], t[1]), (t[0], t[2]), (t[0], t[3]), (t[1], t[2]), (t[1], t[3]),
+                          (t[2], t[3]))}
+    e2n = np.array(sorted(pairs), dtype=np.int32)
+    flip = rng.random(len(e2n)) < 0.5  # both orientations
+    e2n[flip] = e2n[flip][:, ::-1]
+
+    class _M:
+        pass
+    mm = _M()
+    mm.N, mm.e2n = len(used), e2n
+    t2e = meshgen.tet_edges(mm, t2n)
+    N, E = len(used), len(e2n)
+    print(f"[bounded mesh: {N} nodes, {E} edges, {len(t2n)} of {len(t_all)} tets]", flush=True)
+    w_ref, vol_ref = oracle.geometry(e2n, t2n, t2e, xyz, period=0.0)
+    wbar, volbar = rng.normal(size=(3, E)), rng.normal(size=N)
+    xb_ref = oracle.geometry_adjoint(e2n, t2n, t2e, xyz, wbar, volbar, period=0.0)
+    q = np.tile(np.array([1.0, 0.1, 0.0, 0.0, 2.5, 0.3])[:, None], (1, N))
+    for K in (128, 512):
+        ctx = pk.Context(DEV)
+        p = pk.FluxProblem(ctx, e2n, np.zeros((3, E)), np.ones(N), q, renumber="morton",
+                           coords=xyz, cluster_size=K, tets=t2n, tet_edges=t2e)
+        xd = p.nodes_in(xyz)
+        for variant in (pk.OWNER, pk.ATOMIC):
+            w = torch.zeros((3, E), dtype=torch.float64, device=DEV)
+            vol = torch.zeros(N, dtype=torch.float64, device=DEV)
+            p.geometry(xd, w, vol, period=0.0, variant=variant)
+            xbar = torch.zeros((3, N), dtype=torch.float64, device=DEV)
+            p.geometry_adjoint(xd, p.nodes_in(wbar, edges=True),
+                               p.nodes_in(volbar[None])[0].contiguous(), xbar, period=0.0,
+                               variant=variant)
+            p.ctx.sync()
+            tag = f"K={K} v{variant}"
+            assert report(f"bounded geometry w {tag}", normwise(p.nodes_out(w, edges=True), w_ref),
+                          TOL64)
+            assert report(f"bounded geometry vol {tag}",
+                          normwise(p.nodes_out(vol[None]), vol_ref[None]), TOL64)
+            assert report(f"bounded geometry xbar {tag}", normwise(p.nodes_out(xbar), xb_ref),
+                          TOL64)
+        ctx.close()
