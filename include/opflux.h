@@ -464,13 +464,16 @@ int opf_edge_flux_stage(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc.  Same arguments, checks, kernels and results; the per-cluster
  * partial sums go to a static device array of the library (6 doubles for each
- * of at most 16384 owner clusters, 768 KiB; one copy per GPU, resolved by
- * opf_init and held until the process ends) instead of the plan's buffer.  The
+ * of at most 16384 owner clusters, 768 KiB, and 784 bytes for the final sum
+ * and its counter; one copy per GPU, resolved by opf_init and held until the
+ * process ends) instead of the plan's buffer.  The
  * call allocates nothing (no hipMalloc, no context scratch, no event) and does
  * not order itself against other streams: every call on one GPU, from any
  * context, shares that array, so calls that overlap in time on one GPU race.
- * Every cluster writes its partials before they are summed, so nothing needs
- * clearing between calls.  The plan (opf_plan) must exist already.
+ * Every cluster writes its partials before they are summed, and the final
+ * sum's counter starts at zero (static initialisation) and returns to zero at
+ * the end of every call, so nothing needs clearing between calls.  The plan
+ * (opf_plan) must exist already.
  * Errors: as opf_edge_flux_stage; OPF_ESIZE when the plan has more than 16384
  * clusters; OPF_ESTATE when the static array could not be resolved. */
 int opf_edge_flux_stage_noalloc(opf_ctx *ctx, opf_set edges, opf_map e2n, opf_dat q, opf_dat n,

@@ -39,7 +39,7 @@
 // partial sums (6 doubles per cluster).  Host code must not pass this name to a
 // kernel -- on the host it is only a stand-in for the symbol; the device address
 // comes from static_scratch_address(), resolved once per device.
-static __device__ __align__(256) double scratch[6 * opf::gpu::kStaticMaxClusters];
+static __device__ __align__(256) double scratch[opf::gpu::kSumTail + 6 * opf::gpu::kStaticMaxClusters];
 
 // Tuning of the owner kernel per (type, op): edges each thread resolves before
 // computing (B), and the waves per SIMD the register allocator must allow
@@ -1008,61 +1008,82 @@ __global__ __launch_bounds__(kRkThreads) void k_local_dt(int N, const double *__
         dt[i] = cfl * vol[i] / lam[i];
 }
 
-// ss[0..5] += the sum of nparts rows of 6 partial sums.  One workgroup; each
-// thread owns a fixed set of rows and issues the loads of kSumRows rows at once
-// as 16-byte words (the kernel is latency-bound: one round trip for up to
-// 8192 rows), so the order of the additions is fixed.
-constexpr int kSumThreads = 1024, kSumRows = 8;
+// ss[0..5] += the sum of nparts rows of 6 partial sums (rows at buf +
+// kSumTail).  Workgroup g of kSumGroups sums the rows [g R, (g+1) R), each
+// thread a fixed stride of them, then through a fixed LDS tree, into
+// buf[6 g ..]; the last workgroup to finish adds the kSumGroups sums in
+// order.  Every order is fixed, so the result is the same on every run.
+constexpr int kSumThreads = 256;
 
-__global__ __launch_bounds__(kSumThreads) void k_sum_partials(int nparts, const double *partial,
-                                                              double *ss)
+__global__ __launch_bounds__(kSumThreads) void k_sum_partials(int nparts, double *buf, double *ss)
 {
+    const double *rows = buf + kSumTail;
+    unsigned int *counter = reinterpret_cast<unsigned int *>(buf + 6 * kSumGroups);
+    const int g = (int)blockIdx.x, t = (int)threadIdx.x;
+    const int per = (nparts + kSumGroups - 1) / kSumGroups;
+    const int r0 = g * per, r1 = min(nparts, r0 + per);
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const double2 *p2 = reinterpret_cast<const double2 *>(partial);  // a row is 3 words
-    for (int r0 = threadIdx.x; r0 < nparts; r0 += kSumThreads * kSumRows) {
-        double2 r[kSumRows][3];
+    constexpr int U = 4;  // rows whose loads are in flight together
+    for (int r = r0 + t; r < r1; r += kSumThreads * U) {
+        double2 v[U][3];
 #pragma unroll
-        for (int u = 0; u < kSumRows; ++u) {
-            const int k = r0 + u * kSumThreads;
+        for (int u = 0; u < U; ++u) {
+            const int k = r + u * kSumThreads;
+            const double2 *p2 = reinterpret_cast<const double2 *>(rows + 6 * (size_t)k);
 #pragma unroll
-            for (int w = 0; w < 3; ++w) r[u][w] = k < nparts ? p2[3 * k + w] : make_double2(0.0, 0.0);
+            for (int w = 0; w < 3; ++w) v[u][w] = k < r1 ? p2[w] : make_double2(0.0, 0.0);
         }
 #pragma unroll
-        for (int u = 0; u < kSumRows; ++u)
+        for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int w = 0; w < 3; ++w) {
-                acc[2 * w] += r[u][w].x;
-                acc[2 * w + 1] += r[u][w].y;
+                acc[2 * w] += v[u][w].x;
+                acc[2 * w + 1] += v[u][w].y;
             }
     }
-    // fixed tree through LDS: 64 lanes x 16 per component, then 8 x 8, then 8
-    __shared__ double buf[6 * kSumThreads];
-    const int t = threadIdx.x;
+    // fixed tree through LDS: 64 lanes x 4 per component (384 sums over 256
+    // threads), then 8 x 8, then 8
+    __shared__ double red[6 * kSumThreads];
+    __shared__ int last;
 #pragma unroll
-    for (int v = 0; v < 6; ++v) buf[v * kSumThreads + t] = acc[v];
+    for (int v = 0; v < 6; ++v) red[v * kSumThreads + t] = acc[v];
     __syncthreads();
-    if (t < 6 * 64) {
-        const int v = t >> 6, j = t & 63;
+    for (int idx = t; idx < 6 * 64; idx += kSumThreads) {
+        const int v = idx >> 6, j = idx & 63;
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < kSumThreads / 64; ++i) s += buf[v * kSumThreads + j + 64 * i];
-        buf[v * kSumThreads + j] = s;
+        for (int i = 0; i < kSumThreads / 64; ++i) s += red[v * kSumThreads + j + 64 * i];
+        red[v * kSumThreads + j] = s;
     }
     __syncthreads();
     if (t < 6 * 8) {
         const int v = t >> 3, j = t & 7;
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) s += buf[v * kSumThreads + j + 8 * i];
-        buf[v * kSumThreads + j] = s;
+        for (int i = 0; i < 8; ++i) s += red[v * kSumThreads + j + 8 * i];
+        red[v * kSumThreads + j] = s;
     }
     __syncthreads();
     if (t < 6) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) s += buf[t * kSumThreads + i];
+        for (int i = 0; i < 8; ++i) s += red[t * kSumThreads + i];
+        buf[6 * g + t] = s;
+    }
+    // publish this group's sums, then count it; the last group sees all
+    __threadfence();
+    __syncthreads();
+    if (t == 0) last = atomicAdd(counter, 1u) == (unsigned int)(kSumGroups - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (t < 6) {
+        const volatile double *vb = buf;
+        double s = 0.0;
+        for (int i = 0; i < kSumGroups; ++i) s += vb[6 * i + t];
         ss[t] += s;
     }
+    if (t == 0) *counter = 0u;
 }
 
 template <int NV>
@@ -1215,7 +1236,7 @@ int run_owner_stage(const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
     sp.vol = na.vol;
     sp.dt = na.dt;
     sp.adt = adt;
-    sp.partial = partial;
+    sp.partial = partial + kSumTail;
     if (P.K == kOwnerKC)
         hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, kOwnerKC, true>), dim3(P.ncl),
                            dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
@@ -1224,7 +1245,8 @@ int run_owner_stage(const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
         hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, 0, true>), dim3(P.ncl),
                            dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
                            lo.xcd_remap, 0, sp);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSumThreads), 0, st, P.ncl, partial, ss);
+    hipLaunchKernelGGL(k_sum_partials, dim3(kSumGroups), dim3(kSumThreads), 0, st, P.ncl, partial,
+                       ss);
     return (int)hipGetLastError();
 }
 
@@ -1388,8 +1410,9 @@ static int run_rk(int N, const NodeArrays &a, double alpha_dt, double *ss, doubl
     p.dt = a.dt;
     const int grid = std::min(kRkBlocks, std::max(1, (N + kRkThreads - 1) / kRkThreads));
     hipLaunchKernelGGL((k_rk_stage<T>), dim3(grid), dim3(kRkThreads), 0, st, N, p, alpha_dt,
-                       partial, keep_res ? 1 : 0);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kSumThreads), 0, st, grid, partial, ss);
+                       partial + kSumTail, keep_res ? 1 : 0);
+    hipLaunchKernelGGL(k_sum_partials, dim3(kSumGroups), dim3(kSumThreads), 0, st, grid, partial,
+                       ss);
     return (int)hipGetLastError();
 }
 
@@ -1404,8 +1427,10 @@ int launch_dt_min(int N, const double *vol, const double *lam, double cfl, doubl
                   double *partial, hipStream_t st)
 {
     const int grid = std::min(kRkBlocks, std::max(1, (N + kRkThreads - 1) / kRkThreads));
-    hipLaunchKernelGGL(k_dt_min, dim3(grid), dim3(kRkThreads), 0, st, N, vol, lam, partial);
-    hipLaunchKernelGGL(k_min_partials, dim3(1), dim3(256), 0, st, grid, partial, cfl, dt);
+    hipLaunchKernelGGL(k_dt_min, dim3(grid), dim3(kRkThreads), 0, st, N, vol, lam,
+                       partial + kSumTail);
+    hipLaunchKernelGGL(k_min_partials, dim3(1), dim3(256), 0, st, grid, partial + kSumTail, cfl,
+                       dt);
     return (int)hipGetLastError();
 }
 

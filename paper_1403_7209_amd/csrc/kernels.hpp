@@ -48,7 +48,7 @@ struct DevPlan {
                                      // the owned end is the edge's second node
     const uint16_t *cv_own = nullptr; // offset of the owned end in the cluster
     // flat colouring: colour c runs edges flat_eid[flat_off[c] .. flat_off[c+1])
-    double *stage_partial = nullptr;  // [ncl][6] partial sums of the fused stage
+    double *stage_partial = nullptr;  // kSumTail + [ncl][6]: partial sums of the fused stage
     int nflat = 0;
     std::vector<int64_t> flat_off;  // host copy [nflat+1]
     const int *flat_eid = nullptr;  // [E]
@@ -80,9 +80,18 @@ struct NodeArrays {
     const double *dt = nullptr;  // per-node time steps, or null for one global step
 };
 
+// Buffers of partial sums (the stage reductions): kSumTail doubles, then 6
+// per row.  The second pass sums the rows in kSumGroups workgroups, each over
+// a fixed block of rows in a fixed order, into the first 6 * kSumGroups
+// doubles; the last workgroup to finish (a counter in the next word) adds
+// those in order.  The counter must be zero before the first use of a buffer
+// and is zero again after every pass.
+constexpr int kSumGroups = 16;
+constexpr int kSumTail = 6 * kSumGroups + 2;
+
 // q = q0 - alpha_dt * res / vol (alpha_dt * dt_i with per-node steps),
 // ss[v] += sum res^2 (two passes, deterministic), res = 0 unless keep_res.
-// `partial` holds kRkBlocks * 6 doubles.
+// `partial` holds kSumTail + kRkBlocks * 6 doubles.
 constexpr int kRkThreads = 256;
 constexpr int kRkBlocks = 2048;
 int launch_rk_stage(bool fp32, int N, const NodeArrays &a, double alpha_dt, double *ss,
@@ -92,21 +101,23 @@ int launch_rk_stage(bool fp32, int N, const NodeArrays &a, double alpha_dt, doub
 // q = q0 - adt * res / vol (adt * dt_i when a.dt is set) for every node, and
 // ss[v] += sum res^2 (per-cluster partials, fixed-order second pass); the
 // residual is never written.  The plan must have owner clusters.  `partial`
-// holds 6 * P.ncl doubles; every cluster writes its six before they are summed,
-// so it needs no clearing.
+// holds kSumTail + 6 * P.ncl doubles (counter zero); every cluster writes its
+// six before they are summed.
 int launch_edge_stage(bool fp32, const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
                       double gamma, double adt, double *ss, double *partial, hipStream_t stream,
                       const LaunchOpts &lo);
 
 // Clusters whose partial sums fit the library's static device scratch (the
-// fused stage for callers that cannot allocate): 6 doubles each, 768 KiB.
+// fused stage for callers that cannot allocate): 6 doubles each, 768 KiB,
+// after the kSumTail doubles of the second pass.
 constexpr int kStaticMaxClusters = 16384;
 
 // Device address of that static scratch on the current device (each GPU holds
 // its own copy).  Returns 0 or a hipError_t value.
 int static_scratch_address(double **out);
 
-// dt = min(dt, cfl * min_i vol_i / lam_i); `partial` holds kRkBlocks doubles.
+// dt = min(dt, cfl * min_i vol_i / lam_i); `partial` holds kSumTail +
+// kRkBlocks doubles (the rows after the tail).
 int launch_dt_min(int N, const double *vol, const double *lam, double cfl, double *dt,
                   double *partial, hipStream_t stream);
 

@@ -247,11 +247,16 @@ int upload_plan(opf_ctx *ctx, PlanRec &pr)
         if (P.cluster_size > 8192) return ctx->fail(OPF_EINVAL, "cluster_size above 8192");
         rc = upload_owner(ctx, pr);
         if (!rc) {
-            D.stage_partial = static_cast<double *>(ctx->dalloc(sizeof(double) * 6 * D.ncl));
-            if (!D.stage_partial)
+            const size_t nb = sizeof(double) * (opf::gpu::kSumTail + 6 * (size_t)D.ncl);
+            D.stage_partial = static_cast<double *>(ctx->dalloc(nb));
+            if (!D.stage_partial) {
                 rc = ctx->fail(OPF_ENOMEM, "device allocation of plan arrays failed");
-            else
+            } else {
                 pr.bufs.push_back(D.stage_partial);
+                // the second pass's counter starts at zero
+                const hipError_t e = hipMemset(D.stage_partial, 0, nb);
+                if (e != hipSuccess) rc = hip_fail(ctx, e, "clearing the stage partial sums");
+            }
         }
     }
     if (P.flat_ok) {
@@ -368,9 +373,11 @@ int device_ready(opf_ctx *ctx)
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
     if (!ctx->scratch) {
-        ctx->scratch = static_cast<double *>(
-            ctx->dalloc(sizeof(double) * 6 * opf::gpu::kRkBlocks));
+        const size_t nb = sizeof(double) * (opf::gpu::kSumTail + 6 * opf::gpu::kRkBlocks);
+        ctx->scratch = static_cast<double *>(ctx->dalloc(nb));
         if (!ctx->scratch) return ctx->fail(OPF_ENOMEM, "scratch allocation failed");
+        const hipError_t e = hipMemset(ctx->scratch, 0, nb);  // the second pass's counter
+        if (e != hipSuccess) return hip_fail(ctx, e, "clearing the scratch");
     }
     return OPF_OK;
 }
