@@ -280,11 +280,16 @@ typedef struct {
      * c, read through local offsets), then its cut visits
      * cluster_cut_edges[cluster_cut_offsets[c] .. [c+1]), one (edge, owned
      * end) pair each: cluster_cut_ends 0 names the edge's first node, 1 its
-     * second.  Every end of every edge is covered exactly once. */
+     * second.  Every end of every edge is covered exactly once.  The
+     * cluster_cutf_* arrays hold the same visits of each cluster in a second
+     * order (by foreign node within each run of one other cluster), the one
+     * the kernels with wide foreign records use. */
     const int32_t *cluster_interior;     /* [nclusters]                     */
     const int64_t *cluster_cut_offsets;  /* [nclusters+1]                   */
     const int32_t *cluster_cut_edges;
     const uint8_t *cluster_cut_ends;
+    const int32_t *cluster_cutf_edges;
+    const uint8_t *cluster_cutf_ends;
 } opf_plan_view;
 
 int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out);

@@ -96,7 +96,8 @@ class PlanView(ctypes.Structure):
                 ("nflat_colours", ctypes.c_int64), ("flat_offsets", ctypes.c_void_p),
                 ("flat_edges", ctypes.c_void_p), ("owner_swap", ctypes.c_void_p),
                 ("cluster_interior", ctypes.c_void_p), ("cluster_cut_offsets", ctypes.c_void_p),
-                ("cluster_cut_edges", ctypes.c_void_p), ("cluster_cut_ends", ctypes.c_void_p)]
+                ("cluster_cut_edges", ctypes.c_void_p), ("cluster_cut_ends", ctypes.c_void_p),
+                ("cluster_cutf_edges", ctypes.c_void_p), ("cluster_cutf_ends", ctypes.c_void_p)]
 
 
 class PlanReport(ctypes.Structure):
@@ -311,7 +312,11 @@ class Context:
                     cluster_cut_edges=arr(v.cluster_cut_edges, ctypes.c_int32, int(coff[-1]),
                                           np.int32),
                     cluster_cut_ends=arr(v.cluster_cut_ends, ctypes.c_uint8, int(coff[-1]),
-                                         np.uint8))
+                                         np.uint8),
+                    cluster_cutf_edges=arr(v.cluster_cutf_edges, ctypes.c_int32, int(coff[-1]),
+                                           np.int32),
+                    cluster_cutf_ends=arr(v.cluster_cutf_ends, ctypes.c_uint8, int(coff[-1]),
+                                          np.uint8))
 
     def plan_verify(self, m):
         rep = PlanReport()

@@ -363,33 +363,43 @@ struct OpFlux2 {
 
 // B: edges each thread resolves before computing in the interior loop, BC in
 // the cut-visit loop (whose gathered records cost registers).
+// FOREIGN: the cut visits in the plan's foreign-node order (the lanes of a
+// wavefront share foreign records: pays where those records are wide and
+// bandwidth binds) rather than the bank-spread order (pays where the LDS
+// updates bind).
 template <typename T, class Op>
 struct OwnerTune {
     static constexpr int B = 2, BC = 2, WAVES = 0, NT = kOwnerThreads;
+    static constexpr bool FOREIGN = false;
 };
 template <>
 struct OwnerTune<float, OpFlux> {
     static constexpr int B = OPF_FLUX32_BATCH, BC = OPF_FLUX32_CUT_BATCH, WAVES = OPF_FLUX32_WAVES,
                          NT = kOwnerThreads;
+    static constexpr bool FOREIGN = false;
 };
 template <>
 struct OwnerTune<double, OpFlux> {
     static constexpr int B = OPF_FLUX64_BATCH, BC = OPF_FLUX64_CUT_BATCH, WAVES = OPF_FLUX64_WAVES,
                          NT = kOwnerThreads;
+    static constexpr bool FOREIGN = true;
 };
 template <>
 struct OwnerTune<double, OpAdjoint> {
     static constexpr int B = OPF_ADJ_BATCH, BC = OPF_ADJ_CUT_BATCH, WAVES = OPF_ADJ_WAVES,
                          NT = kOwnerThreads;
+    static constexpr bool FOREIGN = true;
 };
 template <>
 struct OwnerTune<double, OpGrad> {
     static constexpr int B = OPF_GRAD_BATCH, BC = OPF_GRAD_BATCH, WAVES = 0, NT = OPF_GRAD_THREADS;
+    static constexpr bool FOREIGN = false;
 };
 template <>
 struct OwnerTune<double, OpFlux2> {
     static constexpr int B = OPF_FLUX2_BATCH, BC = OPF_FLUX2_CUT_BATCH, WAVES = 0,
                          NT = OPF_FLUX2_THREADS;
+    static constexpr bool FOREIGN = true;
 };
 
 // ----------------------------------------------------------- plumbing -- */
@@ -1196,8 +1206,9 @@ constexpr size_t owner_dyn_lds(int K)
     return stage_bytes<T, Op>(K) + (size_t)Op::NOUT * owner_acc_rows(K) * sizeof(double);
 }
 
-OwnerPtrs owner_ptrs(const DevPlan &P)
+OwnerPtrs owner_ptrs(const DevPlan &P, bool foreign)
 {
+    if (foreign) return OwnerPtrs{P.iblk, P.iw, P.cv_off, P.cvf_eid, P.cvf_oth, P.cvf_own};
     return OwnerPtrs{P.iblk, P.iw, P.cv_off, P.cv_eid, P.cv_oth, P.cv_own};
 }
 
@@ -1210,7 +1221,7 @@ int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t s
 {
     if (!P.owner_ok || P.ncl <= 0) return (int)hipErrorInvalidValue;
     const size_t lds = owner_dyn_lds<T, Op>(P.K);
-    const OwnerPtrs op = owner_ptrs(P);
+    const OwnerPtrs op = owner_ptrs(P, OwnerTune<T, Op>::FOREIGN);
     constexpr int NT = OwnerTune<T, Op>::NT;
     if (P.K == kOwnerKC)
         hipLaunchKernelGGL((k_edge_owner<T, Op, NT, kOwnerKC>), dim3(P.ncl), dim3(NT), lds, st, op,
@@ -1227,7 +1238,7 @@ int run_owner_stage(const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
 {
     if (!P.owner_ok || P.ncl <= 0 || !partial) return (int)hipErrorInvalidValue;
     const size_t lds = owner_dyn_lds<T, OpFlux>(P.K);
-    const OwnerPtrs op = owner_ptrs(P);
+    const OwnerPtrs op = owner_ptrs(P, OwnerTune<T, OpFlux>::FOREIGN);
     StagePtrs<T> sp;
     for (int k = 0; k < 6; ++k) {
         sp.q0[k] = static_cast<const T *>(na.q0[k]);

@@ -47,6 +47,9 @@ struct DevPlan {
     const int *cv_oth = nullptr;     // its other end (internal node), bit 31 set when
                                      // the owned end is the edge's second node
     const uint16_t *cv_own = nullptr; // offset of the owned end in the cluster
+    // the same visits ordered by foreign node within each run (same offsets)
+    const int *cvf_eid = nullptr, *cvf_oth = nullptr;
+    const uint16_t *cvf_own = nullptr;
     // flat colouring: colour c runs edges flat_eid[flat_off[c] .. flat_off[c+1])
     double *stage_partial = nullptr;  // kSumTail + [ncl][6]: partial sums of the fused stage
     int nflat = 0;

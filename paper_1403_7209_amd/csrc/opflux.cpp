@@ -193,22 +193,28 @@ int upload_owner(opf_ctx *ctx, PlanRec &pr)
         }
     }
     const size_t nv = P.cl_cut_eid.size();
-    std::vector<int> cv_off(ncl + 1), cv_oth(nv);
-    std::vector<uint16_t> cv_own(nv);
+    std::vector<int> cv_off(ncl + 1);
     for (int64_t c = 0; c <= ncl; ++c) cv_off[c] = (int)P.cl_cut_off[c];
-    for (int64_t c = 0; c < ncl; ++c)
-        for (int64_t s = P.cl_cut_off[c]; s < P.cl_cut_off[c + 1]; ++s) {
-            const int64_t e = P.cl_cut_eid[s];
-            const int h = P.cl_cut_end[s];
-            cv_oth[s] = (int)((uint32_t)P.e2n[2 * e + 1 - h] | ((uint32_t)h << 31));
-            cv_own[s] = (uint16_t)(P.e2n[2 * e + h] - c * K);
-        }
     int rc = upload(ctx, pr, iblk, D.iblk);
     if (!rc) rc = upload(ctx, pr, iw, D.iw);
     if (!rc) rc = upload(ctx, pr, cv_off, D.cv_off);
-    if (!rc) rc = upload(ctx, pr, P.cl_cut_eid, D.cv_eid);
-    if (!rc) rc = upload(ctx, pr, cv_oth, D.cv_oth);
-    if (!rc) rc = upload(ctx, pr, cv_own, D.cv_own);
+    // both orders of the cut visits: edge, other end | orientation, owned offset
+    for (int order = 0; order < 2 && !rc; ++order) {
+        const std::vector<int32_t> &ce = order ? P.cl_cutf_eid : P.cl_cut_eid;
+        const std::vector<uint8_t> &ch = order ? P.cl_cutf_end : P.cl_cut_end;
+        std::vector<int> cv_oth(nv);
+        std::vector<uint16_t> cv_own(nv);
+        for (int64_t c = 0; c < ncl; ++c)
+            for (int64_t s = P.cl_cut_off[c]; s < P.cl_cut_off[c + 1]; ++s) {
+                const int64_t e = ce[s];
+                const int h = ch[s];
+                cv_oth[s] = (int)((uint32_t)P.e2n[2 * e + 1 - h] | ((uint32_t)h << 31));
+                cv_own[s] = (uint16_t)(P.e2n[2 * e + h] - c * K);
+            }
+        rc = upload(ctx, pr, ce, order ? D.cvf_eid : D.cv_eid);
+        if (!rc) rc = upload(ctx, pr, cv_oth, order ? D.cvf_oth : D.cv_oth);
+        if (!rc) rc = upload(ctx, pr, cv_own, order ? D.cvf_own : D.cv_own);
+    }
     return rc;
 }
 
@@ -1460,6 +1466,8 @@ int opf_plan_view_get(const opf_ctx *ctx, opf_map map, opf_plan_view *out)
     out->cluster_cut_offsets = P.cl_cut_off.data();
     out->cluster_cut_edges = P.cl_cut_eid.data();
     out->cluster_cut_ends = P.cl_cut_end.data();
+    out->cluster_cutf_edges = P.cl_cutf_eid.data();
+    out->cluster_cutf_ends = P.cl_cutf_end.data();
     return OPF_OK;
 }
 

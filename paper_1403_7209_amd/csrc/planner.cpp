@@ -708,8 +708,8 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
             while (t < pn && P.e2n[2 * (p0 + t)] / K == c && P.e2n[2 * (p0 + t) + 1] / K == c) ++t;
             P.cl_nint[c] = (int32_t)t;
         }
-        std::vector<std::vector<int32_t>> cut_eid(ncl);
-        std::vector<std::vector<uint8_t>> cut_end(ncl);
+        std::vector<std::vector<int32_t>> cut_eid(ncl), cutf_eid(ncl);
+        std::vector<std::vector<uint8_t>> cut_end(ncl), cutf_end(ncl);
         parallel_for(ncl, [&](int64_t c) {
             std::vector<int64_t> src;
             const int64_t p0 = P.cl_prim[2 * c], pn = P.cl_prim[2 * c + 1];
@@ -723,6 +723,29 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
                         ve.push_back((int32_t)e);
                         vh.push_back((uint8_t)h);
                     }
+            {
+                // the second order: each run sorted by (foreign node, owned node)
+                const int64_t n = (int64_t)ve.size();
+                auto foreign = [&](int64_t t) { return P.e2n[2 * ve[t] + (1 - vh[t])]; };
+                auto owned = [&](int64_t t) { return P.e2n[2 * ve[t] + vh[t]]; };
+                std::vector<int64_t> idx(n);
+                std::iota(idx.begin(), idx.end(), 0);
+                for (int64_t a = 0; a < n;) {
+                    int64_t b = a + 1;
+                    while (b < n && foreign(b) / K == foreign(a) / K) ++b;
+                    std::stable_sort(idx.begin() + a, idx.begin() + b, [&](int64_t x, int64_t y) {
+                        if (foreign(x) != foreign(y)) return foreign(x) < foreign(y);
+                        return owned(x) < owned(y);
+                    });
+                    a = b;
+                }
+                cutf_eid[c].resize(n);
+                cutf_end[c].resize(n);
+                for (int64_t t = 0; t < n; ++t) {
+                    cutf_eid[c][t] = ve[idx[t]];
+                    cutf_end[c][t] = vh[idx[t]];
+                }
+            }
             if (!opt.bank_spread) return;
             std::vector<int32_t> ends, te;
             std::vector<uint8_t> th;
@@ -754,9 +777,13 @@ int build_plan(int64_t N, int64_t E, const int32_t *e2n_user, const PlanOptions 
         for (int64_t c = 0; c < ncl; ++c) P.cl_cut_off[c + 1] = P.cl_cut_off[c] + (int64_t)cut_eid[c].size();
         P.cl_cut_eid.resize(P.cl_cut_off[ncl]);
         P.cl_cut_end.resize(P.cl_cut_off[ncl]);
+        P.cl_cutf_eid.resize(P.cl_cut_off[ncl]);
+        P.cl_cutf_end.resize(P.cl_cut_off[ncl]);
         for (int64_t c = 0; c < ncl; ++c) {
             std::copy(cut_eid[c].begin(), cut_eid[c].end(), P.cl_cut_eid.begin() + P.cl_cut_off[c]);
             std::copy(cut_end[c].begin(), cut_end[c].end(), P.cl_cut_end.begin() + P.cl_cut_off[c]);
+            std::copy(cutf_eid[c].begin(), cutf_eid[c].end(), P.cl_cutf_eid.begin() + P.cl_cut_off[c]);
+            std::copy(cutf_end[c].begin(), cutf_end[c].end(), P.cl_cutf_end.begin() + P.cl_cut_off[c]);
         }
         P.owner_ok = true;
     }
@@ -1039,32 +1066,38 @@ VerifyResult verify_plan(const Plan &P, const int32_t *e2n_user)
             if (seen[k] != want) return fail(8, k, "edge missing from its clusters' visit lists");
         }
         // the two loops of the owner kernel cover every end of every edge exactly
-        // once: interior blocks both ends, each cut visit the end it names
+        // once: interior blocks both ends, each cut visit the end it names (in
+        // both orders of the cut visits)
         if ((int64_t)P.cl_nint.size() != ncl || (int64_t)P.cl_cut_off.size() != ncl + 1 ||
             P.cl_cut_off[0] != 0 || P.cl_cut_off[ncl] != (int64_t)P.cl_cut_eid.size() ||
-            P.cl_cut_eid.size() != P.cl_cut_end.size())
+            P.cl_cut_eid.size() != P.cl_cut_end.size() || P.cl_cutf_eid.size() != P.cl_cut_eid.size() ||
+            P.cl_cutf_end.size() != P.cl_cut_eid.size())
             return fail(8, -1, "interior blocks or cut visits are inconsistent");
-        std::vector<uint8_t> ends(E, 0);  // bit h: end h covered
-        for (int64_t c = 0; c < ncl; ++c) {
-            const int64_t p0 = P.cl_prim[2 * c], ni = P.cl_nint[c];
-            if (ni < 0 || ni > P.cl_prim[2 * c + 1]) return fail(8, c, "interior block outside the range");
-            for (int64_t k = p0; k < p0 + ni; ++k) {
-                if (P.e2n[2 * k] / K != c || P.e2n[2 * k + 1] / K != c)
-                    return fail(8, k, "interior block holds an edge with an end outside the cluster");
-                if (ends[k]) return fail(8, k, "edge end covered twice");
-                ends[k] = 3;
+        for (int order = 0; order < 2; ++order) {
+            const std::vector<int32_t> &ce = order ? P.cl_cutf_eid : P.cl_cut_eid;
+            const std::vector<uint8_t> &ch = order ? P.cl_cutf_end : P.cl_cut_end;
+            std::vector<uint8_t> ends(E, 0);  // bit h: end h covered
+            for (int64_t c = 0; c < ncl; ++c) {
+                const int64_t p0 = P.cl_prim[2 * c], ni = P.cl_nint[c];
+                if (ni < 0 || ni > P.cl_prim[2 * c + 1]) return fail(8, c, "interior block outside the range");
+                for (int64_t k = p0; k < p0 + ni; ++k) {
+                    if (P.e2n[2 * k] / K != c || P.e2n[2 * k + 1] / K != c)
+                        return fail(8, k, "interior block holds an edge with an end outside the cluster");
+                    if (ends[k]) return fail(8, k, "edge end covered twice");
+                    ends[k] = 3;
+                }
+                for (int64_t s = P.cl_cut_off[c]; s < P.cl_cut_off[c + 1]; ++s) {
+                    const int64_t k = ce[s];
+                    const int h = ch[s];
+                    if (k < 0 || k >= E || h > 1) return fail(8, s, "cut visit out of range");
+                    if (P.e2n[2 * k + h] / K != c) return fail(8, s, "cut visit names an end outside the cluster");
+                    if (ends[k] & (1 << h)) return fail(8, k, "edge end covered twice");
+                    ends[k] |= (uint8_t)(1 << h);
+                }
             }
-            for (int64_t s = P.cl_cut_off[c]; s < P.cl_cut_off[c + 1]; ++s) {
-                const int64_t k = P.cl_cut_eid[s];
-                const int h = P.cl_cut_end[s];
-                if (k < 0 || k >= E || h > 1) return fail(8, s, "cut visit out of range");
-                if (P.e2n[2 * k + h] / K != c) return fail(8, s, "cut visit names an end outside the cluster");
-                if (ends[k] & (1 << h)) return fail(8, k, "edge end covered twice");
-                ends[k] |= (uint8_t)(1 << h);
-            }
+            for (int64_t k = 0; k < E; ++k)
+                if (ends[k] != 3) return fail(8, k, "edge end missing from the owner kernel's loops");
         }
-        for (int64_t k = 0; k < E; ++k)
-            if (ends[k] != 3) return fail(8, k, "edge end missing from the owner kernel's loops");
     }
     // (9) flat colouring: every edge in exactly one colour; edges of one colour
     // share no node

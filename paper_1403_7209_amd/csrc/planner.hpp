@@ -86,11 +86,17 @@ struct Plan {
     // offsets.  Then its cut visits cl_cut_eid[cl_cut_off[c] .. [c+1]): every
     // other (edge, end in c) pair, the end given by cl_cut_end (0: the edge's
     // first node, 1: its second), one owned end per visit, ordered so that the
-    // owned ends of 16 consecutive visits fall in distinct LDS banks.
+    // owned ends of 16 consecutive visits fall in distinct LDS banks.  The same
+    // visits of each cluster again in cl_cutf_*, ordered within each run (one
+    // other cluster) by their foreign node, then their owned node, so that the
+    // lanes of a wavefront gather few foreign records: the loops with wide
+    // foreign records use this order, the others the bank-spread one.
     std::vector<int32_t> cl_nint;
     std::vector<int64_t> cl_cut_off;
     std::vector<int32_t> cl_cut_eid;
     std::vector<uint8_t> cl_cut_end;
+    std::vector<int32_t> cl_cutf_eid;
+    std::vector<uint8_t> cl_cutf_end;
     // Flat colouring (one level over all edges; no partitions): edges
     // flat_eid[flat_off[c] .. flat_off[c+1]) have colour c and share no node.
     bool flat_ok = false;  // false when more than 128 colours would be needed

@@ -141,6 +141,16 @@ def check_plan_properties(m, ctx, nodes, edges, mp):
             es, hs = ce[co[c]:co[c + 1]], ch[co[c]:co[c + 1]]
             assert np.all(e2n[es, hs] // K == c)
             np.add.at(cover, (es, hs), 1)
+            # the second order: the same (edge, end) pairs, sorted by foreign
+            # node inside each run of one other cluster
+            fs = v["cluster_cutf_edges"][co[c]:co[c + 1]].astype(np.int64)
+            fh = v["cluster_cutf_ends"][co[c]:co[c + 1]].astype(np.int64)
+            assert sorted(zip(es.tolist(), hs.tolist())) == sorted(zip(fs.tolist(), fh.tolist()))
+            foreign = e2n[fs, 1 - fh]
+            run = foreign // K
+            starts = np.flatnonzero(np.r_[True, run[1:] != run[:-1]])
+            for a, b in zip(starts, np.r_[starts[1:], len(run)]):
+                assert np.all(np.diff(foreign[a:b]) >= 0)
         assert np.all(cover == 1)
         return contiguous / v["nclusters"]
 
