@@ -117,26 +117,36 @@ def host_cpu():
     return model, os.cpu_count()
 
 
-def cpu_baseline(mesh, q, seconds=12.0):
+def cpu_baseline(mesh, q, gpu_res=None, seconds=12.0):
     """The oracle (single thread) on a bounded sample of the same workload:
     repeated FP64 residual passes over the full mesh until ~`seconds` elapse,
     in the input's own (randomly permuted) node numbering, which is what the
-    oracle is given; it does not renumber."""
+    oracle is given; it does not renumber.  gpu_res: {form: residual of the
+    same state from the GPU, user numbering}; each is reported with its error
+    against the oracle's residual (largest over the six variables of
+    max |r - r*| / max |r*|)."""
     import oracle
     passes, t0 = 0, time.perf_counter()
     res = np.zeros_like(q)
     while True:
+        res[:] = 0.0
         oracle.residual(mesh.e2n, q, mesh.w, res=res)
         passes += 1
         el = time.perf_counter() - t0
         if el >= seconds:
             break
     model, nproc = host_cpu()
-    return {"value": passes * mesh.E / el, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "host_cpu": model, "host_nproc": nproc,
-            "sample": f"{passes} sequential FP64 residual passes over all {mesh.E} edges "
-                      f"of the same mesh in its input (randomly permuted) numbering "
-                      f"({el:.1f} s, one thread of {nproc})"}
+    out = {"value": passes * mesh.E / el, "unit": "edges/s", "cores": 1, "kind": "oracle",
+           "host_cpu": model, "host_nproc": nproc,
+           "sample": f"{passes} sequential FP64 residual passes over all {mesh.E} edges "
+                     f"of the same mesh in its input (randomly permuted) numbering "
+                     f"({el:.1f} s, one thread of {nproc})"}
+    if gpu_res:
+        scale = np.abs(res).max(axis=1)
+        out["gpu_residual_error_vs_oracle"] = {
+            k: float(f"{float((np.abs(v - res).max(axis=1) / scale).max()):.3e}")
+            for k, v in gpu_res.items()}
+    return out
 
 
 def cpu_baseline_sweep():
@@ -502,7 +512,17 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
-        out["cpu_baseline"] = cpu_baseline(mesh, q)
+        # the residual of the initial state from both forms (the FP32-storage
+        # form from the state rounded to FP32, as it stores it), for the
+        # oracle leg to compare with its own
+        gpu_res = {}
+        for tag, p, q0 in (("fp64", p64, q0_init64), ("fp32", p32, q0_init32)):
+            r = torch.zeros((6, N), dtype=torch.float64, device=dev)
+            own = bool(p.info["owner_ok"])
+            p.residual(q0, r, pk.OWNER if own else pk.ATOMIC, pk.WRITE if own else pk.INC)
+            torch.cuda.synchronize()
+            gpu_res[tag] = p.nodes_out(r)
+        out["cpu_baseline"] = cpu_baseline(mesh, q, gpu_res)
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -5,6 +5,8 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+
 import bench
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -48,3 +50,20 @@ def test_algorithmic_bytes():
     assert bench.BYTES["rk64"] == (0, 152) and bench.BYTES["rk32"] == (0, 104)
     # the FP32-storage loop moves 1/1.505 of the FP64 loop's bytes
     assert abs(per("fp64") / per("fp32") - 1.505) < 1e-3
+
+
+def test_cpu_baseline_reports_gpu_errors_against_the_oracle():
+    # the oracle leg compares residuals handed to it with its own: an exact copy
+    # scores 0, a copy with one value off by 1e-6 of its variable's largest
+    # magnitude scores 1e-6
+    import meshgen
+    import oracle
+    m = meshgen.build_mesh(4, 0, 0.1)
+    q = meshgen.state(m.N, m.perm)
+    ref = oracle.residual(m.e2n, q, m.w)
+    off = ref.copy()
+    off[2, 5] += 1e-6 * np.abs(ref[2]).max()
+    cb = bench.cpu_baseline(m, q, {"same": ref, "off": off}, seconds=0.01)
+    assert cb["kind"] == "oracle" and cb["value"] > 0
+    assert cb["gpu_residual_error_vs_oracle"]["same"] == 0.0
+    assert abs(cb["gpu_residual_error_vs_oracle"]["off"] - 1e-6) < 1e-9
