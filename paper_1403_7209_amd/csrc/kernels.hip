@@ -74,14 +74,15 @@ static __device__ __align__(256) double scratch[opf::gpu::kSumTail + 6 * opf::gp
 #ifndef OPF_FLUX2_CUT_BATCH
 #define OPF_FLUX2_CUT_BATCH 1
 #endif
-// The gradient and second-order loops hold 24 or more values per node in LDS:
-// one workgroup per CU, so their workgroups take more threads (NT) instead
-// (1024 and 768: the second-order loop spills registers at 1024).
+// The second-order loop holds 30 values per node in LDS: one workgroup per CU,
+// so its workgroups take more threads (768: it spills registers at 1024).  The
+// gradient runs in halves of 12 values per node, three 512-thread workgroups
+// per CU.
 #ifndef OPF_GRAD_BATCH
 #define OPF_GRAD_BATCH 2
 #endif
 #ifndef OPF_GRAD_THREADS
-#define OPF_GRAD_THREADS 1024
+#define OPF_GRAD_THREADS 512
 #endif
 #ifndef OPF_FLUX2_BATCH
 #define OPF_FLUX2_BATCH 2
@@ -329,6 +330,31 @@ struct OpGrad {
     }
 };
 
+// The owner variant runs the Green-Gauss sums in two halves: three variables
+// (9 sums) per workgroup, two workgroups per cluster, so that the 9 LDS sums
+// per node leave room for three workgroups per CU where the 18 left room for
+// one.  The kernel shifts the node inputs and outputs by the half it takes.
+struct OpGradH {
+    static constexpr int NIN = 3, NS = 3, NOUT = 9, NW = 3, NWOUT = 0, MODE = ANTI;
+    template <typename T>
+    __device__ static __forceinline__ void stage(const T *x, T *s, T)
+    {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) s[v] = x[v];
+    }
+    template <typename T>
+    __device__ static __forceinline__ void edge(const T *a, const T *b, const T *n, T,
+                                                double *yi, double *, double *)
+    {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const T f = T(0.5) * (a[v] + b[v]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) yi[3 * v + d] = (double)(f * n[d]);
+        }
+    }
+};
+
 // Second-order flux: the OpFlux flux of the states reconstructed linearly to
 // the edge midpoint.  Node inputs: q (6), Green-Gauss sums G (18), vol (1);
 // staged record: q and the gradient G / vol.  Edge inputs: n, then dx = x_j - x_i.
@@ -391,9 +417,21 @@ struct OwnerTune<double, OpAdjoint> {
     static constexpr bool FOREIGN = true;
 };
 template <>
-struct OwnerTune<double, OpGrad> {
+struct OwnerTune<double, OpGradH> {
     static constexpr int B = OPF_GRAD_BATCH, BC = OPF_GRAD_BATCH, WAVES = 0, NT = OPF_GRAD_THREADS;
     static constexpr bool FOREIGN = false;
+};
+
+// The op the owner variant runs for Op, and whether in two halves per cluster.
+template <class Op>
+struct OwnerOp {
+    using type = Op;
+    static constexpr bool HALVES = false;
+};
+template <>
+struct OwnerOp<OpGrad> {
+    using type = OpGradH;
+    static constexpr bool HALVES = true;
 };
 template <>
 struct OwnerTune<double, OpFlux2> {
@@ -811,9 +849,13 @@ struct StagePtrs {
     double *partial;   // [ncl][6]
 };
 
-template <typename T, class Op, int NT, int KC, bool STAGE = false>
+// HALVES: two workgroups per cluster, b and b + 8 of each 16 (dispatched to the
+// same XCD, so that the second reads the cluster's edges from L2), each
+// running Op on its half of the node inputs and outputs (grid: 16 per 8
+// clusters, rounded up; the surplus exits).
+template <typename T, class Op, int NT, int KC, bool STAGE = false, bool HALVES = false>
 __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>::WAVES : 1)) void k_edge_owner(
-    OwnerPtrs p, Arrays<T> a, T gamma, int N, int Kr, int ncl, int remap, int overwrite,
+    OwnerPtrs p, Arrays<T> a0, T gamma, int N, int Kr, int ncl, int remap, int overwrite,
     StagePtrs<T> sp = {})
 {
     constexpr int B = OwnerTune<T, Op>::B;
@@ -822,7 +864,21 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
     T *ss = reinterpret_cast<T *>(smem);
     double *sy = reinterpret_cast<double *>(smem + stage_bytes<T, Op>(K));
 
-    const int c = remap ? xcd_map((int)blockIdx.x, ncl) : (int)blockIdx.x;
+    int c;
+    Arrays<T> a = a0;
+    if constexpr (HALVES) {
+        const int b = (int)blockIdx.x, k = (b & 7) + 8 * (b >> 4), h = (b >> 3) & 1;
+        if (k >= ncl) return;
+        c = remap ? xcd_map(k, ncl) : k;
+        if (h) {
+#pragma unroll
+            for (int v = 0; v < Op::NIN; ++v) a.x[v] = a0.x[Op::NIN + v];
+#pragma unroll
+            for (int v = 0; v < Op::NOUT; ++v) a.y[v] = a0.y[Op::NOUT + v];
+        }
+    } else {
+        c = remap ? xcd_map((int)blockIdx.x, ncl) : (int)blockIdx.x;
+    }
     const int v0 = c * K, nown = min(K, N - v0);
     // stage the owned nodes (contiguous ids: coalesced), clear the accumulator
     for (int v = threadIdx.x; v < nown; v += NT) {
@@ -1220,14 +1276,17 @@ int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t s
               const LaunchOpts &lo)
 {
     if (!P.owner_ok || P.ncl <= 0) return (int)hipErrorInvalidValue;
-    const size_t lds = owner_dyn_lds<T, Op>(P.K);
-    const OwnerPtrs op = owner_ptrs(P, OwnerTune<T, Op>::FOREIGN);
-    constexpr int NT = OwnerTune<T, Op>::NT;
+    using O = typename OwnerOp<Op>::type;
+    constexpr bool H = OwnerOp<Op>::HALVES;
+    const size_t lds = owner_dyn_lds<T, O>(P.K);
+    const OwnerPtrs op = owner_ptrs(P, OwnerTune<T, O>::FOREIGN);
+    constexpr int NT = OwnerTune<T, O>::NT;
+    const int grid = H ? 16 * ((P.ncl + 7) / 8) : P.ncl;
     if (P.K == kOwnerKC)
-        hipLaunchKernelGGL((k_edge_owner<T, Op, NT, kOwnerKC>), dim3(P.ncl), dim3(NT), lds, st, op,
-                           typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
+        hipLaunchKernelGGL((k_edge_owner<T, O, NT, kOwnerKC, false, H>), dim3(grid), dim3(NT), lds, st,
+                           op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
     else
-        hipLaunchKernelGGL((k_edge_owner<T, Op, NT, 0>), dim3(P.ncl), dim3(NT), lds, st, op,
+        hipLaunchKernelGGL((k_edge_owner<T, O, NT, 0, false, H>), dim3(grid), dim3(NT), lds, st, op,
                            typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
     return (int)hipGetLastError();
 }
@@ -1309,9 +1368,12 @@ int raise_all(size_t bytes)
 {
     int rc = raise_coloured<T, Op, false>(bytes);
     if (!rc) rc = raise_coloured<T, Op, true>(bytes);
-    constexpr int NT = OwnerTune<T, Op>::NT;
-    if (!rc) rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, NT, 0>), bytes);
-    if (!rc) rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, Op, NT, kOwnerKC>), bytes);
+    using O = typename OwnerOp<Op>::type;
+    constexpr bool H = OwnerOp<Op>::HALVES;
+    constexpr int NT = OwnerTune<T, O>::NT;
+    if (!rc) rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, O, NT, 0, false, H>), bytes);
+    if (!rc)
+        rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, O, NT, kOwnerKC, false, H>), bytes);
     if constexpr (std::is_same<Op, OpFlux>::value) {
         if (!rc)
             rc = raise_one(
@@ -1327,7 +1389,7 @@ int raise_all(size_t bytes)
 size_t owner_dyn_lds_bytes(int op, bool fp32, int K)
 {
     if (op == OP_ADJOINT) return owner_dyn_lds<double, OpAdjoint>(K);
-    if (op == OP_GRAD) return owner_dyn_lds<double, OpGrad>(K);
+    if (op == OP_GRAD) return owner_dyn_lds<double, OpGradH>(K);
     if (op == OP_FLUX2) return owner_dyn_lds<double, OpFlux2>(K);
     if (op == OP_SPECRAD) return fp32 ? owner_dyn_lds<float, OpSpecrad>(K) : owner_dyn_lds<double, OpSpecrad>(K);
     return fp32 ? owner_dyn_lds<float, OpFlux>(K) : owner_dyn_lds<double, OpFlux>(K);

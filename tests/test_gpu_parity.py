@@ -227,6 +227,16 @@ def test_gradient_and_second_order_flux(small):
         p.ctx.sync()
         assert report("G owner WRITE", normwise(p.nodes_out(G), G_ref), TOL64)
         assert report("res2 owner WRITE", normwise(p.nodes_out(res), r2_ref), TOL64)
+    # the owner gradient runs two workgroups per cluster (a half of the sums
+    # each) over a grid rounded up to 8 clusters: cluster counts that are not a
+    # multiple of 8, and run-time cluster sizes
+    for K in (96, 200):
+        pk_ = problem(m, q, cluster_size=K)
+        G = torch.full((18, pk_.N), 3e30, dtype=torch.float64, device=DEV)
+        pk_.gradient(pk_.qa, G, pk.OWNER, pk.WRITE)
+        pk_.ctx.sync()
+        assert report(f"G owner K={K} ({pk_.info['nclusters']} clusters)",
+                      normwise(pk_.nodes_out(G), G_ref), TOL64)
 
 
 def test_geometry_and_shape_gradient(small):
