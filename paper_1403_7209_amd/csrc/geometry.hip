@@ -258,17 +258,6 @@ __global__ __launch_bounds__(256) void k_node_sum_vol(int T, TetArrays a)
     a.vol[i] = (a.write_vol ? 0.0 : a.vol[i]) + acc;
 }
 
-// the share of x-bar of tet t at its local vertex v: 3 doubles at the
-// (tet, vertex) pair's slot in the node-major list n2t
-// LDS rows: plane of (x, y) pairs, then plane of z (L rows each).
-__device__ __forceinline__ void geo_get(const double *X, int L, uint32_t l, double *x)
-{
-    const double2 xy = reinterpret_cast<const double2 *>(X)[l];
-    x[0] = xy.x;
-    x[1] = xy.y;
-    x[2] = X[2 * L + l];
-}
-
 // The reverse of one tet at coordinates x (unwrapped): its x-bar shares xb
 // from the signed weight adjoints cb[k] = +-wbar / 24 of its six local edges
 // and the sum vbs of its vertices' volume adjoints (a quarter of the volume
@@ -341,6 +330,8 @@ __global__ __launch_bounds__(256) void k_interleave_w(TetArrays a)
     for (int d = 0; d < 3; ++d) a.wT[3 * (size_t)e + d] = a.w[d][e];
 }
 
+// the share of x-bar of tet t at its local vertex v: 3 doubles at the
+// (tet, vertex) pair's slot in the node-major list n2t
 __device__ __forceinline__ void put_shares(const TetArrays &a, int t, const double (&xb)[4][3])
 {
 #pragma unroll
@@ -415,6 +406,15 @@ __device__ __forceinline__ void geo_diff(const double *x, const double *a, bool 
         d[k] = x[k] - a[k];
         if (wrap) d[k] -= period * rint(d[k] * ip);
     }
+}
+
+// LDS rows: plane of (x, y) pairs, then plane of z (L rows each).
+__device__ __forceinline__ void geo_get(const double *X, int L, uint32_t l, double *x)
+{
+    const double2 xy = reinterpret_cast<const double2 *>(X)[l];
+    x[0] = xy.x;
+    x[1] = xy.y;
+    x[2] = X[2 * L + l];
 }
 
 // The edges of a chunk go in batches of kGeoThreads, one per thread; each
