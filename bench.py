@@ -219,8 +219,9 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (it would "
+              "shard by owned node partitions, each GPU importing its halo's state once per "
+              "stage)", file=sys.stderr)
         sys.exit(2)
 
     import torch
