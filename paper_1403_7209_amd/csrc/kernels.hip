@@ -393,33 +393,37 @@ struct OpFlux2 {
 // wavefront share foreign records: pays where those records are wide and
 // bandwidth binds) rather than the bank-spread order (pays where the LDS
 // updates bind).
+// STREAM: non-temporal hints on the loop's once-touched data (ld1/st1).  They
+// pay in the flux loops (3-5 %) and cost in the adjoint, gradient and
+// second-order loops (4-17 %), whose wider records or scattered edge writes
+// do better through the normal cache policy.
 template <typename T, class Op>
 struct OwnerTune {
     static constexpr int B = 2, BC = 2, WAVES = 0, NT = kOwnerThreads;
-    static constexpr bool FOREIGN = false;
+    static constexpr bool FOREIGN = false, STREAM = false;
 };
 template <>
 struct OwnerTune<float, OpFlux> {
     static constexpr int B = OPF_FLUX32_BATCH, BC = OPF_FLUX32_CUT_BATCH, WAVES = OPF_FLUX32_WAVES,
                          NT = kOwnerThreads;
-    static constexpr bool FOREIGN = false;
+    static constexpr bool FOREIGN = false, STREAM = true;
 };
 template <>
 struct OwnerTune<double, OpFlux> {
     static constexpr int B = OPF_FLUX64_BATCH, BC = OPF_FLUX64_CUT_BATCH, WAVES = OPF_FLUX64_WAVES,
                          NT = kOwnerThreads;
-    static constexpr bool FOREIGN = true;
+    static constexpr bool FOREIGN = true, STREAM = true;
 };
 template <>
 struct OwnerTune<double, OpAdjoint> {
     static constexpr int B = OPF_ADJ_BATCH, BC = OPF_ADJ_CUT_BATCH, WAVES = OPF_ADJ_WAVES,
                          NT = kOwnerThreads;
-    static constexpr bool FOREIGN = true;
+    static constexpr bool FOREIGN = true, STREAM = false;
 };
 template <>
 struct OwnerTune<double, OpGradH> {
     static constexpr int B = OPF_GRAD_BATCH, BC = OPF_GRAD_BATCH, WAVES = 0, NT = OPF_GRAD_THREADS;
-    static constexpr bool FOREIGN = false;
+    static constexpr bool FOREIGN = false, STREAM = false;
 };
 
 // The op the owner variant runs for Op, and whether in two halves per cluster.
@@ -437,7 +441,7 @@ template <>
 struct OwnerTune<double, OpFlux2> {
     static constexpr int B = OPF_FLUX2_BATCH, BC = OPF_FLUX2_CUT_BATCH, WAVES = 0,
                          NT = OPF_FLUX2_THREADS;
-    static constexpr bool FOREIGN = true;
+    static constexpr bool FOREIGN = true, STREAM = false;
 };
 
 // ----------------------------------------------------------- plumbing -- */
@@ -509,6 +513,33 @@ __device__ __forceinline__ void st(T *base, int idx, T v)
 {
     const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(T);
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
+}
+
+// Accesses to data a loop touches once (its edge words and weights, the
+// stage's base state and output, a written residual).  With S set they carry
+// the non-temporal hint, which keeps them from displacing, in L2, the node
+// records that neighbouring workgroups gather.
+template <bool S, typename T>
+__device__ __forceinline__ T ld1(const T *base, int idx)
+{
+    if constexpr (S) {
+        const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(T);
+        return __builtin_nontemporal_load(
+            reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off));
+    } else {
+        return ld(base, idx);
+    }
+}
+
+template <bool S, typename T>
+__device__ __forceinline__ void st1(T *base, int idx, T v)
+{
+    if constexpr (S) {
+        const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(T);
+        __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off));
+    } else {
+        st(base, idx, v);
+    }
 }
 
 template <class Op, typename T>
@@ -859,6 +890,7 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
     StagePtrs<T> sp = {})
 {
     constexpr int B = OwnerTune<T, Op>::B;
+    constexpr bool S = OwnerTune<T, Op>::STREAM;
     const int K = KC > 0 ? KC : Kr;
     extern __shared__ __align__(16) unsigned char smem[];
     T *ss = reinterpret_cast<T *>(smem);
@@ -899,9 +931,9 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
         for (int b = 0; b < B; ++b) {
             const int k = k0 + b * NT;
             if (k < ib.y) {
-                wd[b] = ld(p.iw, ib.x + k);
+                wd[b] = ld1<S>(p.iw, ib.x + k);
 #pragma unroll
-                for (int d = 0; d < Op::NW; ++d) w[b][d] = ld(a.w[d], ib.x + k);
+                for (int d = 0; d < Op::NW; ++d) w[b][d] = ld1<S>(a.w[d], ib.x + k);
             }
         }
 #pragma unroll
@@ -933,7 +965,7 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
             }
             if constexpr (Op::NWOUT > 0) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) st(a.wo[d], ib.x + k, wo[d]);
+                for (int d = 0; d < 3; ++d) st1<S>(a.wo[d], ib.x + k, wo[d]);
             }
         }
     }
@@ -948,9 +980,9 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
             const int k = k0 + b * NT;
             eid[b] = -1;
             if (k < ns) {
-                eid[b] = ld(p.cv_eid, s0 + k);
-                oth[b] = ld(p.cv_oth, s0 + k);
-                own[b] = (int)ld(p.cv_own, s0 + k);
+                eid[b] = ld1<S>(p.cv_eid, s0 + k);
+                oth[b] = ld1<S>(p.cv_oth, s0 + k);
+                own[b] = (int)ld1<S>(p.cv_own, s0 + k);
             }
         }
         T w[BC][Op::NW], xf[BC][Op::NIN];
@@ -981,7 +1013,7 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
             if constexpr (Op::NWOUT > 0) {
                 if (v0 + own[b] < (oth[b] & 0x7fffffff)) {
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) st(a.wo[d], eid[b], flip(wo[d], second));
+                    for (int d = 0; d < 3; ++d) st1<S>(a.wo[d], eid[b], flip(wo[d], second));
                 }
             }
         }
@@ -993,8 +1025,8 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
     if constexpr (STAGE) {
         if (K <= NT && (int)threadIdx.x < nown) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) pq0[k] = (double)ld(sp.q0[k], v0 + (int)threadIdx.x);
-            pvol = ld(sp.vol, v0 + (int)threadIdx.x);
+            for (int k = 0; k < 6; ++k) pq0[k] = (double)ld1<S>(sp.q0[k], v0 + (int)threadIdx.x);
+            pvol = ld1<S>(sp.vol, v0 + (int)threadIdx.x);
         }
     }
     __syncthreads();
@@ -1003,15 +1035,15 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
         for (int v = threadIdx.x; v < nown; v += NT) {
             const int g = v0 + v;
             const bool pre = K <= NT;
-            const double vi = pre ? pvol : ld(sp.vol, g);
+            const double vi = pre ? pvol : ld1<S>(sp.vol, g);
             const double adt = sp.dt ? sp.adt * ld(sp.dt, g) : sp.adt;
             const double step = adt / vi;  // one division per node
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
                 const double r = sy[k * K + v];
                 acc[k] += r * r;
-                const double base = pre ? pq0[k] : (double)ld(sp.q0[k], g);
-                st(sp.q[k], g, (T)(base - step * r));
+                const double base = pre ? pq0[k] : (double)ld1<S>(sp.q0[k], g);
+                st1<S>(sp.q[k], g, (T)(base - step * r));
             }
         }
         bool done = false;
@@ -1027,7 +1059,7 @@ __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>
 #pragma unroll
             for (int k = 0; k < Op::NOUT; ++k) {
                 const double acc = sy[k * K + v];
-                st(a.y[k], v0 + v, overwrite ? acc : ld(a.y[k], v0 + v) + acc);
+                st1<S>(a.y[k], v0 + v, overwrite ? acc : ld(a.y[k], v0 + v) + acc);
             }
         }
     }
