@@ -393,10 +393,11 @@ struct OpFlux2 {
 // wavefront share foreign records: pays where those records are wide and
 // bandwidth binds) rather than the bank-spread order (pays where the LDS
 // updates bind).
-// STREAM: non-temporal hints on the loop's once-touched data (ld1/st1).  They
-// pay in the flux loops (3-5 %) and cost in the adjoint, gradient and
-// second-order loops (4-17 %), whose wider records or scattered edge writes
-// do better through the normal cache policy.
+// STREAM: non-temporal hints on the loop's once-touched data (ld1/st1) when
+// its arrays exceed the last-level cache (owner_streams).  They pay in the
+// flux loops (3-5 %) and cost in the adjoint, gradient and second-order loops
+// (4-17 %), whose wider records or scattered edge writes do better through
+// the normal cache policy.
 template <typename T, class Op>
 struct OwnerTune {
     static constexpr int B = 2, BC = 2, WAVES = 0, NT = kOwnerThreads;
@@ -883,14 +884,16 @@ struct StagePtrs {
 // HALVES: two workgroups per cluster, b and b + 8 of each 16 (dispatched to the
 // same XCD, so that the second reads the cluster's edges from L2), each
 // running Op on its half of the node inputs and outputs (grid: 16 per 8
-// clusters, rounded up; the surplus exits).
-template <typename T, class Op, int NT, int KC, bool STAGE = false, bool HALVES = false>
+// clusters, rounded up; the surplus exits).  HINT: the non-temporal hints
+// (where the op takes them).
+template <typename T, class Op, int NT, int KC, bool STAGE = false, bool HALVES = false,
+          bool HINT = false>
 __global__ __launch_bounds__(NT, (OwnerTune<T, Op>::WAVES > 0 ? OwnerTune<T, Op>::WAVES : 1)) void k_edge_owner(
     OwnerPtrs p, Arrays<T> a0, T gamma, int N, int Kr, int ncl, int remap, int overwrite,
     StagePtrs<T> sp = {})
 {
     constexpr int B = OwnerTune<T, Op>::B;
-    constexpr bool S = OwnerTune<T, Op>::STREAM;
+    constexpr bool S = HINT && OwnerTune<T, Op>::STREAM;
     const int K = KC > 0 ? KC : Kr;
     extern __shared__ __align__(16) unsigned char smem[];
     T *ss = reinterpret_cast<T *>(smem);
@@ -1303,6 +1306,56 @@ OwnerPtrs owner_ptrs(const DevPlan &P, bool foreign)
 // Cluster size fixed at compile time for the default plan.
 constexpr int kOwnerKC = 512;
 
+// The device's last-level cache (MALL, 256 MB).  A loop whose arrays fit in
+// it finds them there again at its next launch, which the non-temporal hints
+// would spoil (the FP32 flux loops of a 1M-node mesh: 12-20 % slower with
+// them); a larger loop streams through it, and the hints keep its L2 for the
+// halo records.
+constexpr double kMallBytes = 256.0 * 1024 * 1024;
+
+// Whether the owner loop of Op over plan P takes the non-temporal hints: its
+// bytes per launch (edge map and inputs; node inputs and outputs, or for the
+// fused stage q, q0, the new state and vol) exceed the last-level cache.
+template <typename T, class Op>
+bool owner_streams(const DevPlan &P, bool stage)
+{
+    if (!OwnerTune<T, Op>::STREAM) return false;
+    const double per_node = stage ? 3.0 * 6 * sizeof(T) + sizeof(double)
+                                  : (double)Op::NIN * sizeof(T) + Op::NOUT * sizeof(double);
+    const double bytes = (double)P.E * (8.0 + Op::NW * sizeof(T)) + (double)P.N * per_node;
+    return bytes > kMallBytes;
+}
+
+// Launches the owner kernel of op O (KC: compile-time cluster size or 0).
+template <typename T, class O, int NT, int KC, bool STAGE, bool H>
+void launch_owner_kc(bool hint, int grid, size_t lds, hipStream_t st, const OwnerPtrs &op,
+                     const Arrays<T> &a, T gamma, const DevPlan &P, const LaunchOpts &lo,
+                     int overwrite, const StagePtrs<T> &sp)
+{
+    if constexpr (OwnerTune<T, O>::STREAM) {
+        if (hint) {
+            hipLaunchKernelGGL((k_edge_owner<T, O, NT, KC, STAGE, H, true>), dim3(grid), dim3(NT),
+                               lds, st, op, a, gamma, P.N, P.K, P.ncl, lo.xcd_remap, overwrite, sp);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_edge_owner<T, O, NT, KC, STAGE, H, false>), dim3(grid), dim3(NT), lds,
+                       st, op, a, gamma, P.N, P.K, P.ncl, lo.xcd_remap, overwrite, sp);
+}
+
+template <typename T, class O, int NT, bool STAGE, bool H>
+void launch_owner(bool hint, int grid, size_t lds, hipStream_t st, const OwnerPtrs &op,
+                  const Arrays<T> &a, T gamma, const DevPlan &P, const LaunchOpts &lo,
+                  int overwrite, const StagePtrs<T> &sp)
+{
+    if (P.K == kOwnerKC)
+        launch_owner_kc<T, O, NT, kOwnerKC, STAGE, H>(hint, grid, lds, st, op, a, gamma, P, lo,
+                                                      overwrite, sp);
+    else
+        launch_owner_kc<T, O, NT, 0, STAGE, H>(hint, grid, lds, st, op, a, gamma, P, lo, overwrite,
+                                               sp);
+}
+
 template <typename T, class Op>
 int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t st,
               const LaunchOpts &lo)
@@ -1314,12 +1367,8 @@ int run_owner(const DevPlan &P, const EdgeArrays &a, double gamma, hipStream_t s
     const OwnerPtrs op = owner_ptrs(P, OwnerTune<T, O>::FOREIGN);
     constexpr int NT = OwnerTune<T, O>::NT;
     const int grid = H ? 16 * ((P.ncl + 7) / 8) : P.ncl;
-    if (P.K == kOwnerKC)
-        hipLaunchKernelGGL((k_edge_owner<T, O, NT, kOwnerKC, false, H>), dim3(grid), dim3(NT), lds, st,
-                           op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
-    else
-        hipLaunchKernelGGL((k_edge_owner<T, O, NT, 0, false, H>), dim3(grid), dim3(NT), lds, st, op,
-                           typed<T>(a), (T)gamma, P.N, P.K, P.ncl, lo.xcd_remap, lo.overwrite);
+    launch_owner<T, O, NT, false, H>(owner_streams<T, O>(P, false), grid, lds, st, op, typed<T>(a),
+                                     (T)gamma, P, lo, lo.overwrite, StagePtrs<T>{});
     return (int)hipGetLastError();
 }
 
@@ -1339,14 +1388,9 @@ int run_owner_stage(const DevPlan &P, const EdgeArrays &a, const NodeArrays &na,
     sp.dt = na.dt;
     sp.adt = adt;
     sp.partial = partial + kSumTail;
-    if (P.K == kOwnerKC)
-        hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, kOwnerKC, true>), dim3(P.ncl),
-                           dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
-                           lo.xcd_remap, 0, sp);
-    else
-        hipLaunchKernelGGL((k_edge_owner<T, OpFlux, kOwnerThreads, 0, true>), dim3(P.ncl),
-                           dim3(kOwnerThreads), lds, st, op, typed<T>(a), (T)gamma, P.N, P.K, P.ncl,
-                           lo.xcd_remap, 0, sp);
+    launch_owner<T, OpFlux, kOwnerThreads, true, false>(owner_streams<T, OpFlux>(P, true), P.ncl,
+                                                        lds, st, op, typed<T>(a), (T)gamma, P, lo,
+                                                        0, sp);
     hipLaunchKernelGGL(k_sum_partials, dim3(kSumGroups), dim3(kSumThreads), 0, st, P.ncl, partial,
                        ss);
     return (int)hipGetLastError();
@@ -1395,6 +1439,24 @@ int raise_coloured(size_t bytes)
     return 0;
 }
 
+template <typename T, class O, int NT, bool STAGE, bool H>
+int raise_owner(size_t bytes)
+{
+    int rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, O, NT, 0, STAGE, H, false>), bytes);
+    if (!rc)
+        rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, O, NT, kOwnerKC, STAGE, H, false>),
+                       bytes);
+    if constexpr (OwnerTune<T, O>::STREAM) {
+        if (!rc)
+            rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, O, NT, 0, STAGE, H, true>),
+                           bytes);
+        if (!rc)
+            rc = raise_one(
+                reinterpret_cast<const void *>(&k_edge_owner<T, O, NT, kOwnerKC, STAGE, H, true>), bytes);
+    }
+    return rc;
+}
+
 template <typename T, class Op>
 int raise_all(size_t bytes)
 {
@@ -1403,17 +1465,9 @@ int raise_all(size_t bytes)
     using O = typename OwnerOp<Op>::type;
     constexpr bool H = OwnerOp<Op>::HALVES;
     constexpr int NT = OwnerTune<T, O>::NT;
-    if (!rc) rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, O, NT, 0, false, H>), bytes);
-    if (!rc)
-        rc = raise_one(reinterpret_cast<const void *>(&k_edge_owner<T, O, NT, kOwnerKC, false, H>), bytes);
+    if (!rc) rc = raise_owner<T, O, NT, false, H>(bytes);
     if constexpr (std::is_same<Op, OpFlux>::value) {
-        if (!rc)
-            rc = raise_one(
-                reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, 0, true>), bytes);
-        if (!rc)
-            rc = raise_one(
-                reinterpret_cast<const void *>(&k_edge_owner<T, Op, kOwnerThreads, kOwnerKC, true>),
-                bytes);
+        if (!rc) rc = raise_owner<T, Op, kOwnerThreads, true, false>(bytes);
     }
     return rc;
 }
