@@ -191,6 +191,75 @@ def cpu_baseline_sweep():
     return out
 
 
+def shard_share(pk, ctx, mesh, q, n, dt, rbar_user, res_user, ev, reps=3):
+    """One GPU's share of the mesh split into 2x2x2 blocks: the central block's
+    owned nodes, their halo and every edge with an owned end (owner-compute),
+    planned as a mesh of its own.  Times its fused FP64 and FP32 iterations and
+    its adjoint, and checks its owned residuals against the whole mesh's."""
+    import torch
+
+    from paper_1403_7209_amd.shard import lattice_block, owner_shard
+    sh = owner_shard(mesh.e2n, lattice_block(mesh.xyz, n, n // 4, n // 2))
+    w_s = np.ascontiguousarray(mesh.w[:, sh.edges])
+    q_s = np.ascontiguousarray(q[:, sh.nodes])
+    ps = pk.FluxProblem(ctx, sh.e2n, w_s, mesh.vol[sh.nodes], q_s, renumber="morton",
+                        coords=np.ascontiguousarray(mesh.xyz[:, sh.nodes]))
+    ps32 = pk.FluxProblem(ctx, sh.e2n, w_s, mesh.vol[sh.nodes], q_s, fp32=True, like=ps)
+    Ns, Es = len(sh.nodes), len(sh.edges)
+    dev = ps.qa.device
+    rb = ps.nodes_in(np.ascontiguousarray(rbar_user[:, sh.nodes]))
+    qbar = torch.zeros((6, Ns), dtype=torch.float64, device=dev)
+    nbar = torch.empty((3, Es), dtype=torch.float64, device=dev)
+    rb_d, qbar_d, nbar_d = ps.dat(rb, "rbar"), ps.dat(qbar, "qbar"), ps.dat(nbar, "nbar", edges=True)
+    for p in (ps, ps32):
+        p.qc = torch.empty_like(p.qa)
+    timers = {"fp64_fused": [], "fp32_fused": [], "adjoint": []}
+
+    def iteration(p, key, rec):  # five fused stages from the same starting state
+        qa = p.dat(p.qa, "qa")
+        bufs, src = (p.dat(p.qb, "qb"), p.dat(p.qc, "qc")), qa
+        for k in range(5):
+            a = ev()
+            p.ctx.edge_flux_stage(p.edges, p.e2n, src, p.w, qa, p.vol, bufs[k % 2],
+                                  pk.RK_ALPHA[k] * dt, p.ss[k], p.gamma)
+            b = ev()
+            if rec:
+                timers[key].append((a, b))
+            src = bufs[k % 2]
+
+    for rec in [False] + [True] * reps:
+        iteration(ps, "fp64_fused", rec)
+        iteration(ps32, "fp32_fused", rec)
+        a = ev()
+        ctx.edge_flux_adjoint(ps.edges, ps.e2n, ps.dat(ps.qa, "q"), ps.w, rb_d, qbar_d, nbar_d,
+                              ps.gamma, pk.OWNER, pk.WRITE)
+        b = ev()
+        if rec:
+            timers["adjoint"].append((a, b))
+    res = torch.empty((6, Ns), dtype=torch.float64, device=dev)
+    ps.residual(ps.qa, res, pk.OWNER, pk.WRITE)
+    torch.cuda.synchronize()
+    own = ps.nodes_out(res)[:, :sh.n_owned]
+    ref = res_user[:, sh.nodes[:sh.n_owned]]
+    err = float((np.abs(own - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
+    forms = {}
+    for k, lst in timers.items():
+        ms = float(np.mean([a.elapsed_time(b) for a, b in lst]))
+        be, bn = BYTES[k]
+        gbs = (be * Es + bn * Ns) / (ms * 1e-3) / 1e9
+        forms[k] = {"ms": round(ms, 4), "edges_per_s": round(Es / (ms * 1e-3), 1),
+                    "algorithmic_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"shard {k:10s} {ms * 1e3:8.1f} us  {gbs:8.1f} GB/s algorithmic "
+            f"({100 * gbs / HBM_PEAK_GBS:.1f} % of 8 TB/s)")
+    log(f"shard: {sh.n_owned} owned + {sh.n_halo} halo nodes, {Es} edges; owned residual vs "
+        f"the whole mesh {err:.2e}")
+    out = {"split": "2x2x2 blocks of the box; the central block", "owned_nodes": sh.n_owned,
+           "halo_nodes": sh.n_halo, "edges": Es, "forms": forms,
+           "owned_residual_error_vs_whole_mesh": float(f"{err:.3e}")}
+    del ps, ps32
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -423,6 +492,20 @@ def main():
                     timers.setdefault("geometry_adj" + tag, []).append((b, c))
     torch.cuda.synchronize()
 
+    # one GPU's share of the mesh split over eight (owned block, halo, every edge
+    # with an owned end), against the whole mesh's residual of the same state
+    shard = None
+    if fused and N >= 8 * 512:
+        res_full = torch.empty((6, N), dtype=torch.float64, device=dev)
+        ctx.edge_flux(p64.edges, p64.e2n, p64.dat(q0_init64, "q0"), p64.w,
+                      p64.dat(res_full, "rfull"), p64.gamma, pk.OWNER, pk.WRITE)
+        torch.cuda.synchronize()
+        res_user = p64.nodes_out(res_full)
+        del res_full
+        shard = shard_share(pk, ctx, mesh, q, mn, dt, rbar_user=meshgen.normal(6 * N, purpose=21)
+                            .reshape(6, N), res_user=res_user, ev=ev)
+        del res_user
+
     # a device-to-device copy of 1 GiB for context: what plain streaming reaches here
     src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
@@ -497,6 +580,7 @@ def main():
         "forms": per,
         "fp32_speedup_over_fp64": round(speedup32, 4),
         "fp32_error_vs_fp64": float(f"{err32:.3e}"),
+        "shard_of_8": shard,
         "roofline": {
             "kernel": ("FP64 edge-flux loop with the stage update fused (opf_edge_flux_stage)"
                        if fused else "FP64 edge-flux loop (opf_edge_flux)"),

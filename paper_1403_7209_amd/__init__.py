@@ -200,6 +200,7 @@ class Context:
             raise OpfError(rc, f"opf_init(device={self.device})")
         self._dats = {}
         self._keep = []
+        self._problems = 0  # FluxProblems declared on this context (their map names)
 
     @property
     def torch_device(self):
@@ -507,17 +508,21 @@ class FluxProblem:
         else:
             e2n = np.ascontiguousarray(e2n, dtype=np.int32)
             self.N, self.E = int(np.asarray(vol).shape[0]), int(e2n.shape[0])
-            self.nodes = ctx.decl_set(self.N, "nodes")
-            self.edges = ctx.decl_set(self.E, "edges")
-            self.e2n = ctx.decl_map(self.edges, self.nodes, 2, e2n, index_base, "e2n")
+            # a map declared under a name already taken replaces that map, so
+            # every problem on a context names its maps apart
+            ctx._problems += 1
+            tag = f"/{ctx._problems}"
+            self.nodes = ctx.decl_set(self.N, "nodes" + tag)
+            self.edges = ctx.decl_set(self.E, "edges" + tag)
+            self.e2n = ctx.decl_map(self.edges, self.nodes, 2, e2n, index_base, "e2n" + tag)
             self.tets = self.t2n = self.t2e = None
             if tets is not None:  # tet maps must exist before the plan renumbers the sets
                 tets = np.ascontiguousarray(tets, dtype=np.int32)
-                self.tets = ctx.decl_set(tets.shape[0], "tets")
-                self.t2n = ctx.decl_map(self.tets, self.nodes, 4, tets, index_base, "t2n")
+                self.tets = ctx.decl_set(tets.shape[0], "tets" + tag)
+                self.t2n = ctx.decl_map(self.tets, self.nodes, 4, tets, index_base, "t2n" + tag)
                 self.t2e = ctx.decl_map(self.tets, self.edges, 6,
                                         np.ascontiguousarray(tet_edges, dtype=np.int32),
-                                        index_base, "t2e")
+                                        index_base, "t2e" + tag)
             self.info = ctx.plan(self.e2n, renumber=renumber, block_size=block_size,
                                  colour_sort=colour_sort, coords=coords,
                                  cluster_size=cluster_size, lane_groups=lane_groups,
