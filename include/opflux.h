@@ -159,9 +159,11 @@ int opf_decl_set(opf_ctx *ctx, int64_t size, const char *name, opf_set *out);
  * op_decl_map; argument order from, to, dim).  `idx` is host memory,
  * row-major from.size x dim; it is COPIED and the library owns the copy.
  * index_base is 0 or 1 (the paper's Fortran maps are 1-based).  Declaring a
- * map again under the same name replaces it and makes its plan stale.
- * Errors: OPF_EINVAL (bad handle, dim < 1, index_base), OPF_ERANGE (an entry
- * outside [0, to.size) after subtracting index_base). */
+ * map again under the same name (same sets, same arity) replaces its entries,
+ * keeps its handle and makes its plan stale.
+ * Errors: OPF_EINVAL (bad handle, dim < 1, index_base, a name already taken by
+ * a map between other sets or of another arity), OPF_ERANGE (an entry outside
+ * [0, to.size) after subtracting index_base). */
 int opf_decl_map(opf_ctx *ctx, opf_set from, opf_set to, int dim, const int32_t *idx,
                  int index_base, const char *name, opf_map *out);
 

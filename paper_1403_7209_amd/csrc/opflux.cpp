@@ -1282,6 +1282,13 @@ int opf_decl_map(opf_ctx *ctx, opf_set from, opf_set to, int dim, const int32_t 
     if (!ctx->set_ok(from) || !ctx->set_ok(to)) return ctx->fail(OPF_EINVAL, "invalid set handle");
     if (dim < 1) return ctx->fail(OPF_EINVAL, "map dimension must be >= 1");
     if (index_base != 0 && index_base != 1) return ctx->fail(OPF_EINVAL, "index_base must be 0 or 1");
+    // a map declared again under its name must join the same sets with the
+    // same arity: handles other code holds keep their meaning
+    if (name && *name)
+        for (const MapRec &m : ctx->maps)
+            if (m.name == name && (m.from != from || m.to != to || m.dim != dim))
+                return ctx->fail(OPF_EINVAL, std::string("map '") + name +
+                                                 "' already joins other sets or has another arity");
     if (ctx->sets[from].plan_map >= 0 || ctx->sets[to].plan_map >= 0) {
         // a map declared on renumbered sets would have to be in internal
         // numbering; keep declarations in user numbering only

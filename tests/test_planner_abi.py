@@ -410,6 +410,16 @@ def test_plan_errors_and_stale_plans():
     with pytest.raises(pk.OpfError) as e:
         ctx.decl_map(edges, nodes, 2, np.array([[0, 1], [1, 2]]), 0, "other")
     assert e.value.status == pk.ESTATE
+    # a name already taken by a map between other sets, or of another arity, is
+    # refused: the handle keeps its map
+    cells = ctx.decl_set(2, "cells")
+    with pytest.raises(pk.OpfError) as e:
+        ctx.decl_map(cells, nodes, 2, np.array([[0, 1], [1, 2]]), 0, "loop")
+    assert e.value.status == pk.EINVAL
+    with pytest.raises(pk.OpfError) as e:
+        ctx.decl_map(edges, nodes, 1, np.array([0, 1]), 0, "loop")
+    assert e.value.status == pk.EINVAL
+    assert ctx.decl_map(edges, nodes, 2, np.array([[1, 0], [1, 2]]), 0, "loop") == loop
     # plans are for arity-2 maps (the paper's cell->node example has arity 3)
     c2 = pk.Context(None)
     cells = c2.decl_set(2, "cells")
