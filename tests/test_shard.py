@@ -75,3 +75,22 @@ def test_owner_shard_rejects_bad_input():
         owner_shard(np.zeros((3, 3), np.int32), np.ones(4, bool))
     with pytest.raises(ValueError):
         owner_shard(np.array([[0, 5]], np.int32), np.ones(4, bool))
+
+
+def test_owner_shard_degenerate_splits(mesh):
+    # nothing owned: an empty share; everything owned: the whole mesh, no halo
+    none = owner_shard(mesh.e2n, np.zeros(mesh.N, bool))
+    assert none.n_owned == 0 and none.n_halo == 0 and len(none.edges) == 0
+    assert none.e2n.shape == (0, 2)
+    full = owner_shard(mesh.e2n, np.ones(mesh.N, bool))
+    assert full.n_owned == mesh.N and full.n_halo == 0
+    assert np.array_equal(full.edges, np.arange(mesh.E))
+    assert np.array_equal(full.e2n, mesh.e2n)
+    # one owned node: its star, with its neighbours as the halo
+    one = np.zeros(mesh.N, bool)
+    one[7] = True
+    sh = owner_shard(mesh.e2n, one)
+    e2n = mesh.e2n.astype(np.int64)
+    star = np.flatnonzero((e2n[:, 0] == 7) | (e2n[:, 1] == 7))
+    assert np.array_equal(sh.edges, star)
+    assert sh.n_owned == 1 and sh.n_halo == len(star)
